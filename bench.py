@@ -1,0 +1,175 @@
+"""Throughput of the fused coupled-lattice step on one MI355X.
+
+A step is one time step of all three D2Q9 lattices (phase field, flow,
+enthalpy) over the whole grid; the default workload is the 512x256 sessile
+droplet (R = 80, theta = 90, rho_s/rho_l = 0.9, Ste = 0.1, Bond = 0.1, FP32
+populations).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line with MLUPS, the roofline of the step kernel (HBM
+bound, algorithmic 256 B per node update), the FP64 oracle timed on the host
+cores, and the same step kernel on a 4096x2048 grid whose 2.3 GB working
+set does not fit the 256 MB Infinity Cache.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+BYTES_PER_NODE = 256  # 27 populations + 5 history values, FP32, read and written once
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS (φ+flow+T lattices), % HBM peak; batched sweep droplets/s vs plain"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2403_16122_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs stored
+    under profiles/, valid only for the kernel source they were taken on."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_steps(solver, steps: int, warmup: int):
+    import torch
+
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    stream = solver.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    solver.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def cpu_baseline(params, phi0, T0, budget_s: float):
+    import oracle
+
+    o = oracle.OracleSolver(params, phi0, T0)
+    n = 0
+    t0 = time.perf_counter()
+    chunk = 5
+    while time.perf_counter() - t0 < budget_s:
+        o.step(chunk)
+        n += chunk
+    dt = time.perf_counter() - t0
+    return dict(value=round(params["nx"] * params["ny"] * n / dt / 1e6, 3), unit="MLUPS",
+                cores=oracle.oracle.default_threads(), kind="oracle",
+                sample=f"{n} steps of the same workload from its initial state ({dt:.1f} s, FP64, OpenMP rows)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--workload", default="sessile512")
+    ap.add_argument("--tile", default="64x4")
+    ap.add_argument("--no-xcd", action="store_true")
+    ap.add_argument("--probe-steps", type=int, default=100, help="steps on the 4096x2048 grid (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle timing budget (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the y-slab multi-GPU decomposition is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2403_16122_amd import lbm, workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    params, phi0, T0, meta = W.workload(args.workload, seed=0)
+    N = params["nx"] * params["ny"]
+    solver = lbm.Solver(params, phi0, T0)
+    solver.set_launch(args.tile, not args.no_xcd)
+    torch.cuda.synchronize()
+    secs, wall = time_steps(solver, args.steps, args.warmup)
+    d = solver.diag()
+    if d["rc"] != 0:
+        print(f"bench.py: non-finite state after the timed steps ({d})", file=sys.stderr)
+        sys.exit(3)
+    mlups = N * args.steps / secs / 1e6
+    launch_s = secs / args.steps
+    achieved = BYTES_PER_NODE * N / launch_s / 1e9
+    traffic = measured_traffic(args.workload)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(secs / args.steps * 1e3, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {params['nx']}x{params['ny']} sessile droplet R={meta['R']:g} lu, "
+                        f"theta {meta['theta']:g}, rho_s/rho_l {params['rho_s']:g}, Ste 0.1, Bond 0.1, "
+                        "W=4, M=0.1, rho_l/rho_g=1000, FP32 populations (planar 2-D)",
+            "nx": params["nx"], "ny": params["ny"], "tile": args.tile, "xcd_remap": not args.no_xcd,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_step (fused collide + pull-stream)",
+            "bytes_per_launch": BYTES_PER_NODE * N,
+            "note": "working set fits the 256 MB Infinity Cache at this size; see hbm_probe",
+        },
+        "wall_s": round(wall, 3),
+    }
+    del solver
+    torch.cuda.empty_cache()
+    if args.probe_steps > 0:
+        pp, pphi, pT, _ = W.workload("probe4096", seed=0)
+        Np = pp["nx"] * pp["ny"]
+        ps = lbm.Solver(pp, pphi, pT)
+        ps.set_launch(args.tile, not args.no_xcd)
+        psecs, _ = time_steps(ps, args.probe_steps, 10)
+        pl = psecs / args.probe_steps
+        pach = BYTES_PER_NODE * Np / pl / 1e9
+        out["hbm_probe"] = {
+            "workload": "probe4096: 4096x2048 sessile droplet R=640 (same physics), 2.3 GB working set",
+            "steps": args.probe_steps, "MLUPS": round(Np * args.probe_steps / psecs / 1e6, 1),
+            "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("probe4096"),
+        }
+        del ps
+        torch.cuda.empty_cache()
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(params, phi0, T0, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

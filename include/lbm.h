@@ -1,0 +1,136 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) solver for the phase-field lattice
+ * Boltzmann method for containerless freezing of Huang, Wang, Chai & Shi
+ * (arXiv:2403.16122).
+ *
+ * One time step updates three coupled D2Q9 lattices:
+ *   g  conservative Allen-Cahn phase field with the dilatation term phi div(u)
+ *      (Sec. 3.1, Eq. (21)-(26)),
+ *   f  pressure/velocity flow model with surface tension mu_phi grad(phi),
+ *      body force, the fluid-solid force rho f and the freezing mass source
+ *      (Sec. 3.3, Eq. (30)-(36), mass source Eq. (19)),
+ *   h  total-enthalpy model with the liquid-fraction rule (Sec. 3.2,
+ *      Eq. (27)-(29), enthalpy rule Eq. (9)),
+ * on a rectangular domain that is periodic in x, with walls half a spacing
+ * below row 0 and above row ny-1: half-way bounce-back for g and f,
+ * anti-bounce-back Dirichlet temperature at the bottom, adiabatic top, and
+ * the geometric wetting condition of Eq. (39)-(41) at both walls (Sec. 4.1).
+ * All quantities are in lattice units (dx = dt = 1, cs^2 = 1/3).
+ *
+ * Layout.  Node (x, y) has index k = y*nx + x; host arrays are row-major
+ * with nx*ny doubles.  Device state lives in one caller-provided workspace.
+ *
+ * Errors.  Every call returns LBM_OK (0) or a negative code; no exception
+ * crosses this boundary.  Kernel faults surface at the next call that
+ * synchronises (lbm_fields, lbm_diag, lbm_save, lbm_sync).
+ *
+ * Threading.  A context is bound to one device and one stream; calls on
+ * one context must not overlap.
+ */
+#ifndef LBM_H
+#define LBM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* bad argument: sizes, a relaxation time <= 1/2, angle, workspace */
+  LBM_ENOMEM = -2,     /* library-side allocation failed */
+  LBM_EDEVICE = -3,    /* HIP runtime error; text from lbm_last_error() */
+  LBM_ENONFINITE = -4, /* diagnostics found NaN/Inf in the fields */
+  LBM_ESTATE = -5      /* checkpoint does not match this context */
+};
+
+enum { LBM_STORE_FP32 = 0 };
+
+/* Physical parameters in lattice units.  Mixture properties follow Eq. (1)
+ * with subscripts s (solid), l (liquid), g (gas). */
+typedef struct {
+  int32_t nx, ny;                 /* >= 3 each */
+  double W, M, sigma;             /* interface width, mobility (tau_g = M/cs^2 + 1/2, Sec. 3.1),
+                                     surface tension (beta = 12 sigma/W, kappa = 3 sigma W/2, Eq. (13)) */
+  double rho_l, rho_g, rho_s;     /* densities (> 0); rho_s/rho_l sets the mass source, Eq. (19) */
+  double mu_l, mu_g, mu_s;        /* dynamic viscosities (> 0); tau_f = mu/(rho cs^2) + 1/2 */
+  double cp_l, cp_g, cp_s, cp_ref;/* heat capacities; cp_ref of the enthalpy equilibrium, Eq. (28) */
+  double k_l, k_g, k_s;           /* conductivities (> 0); tau_h = k/(cp_ref cs^2) + 1/2 */
+  double latent, T_melt, T_bottom;/* latent heat (> 0), melting temperature, bottom wall temperature */
+  double theta_bottom_deg, theta_top_deg; /* contact angles in (0, 180), Eq. (39) */
+  double gx, gy;                  /* gravity: body force rho*g */
+  double bq_beta, bq_rho0, bq_Tref; /* optional Boussinesq force -rho0 beta (T - Tref) g (Sec. 4.3) */
+  int32_t st_solid_mask;          /* 0: F_s = mu grad(phi) (Eq. (11)); 1: (1 - f_s) mu grad(phi) */
+  int32_t storage;                /* LBM_STORE_FP32 */
+} lbm_params;
+
+typedef struct {
+  int64_t step;
+  double sum_phi, sum_phic, sum_solid, sum_liquid, sum_H, max_u, h_c;
+  int32_t nonfinite;
+} lbm_diag_t;
+
+/* Field selection bits for lbm_fields / lbm_fields_device. */
+enum {
+  LBM_F_PHI = 1u << 0, LBM_F_T = 1u << 1, LBM_F_UX = 1u << 2, LBM_F_UY = 1u << 3,
+  LBM_F_P = 1u << 4, LBM_F_FS = 1u << 5, LBM_F_FL = 1u << 6, LBM_F_RHO = 1u << 7,
+  LBM_F_H = 1u << 8, LBM_F_MDOT = 1u << 9
+};
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Bytes of device workspace lbm_init needs for these parameters. */
+int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
+
+/* Validate p, lay out the state in d_workspace (device memory, 256-byte
+ * aligned, at least lbm_workspace_bytes; NULL lets the library allocate
+ * and own it), copy phi0/T0 (host, nx*ny doubles each, read before return)
+ * and build the initial state: u = 0, p = 0, liquid fraction 1, every
+ * lattice at equilibrium.  hip_stream is a hipStream_t (NULL = default
+ * stream).  On success *out owns the context; the caller's workspace must
+ * outlive it. */
+int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_workspace,
+             size_t ws_bytes, void* hip_stream, lbm_ctx** out);
+
+/* Enqueue nsteps >= 0 time steps on the context's stream (asynchronous). */
+int lbm_step(lbm_ctx* c, int32_t nsteps);
+
+/* Macroscopic fields at the current time level (phi, T, u, p, f_s, f_l,
+ * rho, H, mdot as the next step would compute them).  host_out[j] receives
+ * the j-th set bit of field_mask, nx*ny doubles.  Synchronises. */
+int lbm_fields(lbm_ctx* c, uint32_t field_mask, double* const* host_out);
+
+/* Same fields as FP32 into device buffers (nx*ny floats each), enqueued on
+ * the context's stream; no synchronisation. */
+int lbm_fields_device(lbm_ctx* c, uint32_t field_mask, float* const* d_out);
+
+/* FP64 sums over the grid: sum phi, sum clamp(phi), solid and liquid
+ * volume, sum H, max |u|, solid height on the centre column; returns
+ * LBM_ENONFINITE if a field is NaN/Inf.  Synchronises. */
+int lbm_diag(lbm_ctx* c, lbm_diag_t* out);
+
+/* Post-collision populations of lattice 0 = g, 1 = f, 2 = h (9*nx*ny
+ * doubles, [i][k]) as stored after the last step.  Synchronises. */
+int lbm_pops(lbm_ctx* c, int32_t lattice, double* host_out);
+
+/* Checkpoint of the whole state (populations, history fields, step count)
+ * as raw bytes; lbm_load accepts only a blob from an identical grid. */
+size_t lbm_state_bytes(const lbm_ctx* c);
+int lbm_save(lbm_ctx* c, void* host_buf, size_t bytes);
+int lbm_load(lbm_ctx* c, const void* host_buf, size_t bytes);
+
+int64_t lbm_step_count(const lbm_ctx* c);
+int lbm_sync(lbm_ctx* c);
+void lbm_destroy(lbm_ctx* c);
+const char* lbm_strerror(int code);
+const char* lbm_last_error(void);
+
+/* Tile shape of the fused step kernel: 0 = 64x4 (default), 1 = 32x8,
+ * 2 = 64x8; xcd_remap 1 maps consecutive tiles to one XCD. */
+int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

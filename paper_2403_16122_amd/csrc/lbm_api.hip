@@ -1,0 +1,432 @@
+// Host side of the C ABI declared in include/lbm.h: parameter validation,
+// workspace layout, launches on the caller's stream, read-back and
+// checkpointing.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int dev_error(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return LBM_EDEVICE;
+}
+
+#define LBM_CK(expr)                                  \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return dev_error(e_, #expr); \
+  } while (0)
+
+constexpr double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+constexpr int kPops = 27;
+constexpr int kAuxPlanes = 2 + 8;  // (phi u) x/y; phi_ref, f_s^H, p, S double-buffered
+constexpr int kStatePlanes = kPops + 6;  // checkpointed planes
+constexpr int64_t kMagic = 0x4c424d4750555331LL;
+
+bool all_finite(const lbm_params* p) {
+  const double v[] = {p->W,       p->M,      p->sigma,  p->rho_l,  p->rho_g,  p->rho_s,
+                      p->mu_l,    p->mu_g,   p->mu_s,   p->cp_l,   p->cp_g,   p->cp_s,
+                      p->cp_ref,  p->k_l,    p->k_g,    p->k_s,    p->latent, p->T_melt,
+                      p->T_bottom, p->theta_bottom_deg, p->theta_top_deg, p->gx, p->gy,
+                      p->bq_beta, p->bq_rho0, p->bq_Tref};
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return true;
+}
+
+// Every relaxation time must exceed 1/2: tau_g = M/cs^2 + 1/2 needs M > 0,
+// tau_f = mu/(rho cs^2) + 1/2 needs mu, rho > 0 in every phase (mixtures
+// stay positive), tau_h = k/(cp_ref cs^2) + 1/2 needs k, cp_ref > 0.
+int validate(const lbm_params* p) {
+  if (!p) return LBM_EINVAL;
+  if (p->nx < 3 || p->ny < 3) return LBM_EINVAL;
+  if ((long long)p->nx * p->ny > (1LL << 31) / 32) return LBM_EINVAL;  // 32-bit node indices
+  if (!all_finite(p)) return LBM_EINVAL;
+  if (!(p->W > 0) || !(p->M > 0) || p->sigma < 0) return LBM_EINVAL;
+  if (!(p->rho_l > 0 && p->rho_g > 0 && p->rho_s > 0)) return LBM_EINVAL;
+  if (!(p->mu_l > 0 && p->mu_g > 0 && p->mu_s > 0)) return LBM_EINVAL;
+  if (!(p->cp_l > 0 && p->cp_g > 0 && p->cp_s > 0 && p->cp_ref > 0)) return LBM_EINVAL;
+  if (!(p->k_l > 0 && p->k_g > 0 && p->k_s > 0)) return LBM_EINVAL;
+  if (!(p->latent > 0)) return LBM_EINVAL;
+  if (!(p->theta_bottom_deg > 0 && p->theta_bottom_deg < 180)) return LBM_EINVAL;
+  if (!(p->theta_top_deg > 0 && p->theta_top_deg < 180)) return LBM_EINVAL;
+  if (p->st_solid_mask != 0 && p->st_solid_mask != 1) return LBM_EINVAL;
+  if (p->storage != LBM_STORE_FP32) return LBM_EINVAL;
+  return LBM_OK;
+}
+
+long long plane_floats(const lbm_params* p) {
+  const long long n = (long long)p->nx * p->ny;
+  return (n + 63) / 64 * 64;  // 256-byte aligned planes
+}
+
+size_t part_bytes() { return (size_t)(lbmk::RED_BLOCKS + 1) * lbmk::RED_NVAL * sizeof(double); }
+
+size_t ws_size(const lbm_params* p) {
+  const long long pl = plane_floats(p);
+  return (size_t)(2 * kPops + kAuxPlanes + lbmk::NFIELD) * pl * sizeof(float) + part_bytes();
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params P;
+  lbmk::KParams K;
+  lbmk::IParams I;
+  lbmk::State S;
+  hipStream_t stream;
+  int device;
+  void* ws;
+  bool own_ws;
+  int cur;
+  int64_t step;
+  int tile_variant;
+  int xcd;
+  double Href;
+  std::vector<float> stage;
+};
+
+namespace {
+
+void fill_kparams(lbm_ctx* c) {
+  const lbm_params& p = c->P;
+  lbmk::KParams& K = c->K;
+  K.nx = p.nx;
+  K.ny = p.ny;
+  K.plane = plane_floats(&p);
+  const double tau_g = 3.0 * p.M + 0.5;
+  K.inv_tau_g = (float)(1.0 / tau_g);
+  K.src_g = (float)(1.0 - 0.5 / tau_g);
+  K.four_over_W = (float)(4.0 / p.W);
+  K.beta4 = (float)(4.0 * 12.0 * p.sigma / p.W);
+  K.kappa = (float)(1.5 * p.sigma * p.W);
+  K.rho_s = (float)p.rho_s; K.rho_l = (float)p.rho_l; K.rho_g = (float)p.rho_g;
+  K.mu_s = (float)p.mu_s; K.mu_l = (float)p.mu_l; K.mu_g = (float)p.mu_g;
+  K.cp_s = (float)p.cp_s; K.cp_l = (float)p.cp_l; K.cp_g = (float)p.cp_g;
+  K.k_s = (float)p.k_s; K.k_l = (float)p.k_l; K.k_g = (float)p.k_g;
+  K.cp_ref = (float)p.cp_ref;
+  K.T_melt = (float)p.T_melt;
+  K.latent = (float)p.latent;
+  K.inv_latent = (float)(1.0 / p.latent);
+  K.three_over_cpref = (float)(3.0 / p.cp_ref);
+  for (int i = 0; i < 9; ++i) K.hwall[i] = 0.0f;
+  for (int i : {2, 5, 6}) K.hwall[i] = (float)(2.0 * kW[i] * p.cp_ref * (p.T_bottom - p.T_melt));
+  K.mdot_coef = (float)(1.0 - p.rho_s / p.rho_l);
+  K.tan_b = (float)std::tan((90.0 - p.theta_bottom_deg) * M_PI / 180.0);
+  K.tan_t = (float)std::tan((90.0 - p.theta_top_deg) * M_PI / 180.0);
+  K.gx = (float)p.gx;
+  K.gy = (float)p.gy;
+  K.bq_coef = (float)(p.bq_rho0 * p.bq_beta);
+  K.bq_Tref = (float)p.bq_Tref;
+  K.chi = (float)p.st_solid_mask;
+  c->I.cp_l = p.cp_l;
+  c->I.cp_g = p.cp_g;
+  c->I.cp_ref = p.cp_ref;
+  c->I.T_melt = p.T_melt;
+  c->I.latent = p.latent;
+  c->Href = p.cp_ref * p.T_melt + p.latent;
+}
+
+void carve(lbm_ctx* c) {
+  const long long pl = c->K.plane;
+  float* base = (float*)c->ws;
+  c->S.pops[0] = base;
+  c->S.pops[1] = base + kPops * pl;
+  float* aux = base + 2 * kPops * pl;
+  c->S.phiu = aux;
+  c->S.fsH[0] = aux + 2 * pl;
+  c->S.fsH[1] = aux + 3 * pl;
+  c->S.p[0] = aux + 4 * pl;
+  c->S.p[1] = aux + 5 * pl;
+  c->S.S[0] = aux + 6 * pl;
+  c->S.S[1] = aux + 7 * pl;
+  c->S.ref[0] = aux + 8 * pl;
+  c->S.ref[1] = aux + 9 * pl;
+  c->S.fields = aux + kAuxPlanes * pl;
+  c->S.part = (double*)(c->S.fields + lbmk::NFIELD * pl);
+}
+
+int run_fields(lbm_ctx* c) {
+  if (lbmk::launch_step(c->K, c->S, c->cur, true, c->tile_variant, c->xcd, c->stream))
+    return dev_error(hipGetLastError(), "fields kernel launch");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
+  if (!bytes) return LBM_EINVAL;
+  int rc = validate(p);
+  if (rc) return rc;
+  *bytes = ws_size(p);
+  return LBM_OK;
+}
+
+int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_workspace,
+             size_t ws_bytes, void* hip_stream, lbm_ctx** out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) {
+    g_last_error = "invalid parameters";
+    return rc;
+  }
+  if (!phi0 || !T0) return LBM_EINVAL;
+  const size_t need = ws_size(p);
+  if (d_workspace && (ws_bytes < need || ((uintptr_t)d_workspace & 255))) {
+    g_last_error = "workspace too small or not 256-byte aligned";
+    return LBM_EINVAL;
+  }
+  const long long N = (long long)p->nx * p->ny;
+  for (long long k = 0; k < N; ++k)
+    if (!std::isfinite(phi0[k]) || !std::isfinite(T0[k])) {
+      g_last_error = "non-finite initial field";
+      return LBM_EINVAL;
+    }
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ENOMEM;
+  c->P = *p;
+  c->stream = (hipStream_t)hip_stream;
+  c->cur = 0;
+  c->step = 0;
+  c->tile_variant = 0;
+  c->xcd = 1;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return dev_error(e, "hipGetDevice");
+  }
+  fill_kparams(c);
+  if (d_workspace) {
+    c->ws = d_workspace;
+    c->own_ws = false;
+  } else {
+    e = hipMalloc(&c->ws, need);
+    if (e != hipSuccess) {
+      delete c;
+      g_last_error = "hipMalloc of the workspace failed";
+      return LBM_ENOMEM;
+    }
+    c->own_ws = true;
+  }
+  carve(c);
+  // stage phi0 and T0 (FP64) in the output-field planes (10 planes >= 4)
+  double* d_phi0 = (double*)c->S.fields;
+  double* d_T0 = d_phi0 + N;
+  e = hipMemcpyAsync(d_phi0, phi0, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_T0, T0, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && lbmk::launch_init(c->K, c->I, c->S, 0, d_phi0, d_T0, c->stream))
+    e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    int r = dev_error(e, "lbm_init");
+    lbm_destroy(c);
+    return r;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    if (lbmk::launch_step(c->K, c->S, c->cur, false, c->tile_variant, c->xcd, c->stream))
+      return dev_error(hipGetLastError(), "step kernel launch");
+    c->cur ^= 1;
+    c->step++;
+  }
+  return LBM_OK;
+}
+
+int lbm_fields_device(lbm_ctx* c, uint32_t mask, float* const* d_out) {
+  if (!c || !d_out || (mask >> lbmk::NFIELD)) return LBM_EINVAL;
+  int rc = run_fields(c);
+  if (rc) return rc;
+  const long long N = (long long)c->P.nx * c->P.ny;
+  int j = 0;
+  for (int b = 0; b < lbmk::NFIELD; ++b) {
+    if (!(mask & (1u << b))) continue;
+    if (!d_out[j]) return LBM_EINVAL;
+    LBM_CK(hipMemcpyAsync(d_out[j], c->S.fields + b * c->K.plane, N * sizeof(float),
+                          hipMemcpyDeviceToDevice, c->stream));
+    ++j;
+  }
+  return LBM_OK;
+}
+
+int lbm_fields(lbm_ctx* c, uint32_t mask, double* const* host_out) {
+  if (!c || !host_out || (mask >> lbmk::NFIELD)) return LBM_EINVAL;
+  int rc = run_fields(c);
+  if (rc) return rc;
+  const long long N = (long long)c->P.nx * c->P.ny;
+  c->stage.resize(N);
+  int j = 0;
+  for (int b = 0; b < lbmk::NFIELD; ++b) {
+    if (!(mask & (1u << b))) continue;
+    if (!host_out[j]) return LBM_EINVAL;
+    LBM_CK(hipMemcpyAsync(c->stage.data(), c->S.fields + b * c->K.plane, N * sizeof(float),
+                          hipMemcpyDeviceToHost, c->stream));
+    LBM_CK(hipStreamSynchronize(c->stream));
+    const double add = (b == 8) ? c->Href : 0.0;  // H is kept relative to H_ref on the device
+    for (long long k = 0; k < N; ++k) host_out[j][k] = (double)c->stage[k] + add;
+    ++j;
+  }
+  LBM_CK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_diag(lbm_ctx* c, lbm_diag_t* out) {
+  if (!c || !out) return LBM_EINVAL;
+  int rc = run_fields(c);
+  if (rc) return rc;
+  if (lbmk::launch_reduce(c->K, c->S, c->Href, c->stream))
+    return dev_error(hipGetLastError(), "reduce launch");
+  double v[lbmk::RED_NVAL];
+  LBM_CK(hipMemcpyAsync(v, c->S.part + lbmk::RED_BLOCKS * lbmk::RED_NVAL, sizeof(v),
+                        hipMemcpyDeviceToHost, c->stream));
+  LBM_CK(hipStreamSynchronize(c->stream));
+  out->step = c->step;
+  out->sum_phi = v[0];
+  out->sum_phic = v[1];
+  out->sum_solid = v[2];
+  out->sum_liquid = v[3];
+  out->sum_H = v[4];
+  out->max_u = v[5];
+  out->nonfinite = v[6] > 0 ? 1 : 0;
+  out->h_c = v[7];
+  return out->nonfinite ? LBM_ENONFINITE : LBM_OK;
+}
+
+int lbm_pops(lbm_ctx* c, int32_t lattice, double* host_out) {
+  if (!c || !host_out || lattice < 0 || lattice > 2) return LBM_EINVAL;
+  const long long N = (long long)c->P.nx * c->P.ny;
+  c->stage.resize(N);
+  const double cpr = c->P.cp_ref, Tm = c->P.T_melt;
+  // g is stored relative to w_i phi_ref, the rest h population relative to L f_s^H
+  std::vector<float> fs;
+  if (lattice != 1) {
+    fs.resize(N);
+    LBM_CK(hipMemcpyAsync(fs.data(), lattice == 0 ? c->S.ref[c->cur] : c->S.fsH[c->cur],
+                          N * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  }
+  for (int i = 0; i < 9; ++i) {
+    LBM_CK(hipMemcpyAsync(c->stage.data(), c->S.pops[c->cur] + (lattice * 9 + i) * c->K.plane,
+                          N * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    LBM_CK(hipStreamSynchronize(c->stream));
+    double add = 0.0;
+    if (lattice == 2) add = i == 0 ? c->Href - cpr * Tm + kW[0] * cpr * Tm : kW[i] * cpr * Tm;
+    for (long long k = 0; k < N; ++k) {
+      double v = (double)c->stage[k] + add;
+      if (lattice == 2 && i == 0) v -= c->P.latent * (double)fs[k];
+      if (lattice == 0) v += kW[i] * (double)fs[k];  // stored g_i - w_i phi_ref
+      host_out[i * N + k] = v;
+    }
+  }
+  return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c) {
+  if (!c) return 0;
+  const size_t N = (size_t)c->P.nx * c->P.ny;
+  return 4 * sizeof(int64_t) + (size_t)kStatePlanes * N * sizeof(float);
+}
+
+int lbm_save(lbm_ctx* c, void* buf, size_t bytes) {
+  if (!c || !buf || bytes < lbm_state_bytes(c)) return LBM_EINVAL;
+  const size_t N = (size_t)c->P.nx * c->P.ny;
+  int64_t hdr[4] = {kMagic, c->P.nx, c->P.ny, c->step};
+  char* o = (char*)buf;
+  std::memcpy(o, hdr, sizeof(hdr));
+  o += sizeof(hdr);
+  const float* src[kStatePlanes];
+  for (int i = 0; i < kPops; ++i) src[i] = c->S.pops[c->cur] + i * c->K.plane;
+  src[kPops + 0] = c->S.phiu;
+  src[kPops + 1] = c->S.phiu + c->K.plane;
+  src[kPops + 2] = c->S.fsH[c->cur];
+  src[kPops + 3] = c->S.p[c->cur];
+  src[kPops + 4] = c->S.S[c->cur];
+  src[kPops + 5] = c->S.ref[c->cur];
+  for (int i = 0; i < kStatePlanes; ++i) {
+    LBM_CK(hipMemcpyAsync(o, src[i], N * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    o += N * sizeof(float);
+  }
+  LBM_CK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_load(lbm_ctx* c, const void* buf, size_t bytes) {
+  if (!c || !buf || bytes < lbm_state_bytes(c)) return LBM_EINVAL;
+  const size_t N = (size_t)c->P.nx * c->P.ny;
+  int64_t hdr[4];
+  const char* o = (const char*)buf;
+  std::memcpy(hdr, o, sizeof(hdr));
+  if (hdr[0] != kMagic || hdr[1] != c->P.nx || hdr[2] != c->P.ny) return LBM_ESTATE;
+  o += sizeof(hdr);
+  float* dst[kStatePlanes];
+  for (int i = 0; i < kPops; ++i) dst[i] = c->S.pops[c->cur] + i * c->K.plane;
+  dst[kPops + 0] = c->S.phiu;
+  dst[kPops + 1] = c->S.phiu + c->K.plane;
+  dst[kPops + 2] = c->S.fsH[c->cur];
+  dst[kPops + 3] = c->S.p[c->cur];
+  dst[kPops + 4] = c->S.S[c->cur];
+  dst[kPops + 5] = c->S.ref[c->cur];
+  for (int i = 0; i < kStatePlanes; ++i) {
+    LBM_CK(hipMemcpyAsync(dst[i], o, N * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    o += N * sizeof(float);
+  }
+  LBM_CK(hipStreamSynchronize(c->stream));
+  c->step = hdr[3];
+  return LBM_OK;
+}
+
+int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->step : -1; }
+
+int lbm_sync(lbm_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  LBM_CK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap) {
+  if (!c || tile_variant < 0 || tile_variant > 2 || xcd_remap < 0 || xcd_remap > 1)
+    return LBM_EINVAL;
+  c->tile_variant = tile_variant;
+  c->xcd = xcd_remap;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  if (c->own_ws && c->ws) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->ws);
+  }
+  delete c;
+}
+
+const char* lbm_strerror(int code) {
+  switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of memory";
+    case LBM_EDEVICE: return "HIP device error";
+    case LBM_ENONFINITE: return "non-finite field";
+    case LBM_ESTATE: return "state mismatch";
+    default: return "unknown error";
+  }
+}
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,577 @@
+// gfx950 kernels of the coupled phase-field / flow / enthalpy D2Q9 step
+// (Huang, Wang, Chai & Shi, arXiv:2403.16122, Sec. 3).
+//
+// One fused kernel per time step.  A workgroup owns a TX x TY tile of nodes
+// (one node per lane, TX lanes along x so a wavefront reads whole rows).
+// It first rebuilds, for the tile plus a halo ring, the node-local
+// macroscopic quantities of time t (pull-streamed g and h -> H, f_l, T,
+// mass source, phi, rho; Eq. (9), (19), (26), (1)) into LDS, fills the wall
+// ghost rows with the wetting condition (Eq. (39)-(41)), and then evaluates
+// the isotropic stencils of Eq. (38), the forces, the flow macros and the
+// three BGK collisions for its own nodes, writing post-collision
+// populations to the other buffer.  Halo macros are recomputed rather than
+// exchanged, so a step is one launch and HBM sees each population once per
+// direction.
+#include "lbm_internal.h"
+
+#include <algorithm>
+
+namespace lbmk {
+namespace {
+
+// D2Q9 order: rest, +x, +y, -x, -y, (+x,+y), (-x,+y), (-x,-y), (+x,-y)
+constexpr float W0 = 4.0f / 9.0f, W1 = 1.0f / 9.0f, W5 = 1.0f / 36.0f;
+__device__ __forceinline__ constexpr float wt(int i) { return i == 0 ? W0 : (i < 5 ? W1 : W5); }
+__device__ __forceinline__ constexpr int cxv(int i) {
+  return (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+__device__ __forceinline__ constexpr int cyv(int i) {
+  return (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
+}
+__device__ __forceinline__ constexpr int opp(int i) {
+  return i == 0 ? 0 : (i < 5 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5);
+}
+
+__device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
+__device__ __forceinline__ float mix3(float fs, float pc, float zs, float zl, float zg) {
+  // Eq. (1) with the clamped order parameter
+  return fs * zs + (1.0f - fs) * (pc * zl + (1.0f - pc) * zg);
+}
+__device__ __forceinline__ int wrapx(int x, int nx) {
+  int r = x % nx;
+  return r < 0 ? r + nx : r;
+}
+
+// Pull-stream the 9 populations of one lattice into node (x, y).  Sources
+// beyond a wall are replaced by the bounce-back of the node's own opposite
+// population (half-way rule); for h at the bottom wall by the
+// anti-bounce-back Dirichlet value -h_opp + 2 w_i cp_ref (T_w - T_m) in the
+// shifted variables.
+template <int LAT>
+__device__ __forceinline__ void pull9(const float* __restrict__ A, const KParams& P, int x, int y,
+                                      int xm, int xp, float q[9]) {
+  const long long pl = P.plane;
+  const float* base = A + (long long)(LAT * 9) * pl;
+  const int nx = P.nx;
+  const bool bot = (y == 0), top = (y == P.ny - 1);
+  const int k = y * nx + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cy = cyv(i), cx = cxv(i);
+    const bool wall = (cy > 0 && bot) || (cy < 0 && top);
+    const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
+    const int sk = (y - cy) * nx + sx;
+    const long long addr = wall ? (long long)opp(i) * pl + k : (long long)i * pl + sk;
+    float v = base[addr];
+    if (LAT == 2 && cy > 0) v = bot ? (P.hwall[i] - v) : v;
+    q[i] = v;
+  }
+}
+
+// The phase-field populations are stored relative to the rest state of
+// the node that wrote them: node x stores g_i(x) - w_i phi_ref(x), where
+// phi_ref(x) is its order parameter of that step, kept in its own plane.
+// A receiving node adds back w_i phi_ref(source) and re-expresses all nine
+// in its own reference, q_i = g_i - w_i phi_ref(self).  Every stored number
+// is then a one-step increment, so FP32 resolves phi to ~1e-11 in bulk
+// liquid, bulk gas, interfaces and frozen regions alike (exact algebra).
+__device__ __forceinline__ void pull_g(const float* __restrict__ A, const float* __restrict__ ref,
+                                       const KParams& P, int x, int y, int xm, int xp, float q[9],
+                                       float& rself) {
+  const long long pl = P.plane;
+  const int nx = P.nx;
+  const bool bot = (y == 0), top = (y == P.ny - 1);
+  const int k = y * nx + x;
+  rself = ref[k];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cy = cyv(i), cx = cxv(i);
+    const bool wall = (cy > 0 && bot) || (cy < 0 && top);
+    const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
+    const int sk = wall ? k : (y - cy) * nx + sx;
+    const int si = wall ? opp(i) : i;
+    const float v = A[(long long)si * pl + sk];
+    const float rs = i == 0 ? rself : ref[sk];
+    q[i] = i == 0 ? v : v + wt(i) * (rs - rself);
+  }
+}
+
+struct Macro {
+  float g[9], h[9];
+  float E;      // H - H_l + L f_s^H(n-1): the enthalpy excess over the stored latent part
+  float dT;     // T - T_m
+  float fprev;  // f_s^H of the previous step
+  float cp, kk, fl, fsH, mdot, phi, fsol, rho, mu;
+  float r;      // reference phi of the received g populations (own previous phi)
+  float dl;     // phi - r, resolved to the precision of the small stored numbers
+};
+
+// Node-local macroscopic quantities of time t (Eq. (29), (9), (19), (26), (1)).
+//
+// Storage of h: every population is kept relative to the equilibrium of
+// liquid at rest at T_m (h_i - h_i^ref), and the rest population, which
+// carries the latent heat, is additionally kept relative to L f_s^H of the
+// previous step: s_0 = (h_0 - h_0^ref) + L f_s^H(n-1).  Both shifts are
+// exact algebra; together they keep every stored value small, so FP32
+// resolves H to ~1e-7 of the sensible part in liquid, mushy and solid
+// nodes alike instead of ~1e-6 of H ~ L.
+__device__ __forceinline__ void node_macro(const float* __restrict__ A,
+                                           const float* __restrict__ phiref,
+                                           const float* __restrict__ fsH_prev, const KParams& P,
+                                           int x, int y, Macro& m) {
+  const int xm = x == 0 ? P.nx - 1 : x - 1;
+  const int xp = x == P.nx - 1 ? 0 : x + 1;
+  float rs;
+  pull_g(A, phiref, P, x, y, xm, xp, m.g, rs);
+  pull9<2>(A, P, x, y, xm, xp, m.h);
+  const float fprev = fsH_prev[y * P.nx + x];
+  float D0 = 0.0f, hs = 0.0f;  // D0 = sum g_i - r
+#pragma unroll
+  for (int i = 0; i < 9; ++i) D0 += m.g[i];
+  const float G0 = rs + D0;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) hs += m.h[i];
+  const float pc0 = clamp01(G0);
+  const float fs_lag = pc0 * fprev;  // cp and k use the lagged solid fraction
+  const float cp = mix3(fs_lag, pc0, P.cp_s, P.cp_l, P.cp_g);
+  const float kk = mix3(fs_lag, pc0, P.k_s, P.k_l, P.k_g);
+  // H - H_l = E - L f_s^H(n-1) and H - H_s = E + L (1 - f_s^H(n-1)) for
+  // H_s = cp T_m, H_l = cp T_m + L (Eq. (9))
+  const float E = hs + m.h[0] + (P.cp_ref - cp) * P.T_melt;
+  const float dHl = E - P.latent * fprev;
+  const float dHs = E + P.latent * (1.0f - fprev);
+  const float fl = clamp01(E * P.inv_latent + (1.0f - fprev));
+  const float rcp = 1.0f / cp;
+  const float dT = dHs < 0.0f ? dHs * rcp : (dHl > 0.0f ? dHl * rcp : 0.0f);
+  const float fsH = 1.0f - fl;
+  const float mdot = P.mdot_coef * pc0 * (fsH - fprev);
+  // phi from Eq. (26) with div(u) = mdot; phi - r = (D0 + r mdot/2)/(1 - mdot/2)
+  const float rden = 1.0f / (1.0f - 0.5f * mdot);
+  const float dl = (D0 + 0.5f * rs * mdot) * rden;
+  const float phi = rs + dl;
+  const float pc = clamp01(phi);
+  m.r = rs;
+  m.dl = dl;
+  const float fsol = pc * fsH;
+  m.E = E;
+  m.dT = dT;
+  m.fprev = fprev;
+  m.cp = cp;
+  m.kk = kk;
+  m.fl = fl;
+  m.fsH = fsH;
+  m.mdot = mdot;
+  m.phi = phi;
+  m.fsol = fsol;
+  m.rho = mix3(fsol, pc, P.rho_s, P.rho_l, P.rho_g);
+  m.mu = mix3(fsol, pc, P.mu_s, P.mu_l, P.mu_g);
+}
+
+// Halo cells only need phi (kept as phi - 1 in LDS), rho and f_s^H.
+__device__ __forceinline__ void halo_macro(const float* __restrict__ A,
+                                           const float* __restrict__ phiref,
+                                           const float* __restrict__ fsH_prev, const KParams& P,
+                                           int x, int y, float& phim1, float& rho, float& fsH) {
+  Macro m;
+  node_macro(A, phiref, fsH_prev, P, x, y, m);
+  phim1 = (m.r - 1.0f) + m.dl;
+  rho = m.rho;
+  fsH = m.fsH;
+}
+
+template <int TX, int TY, bool FIELDS>
+__global__ __launch_bounds__(TX* TY) void k_step(
+    KParams P, const float* __restrict__ A, float* __restrict__ B, float* __restrict__ phiu,
+    const float* __restrict__ ref_in, float* __restrict__ ref_out,
+    const float* __restrict__ fsH_in, float* __restrict__ fsH_out, const float* __restrict__ p_in,
+    float* __restrict__ p_out, const float* __restrict__ S_in, float* __restrict__ S_out,
+    float* __restrict__ fields, int ntx, int ntiles, int tiles_per_xcd) {
+  constexpr int NT = TX * TY;
+  constexpr int LX = TX + 4, LY = TY + 2;  // LDS column c <-> x0 + c - 2, row r <-> y0 + r - 1
+  __shared__ float s_phi[LY][LX];  // phi - 1 (stencils are blind to the constant)
+  __shared__ float s_rho[LY][LX];
+  __shared__ float s_fsH[LY][LX];
+  __shared__ float s_p[LY][LX];
+  __shared__ float s_S[LY][LX];
+
+  const int b = blockIdx.x;
+  const int tile = tiles_per_xcd > 0 ? (b & 7) * tiles_per_xcd + (b >> 3) : b;
+  if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
+  const int nx = P.nx, ny = P.ny;
+  const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+  const int t = threadIdx.x;
+  const int lx = t % TX, ly = t / TX;
+  const int x = x0 + lx, y = y0 + ly;
+  const int xw = wrapx(x, nx);
+  const bool yin = y < ny;
+  const bool active = yin && x < nx;
+
+  // ---- phase 1: macroscopic quantities of time t into LDS ----------------
+  Macro m;
+  if (yin) {
+    node_macro(A, ref_in, fsH_in, P, xw, y, m);
+    s_phi[ly + 1][lx + 2] = (m.r - 1.0f) + m.dl;
+    s_rho[ly + 1][lx + 2] = m.rho;
+    s_fsH[ly + 1][lx + 2] = m.fsH;
+  }
+  constexpr int NRING = 2 * LX + 4 * TY;
+  for (int j = t; j < NRING; j += NT) {
+    int r, c;
+    if (j < LX) {
+      r = 0;
+      c = j;
+    } else if (j < 2 * LX) {
+      r = LY - 1;
+      c = j - LX;
+    } else {
+      const int q = j - 2 * LX;
+      r = 1 + (q >> 2);
+      const int s = q & 3;
+      c = s < 2 ? s : TX + s;
+    }
+    const int gy = y0 + r - 1;
+    if (gy >= 0 && gy < ny) {
+      float ph, rh, fh;
+      halo_macro(A, ref_in, fsH_in, P, wrapx(x0 + c - 2, nx), gy, ph, rh, fh);
+      s_phi[r][c] = ph;
+      s_rho[r][c] = rh;
+      s_fsH[r][c] = fh;
+    }
+  }
+  // lagged p and S; rows beyond a wall copy the adjacent row
+  for (int j = t; j < LX * LY; j += NT) {
+    const int r = j / LX, c = j - (j / LX) * LX;
+    const int gy = min(max(y0 + r - 1, 0), ny - 1);
+    const int k = gy * nx + wrapx(x0 + c - 2, nx);
+    s_p[r][c] = p_in[k];
+    s_S[r][c] = S_in[k];
+  }
+  __syncthreads();
+
+  // ---- wall ghost rows: wetting condition, Eq. (39)-(41) -----------------
+  const bool has_bot = (y0 == 0), has_top = (ny <= y0 + TY);
+  if (has_bot || has_top) {
+    for (int j = t; j < 2 * LX; j += NT) {
+      const bool isb = j < LX;
+      const int c = isb ? j : j - LX;
+      if (c < 1 || c > LX - 2) continue;
+      int r, r0, r1;
+      float tv;
+      if (isb) {
+        if (!has_bot) continue;
+        r = 0;
+        r0 = 1;
+        r1 = 2;
+        tv = P.tan_b;
+      } else {
+        if (!has_top) continue;
+        r = ny - y0 + 1;
+        r0 = r - 1;
+        r1 = r - 2;
+        tv = P.tan_t;
+      }
+      const float d0 = 0.5f * (s_phi[r0][c + 1] - s_phi[r0][c - 1]);
+      const float d1 = 0.5f * (s_phi[r1][c + 1] - s_phi[r1][c - 1]);
+      const float pg = s_phi[r0][c] + tv * fabsf(1.5f * d0 - 0.5f * d1);
+      const float pcg = clamp01(1.0f + pg);
+      s_phi[r][c] = pg;
+      s_rho[r][c] = mix3(pcg * s_fsH[r0][c], pcg, P.rho_s, P.rho_l, P.rho_g);
+    }
+    __syncthreads();
+  }
+  if (!active) return;  // no barrier below
+
+  // ---- phase 2: stencils (Eq. (38)), forces, flow macros, collisions -----
+  const int r = ly + 1, c = lx + 2;
+  const int k = y * nx + x;
+  float gphx, gphy, lphi, grx, gry, gpx, gpy, gSx, gSy;
+  {
+    const float C = s_phi[r][c];
+    const float E = s_phi[r][c + 1], Wv = s_phi[r][c - 1], N = s_phi[r + 1][c], S = s_phi[r - 1][c];
+    const float NE = s_phi[r + 1][c + 1], NW = s_phi[r + 1][c - 1];
+    const float SW = s_phi[r - 1][c - 1], SE = s_phi[r - 1][c + 1];
+    // 3 sum w_i c_i z_i and 6 sum w_i (z_i - z_0)
+    gphx = (E - Wv) * (1.0f / 3.0f) + (NE - NW - SW + SE) * (1.0f / 12.0f);
+    gphy = (N - S) * (1.0f / 3.0f) + (NE + NW - SW - SE) * (1.0f / 12.0f);
+    lphi = (E + N + Wv + S - 4.0f * C) * (2.0f / 3.0f) + (NE + NW + SW + SE - 4.0f * C) * (1.0f / 6.0f);
+  }
+#define LBM_GRAD(arr, ox, oy)                                                                   \
+  {                                                                                             \
+    const float E = arr[r][c + 1], Wv = arr[r][c - 1], N = arr[r + 1][c], S = arr[r - 1][c];    \
+    const float NE = arr[r + 1][c + 1], NW = arr[r + 1][c - 1];                                 \
+    const float SW = arr[r - 1][c - 1], SE = arr[r - 1][c + 1];                                 \
+    ox = (E - Wv) * (1.0f / 3.0f) + (NE - NW - SW + SE) * (1.0f / 12.0f);                       \
+    oy = (N - S) * (1.0f / 3.0f) + (NE + NW - SW - SE) * (1.0f / 12.0f);                        \
+  }
+  LBM_GRAD(s_rho, grx, gry)
+  LBM_GRAD(s_p, gpx, gpy)
+  LBM_GRAD(s_S, gSx, gSy)
+#undef LBM_GRAD
+
+  const float phi = m.phi, rho = m.rho;
+  const float om = (1.0f - m.r) - m.dl;  // 1 - phi without cancellation in either bulk
+  // interface terms (Eq. (3), (12), (13))
+  const float lam = P.four_over_W * phi * om;
+  const float gn2 = gphx * gphx + gphy * gphy;
+  float lnx = 0.0f, lny = 0.0f;
+  if (gn2 > 1e-24f) {
+    const float s = lam * rsqrtf(gn2);
+    lnx = s * gphx;
+    lny = s * gphy;
+  }
+  const float muphi = -P.beta4 * phi * om * (phi - 0.5f) - P.kappa * lphi;
+  const float smask = 1.0f - P.chi * m.fsol;
+  const float T = P.T_melt + m.dT;
+  const float gcoef = rho - P.bq_coef * (T - P.bq_Tref);
+  const float Fx = smask * muphi * gphx + gcoef * P.gx;
+  const float Fy = smask * muphi * gphy + gcoef * P.gy;
+
+  // flow populations (Eq. (34)-(35))
+  float f[9];
+  {
+    const int xm = x == 0 ? nx - 1 : x - 1;
+    const int xp = x == nx - 1 ? 0 : x + 1;
+    pull9<1>(A, P, x, y, xm, xp, f);
+  }
+  const float mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const float my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  const float rrho = 1.0f / rho;
+  const float usx = (mx + 0.5f * Fx) * rrho, usy = (my + 0.5f * Fy) * rrho;
+  const float fbx = -m.fsol * usx, fby = -m.fsol * usy;  // f = f_s (u_s - u*), u_s = 0
+  const float ux = usx + 0.5f * fbx, uy = usy + 0.5f * fby;
+  const float Ssrc = rho * m.mdot + ux * grx + uy * gry;
+  const float Ftx = Fx - gpx + (1.0f / 3.0f) * (grx + gSx);
+  const float Fty = Fy - gpy + (1.0f / 3.0f) * (gry + gSy);
+  const float uFt = ux * Ftx + uy * Fty;
+  const float usq = ux * ux + uy * uy;
+  const float tauf = 3.0f * m.mu * rrho + 0.5f;
+  const float F0 = W0 * (Ssrc - 3.0f * uFt);
+  float sumf = 0.0f;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) sumf += f[i];
+  const float p = 0.6f * (sumf + 0.5f * Ssrc + tauf * F0 + rho * (W0 * (-1.5f * usq)));
+
+  if (FIELDS) {
+    const long long pl = P.plane;
+    fields[0 * pl + k] = phi;
+    fields[1 * pl + k] = T;
+    fields[2 * pl + k] = ux;
+    fields[3 * pl + k] = uy;
+    fields[4 * pl + k] = p;
+    fields[5 * pl + k] = m.fsol;
+    fields[6 * pl + k] = m.fl;
+    fields[7 * pl + k] = rho;
+    fields[8 * pl + k] = m.E - P.latent * m.fprev - (P.cp_ref - m.cp) * P.T_melt;
+    fields[9 * pl + k] = m.mdot;
+    return;
+  }
+
+  const long long pl = P.plane;
+  // flow collision (Eq. (30)-(33))
+  {
+    const float itau = 1.0f / tauf, sf = 1.0f - 0.5f * itau;
+    const float Gx = Fx + rho * fbx, Gy = Fy + rho * fby;
+    float* Bf = B + 9 * pl;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const float cx = (float)cxv(i), cy = (float)cyv(i);
+      const float cu = cx * ux + cy * uy;
+      const float si = wt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq);
+      const float feq = 3.0f * p * (wt(i) - (i == 0 ? 1.0f : 0.0f)) + rho * si;
+      const float cF = cx * Ftx + cy * Fty;
+      const float Fi = wt(i) * (Ssrc + 3.0f * (cx * Gx + cy * Gy) + 9.0f * cu * cF - 3.0f * uFt);
+      Bf[i * pl + k] = f[i] - (f[i] - feq) * itau + sf * Fi;
+    }
+  }
+  // phase-field collision (Eq. (21), (24), (25), (37))
+  {
+    const float pux = phi * ux, puy = phi * uy;
+    const float dpx = pux - phiu[k], dpy = puy - phiu[pl + k];
+    const float ax = 3.0f * dpx + lnx, ay = 3.0f * dpy + lny;
+    const float pm = phi * m.mdot;
+    // the new reference is this step's phi (as stored); re-express the
+    // populations and the equilibrium relative to it
+    const float dr = m.r - phi;   // exact for nearby floats
+    const float dln = m.dl + dr;  // phi - phi_ref(new)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const float cx = (float)cxv(i), cy = (float)cyv(i);
+      const float cu = cx * ux + cy * uy;
+      const float gi = m.g[i] + wt(i) * dr;                 // g_i - w_i phi_ref
+      const float geq = wt(i) * (dln + 3.0f * phi * cu);  // g_i^eq - w_i phi_ref
+      const float Gi = wt(i) * (cx * ax + cy * ay + pm);
+      B[i * pl + k] = gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi;
+    }
+    ref_out[k] = phi;
+    phiu[k] = pux;
+    phiu[pl + k] = puy;
+  }
+  // enthalpy collision (Eq. (27)-(28)) in the shifted variables
+  {
+    const float itau = 1.0f / (m.kk * P.three_over_cpref + 0.5f);
+    const float cpT = m.cp * T;
+    const float crd = P.cp_ref * m.dT;
+    float* Bh = B + 18 * pl;
+    float hs = 0.0f;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const float cx = (float)cxv(i), cy = (float)cyv(i);
+      const float cu = cx * ux + cy * uy;
+      const float heq = wt(i) * (crd + cpT * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+      Bh[i * pl + k] = m.h[i] - (m.h[i] - heq) * itau;
+      hs += m.h[i];
+    }
+    // rest population: h0eq - h0 = sum_{i>0} h_i - cp_ref dT + w0 (cp_ref dT - 1.5 cp T u.u);
+    // the stored value moves by that relaxation plus L (f_s^H(n) - f_s^H(n-1))
+    const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
+    Bh[k] = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
+  }
+  fsH_out[k] = m.fsH;
+  p_out[k] = p;
+  S_out[k] = Ssrc;
+}
+
+// Initial state (no time-stepping yet): u = 0, p = 0, liquid fraction 1,
+// each lattice at its equilibrium; computed in FP64 and rounded once.
+__global__ void k_init(KParams P, IParams I, const double* __restrict__ phi0,
+                       const double* __restrict__ T0, float* __restrict__ A,
+                       float* __restrict__ phiu, float* __restrict__ ref, float* __restrict__ fsH,
+                       float* __restrict__ p, float* __restrict__ S) {
+  const long long N = (long long)P.nx * P.ny;
+  const long long pl = P.plane;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < N;
+       k += (long long)gridDim.x * blockDim.x) {
+    const double ph = phi0[k];
+    const double pc = ph < 0.0 ? 0.0 : (ph > 1.0 ? 1.0 : ph);
+    const double cp = pc * I.cp_l + (1.0 - pc) * I.cp_g;
+    const double H0 = cp * T0[k] + I.latent;
+    const double Hs = cp * I.T_melt, Hl = Hs + I.latent;
+    const double fl = H0 <= Hs ? 0.0 : (H0 >= Hl ? 1.0 : (H0 - Hs) / (Hl - Hs));
+    const double T = H0 < Hs ? H0 / cp : (H0 > Hl ? I.T_melt + (H0 - Hl) / cp : I.T_melt);
+    const double dT = T - I.T_melt;
+    const double Href = I.cp_ref * I.T_melt + I.latent;
+    const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const float fs0 = (float)(1.0 - fl);
+    const float ref0 = (float)ph;
+    ref[k] = ref0;
+    for (int i = 0; i < 9; ++i) {
+      A[i * pl + k] = (float)(w[i] * (ph - (double)ref0));
+      A[(9 + i) * pl + k] = 0.0f;
+      const double hs = i == 0 ? (H0 - Href) - I.cp_ref * dT + w[0] * I.cp_ref * dT + I.latent * (double)fs0
+                               : w[i] * I.cp_ref * dT;
+      A[(18 + i) * pl + k] = (float)hs;
+    }
+    phiu[k] = 0.0f;
+    phiu[pl + k] = 0.0f;
+    fsH[k] = fs0;
+    p[k] = 0.0f;
+    S[k] = 0.0f;
+  }
+}
+
+// Diagnostics: per-block FP64 partial sums of the output fields, then one
+// block combines the partials in a fixed order (deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_reduce1(KParams P, const float* __restrict__ F,
+                                                 double Href, double* __restrict__ part) {
+  const long long N = (long long)P.nx * P.ny;
+  const long long pl = P.plane;
+  const int xc = P.nx / 2;
+  double v[RED_NVAL] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long k = blockIdx.x * 256LL + threadIdx.x; k < N; k += (long long)gridDim.x * 256) {
+    const double ph = F[k], T = F[pl + k], ux = F[2 * pl + k], uy = F[3 * pl + k];
+    const double pr = F[4 * pl + k], fs = F[5 * pl + k], fl = F[6 * pl + k], Ht = F[8 * pl + k];
+    const double pc = ph < 0.0 ? 0.0 : (ph > 1.0 ? 1.0 : ph);
+    const double um = sqrt(ux * ux + uy * uy);
+    v[0] += ph;
+    v[1] += pc;
+    v[2] += fs;
+    v[3] += pc * fl;
+    v[4] += Ht + Href;
+    v[5] = fmax(v[5], um);
+    if (!isfinite(ph) || !isfinite(T) || !isfinite(um) || !isfinite(pr)) v[6] += 1.0;
+    if ((int)(k % P.nx) == xc) v[7] += fs;
+  }
+  __shared__ double sh[4][RED_NVAL];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < RED_NVAL; ++j) {
+    const double r = j == 5 ? wave_max(v[j]) : wave_sum(v[j]);
+    if (lane == 0) sh[wv][j] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < RED_NVAL) {
+    const int j = threadIdx.x;
+    double r = sh[0][j];
+    for (int w = 1; w < 4; ++w) r = j == 5 ? fmax(r, sh[w][j]) : r + sh[w][j];
+    part[blockIdx.x * RED_NVAL + j] = r;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_reduce2(double* __restrict__ part, int nblocks) {
+  const int j = threadIdx.x;
+  if (j >= RED_NVAL) return;
+  double r = part[j];
+  for (int b = 1; b < nblocks; ++b) r = j == 5 ? fmax(r, part[b * RED_NVAL + j]) : r + part[b * RED_NVAL + j];
+  part[RED_BLOCKS * RED_NVAL + j] = r;  // final values after the partials
+}
+
+template <int TX, int TY>
+int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int xcd, hipStream_t st) {
+  const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+  const int ntiles = ntx * nty;
+  int tpx = 0, grid = ntiles;
+  if (xcd) {
+    tpx = (ntiles + 7) / 8;
+    grid = 8 * tpx;
+  }
+  const int nxt = cur ^ 1;
+  if (fields_only)
+    hipLaunchKernelGGL((k_step<TX, TY, true>), dim3(grid), dim3(TX * TY), 0, st, P, S.pops[cur],
+                       S.pops[nxt], S.phiu, S.ref[cur], S.ref[nxt], S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur],
+                       S.S[nxt], S.fields, ntx, ntiles, tpx);
+  else
+    hipLaunchKernelGGL((k_step<TX, TY, false>), dim3(grid), dim3(TX * TY), 0, st, P, S.pops[cur],
+                       S.pops[nxt], S.phiu, S.ref[cur], S.ref[nxt], S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur],
+                       S.S[nxt], S.fields, ntx, ntiles, tpx);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace
+
+int launch_init(const KParams& P, const IParams& I, const State& S, int cur, const double* d_phi0,
+                const double* d_T0, hipStream_t st) {
+  const long long N = (long long)P.nx * P.ny;
+  const int grid = (int)std::min<long long>((N + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, st, P, I, d_phi0, d_T0, S.pops[cur], S.phiu,
+                     S.ref[cur], S.fsH[cur], S.p[cur], S.S[cur]);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int tile_variant,
+                int xcd_remap, hipStream_t st) {
+  switch (tile_variant) {
+    case 1:
+      return launch_tile<32, 8>(P, S, cur, fields_only, xcd_remap, st);
+    case 2:
+      return launch_tile<64, 8>(P, S, cur, fields_only, xcd_remap, st);
+    default:
+      return launch_tile<64, 4>(P, S, cur, fields_only, xcd_remap, st);
+  }
+}
+
+int launch_reduce(const KParams& P, const State& S, double Href, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce1, dim3(RED_BLOCKS), dim3(256), 0, st, P, S.fields, Href, S.part);
+  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(64), 0, st, S.part, RED_BLOCKS);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace lbmk

@@ -1,0 +1,216 @@
+"""Thin ctypes binding of ``liblbm.so`` (include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides the device workspace and the stream.  There
+is no CPU fallback: importing the binding without the built library, or
+creating a solver without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Iterable, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+FIELD_BITS = {"phi": 0, "T": 1, "ux": 2, "uy": 3, "p": 4, "fs": 5, "fl": 6, "rho": 7, "H": 8, "mdot": 9}
+TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2}
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+
+EXPORTED = [
+    "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_diag",
+    "lbm_pops", "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_step_count", "lbm_sync",
+    "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_set_launch",
+]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        self.code = code
+        super().__init__(f"{what} failed: {code} ({detail})")
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("W", C.c_double), ("M", C.c_double), ("sigma", C.c_double),
+        ("rho_l", C.c_double), ("rho_g", C.c_double), ("rho_s", C.c_double),
+        ("mu_l", C.c_double), ("mu_g", C.c_double), ("mu_s", C.c_double),
+        ("cp_l", C.c_double), ("cp_g", C.c_double), ("cp_s", C.c_double), ("cp_ref", C.c_double),
+        ("k_l", C.c_double), ("k_g", C.c_double), ("k_s", C.c_double),
+        ("latent", C.c_double), ("T_melt", C.c_double), ("T_bottom", C.c_double),
+        ("theta_bottom_deg", C.c_double), ("theta_top_deg", C.c_double),
+        ("gx", C.c_double), ("gy", C.c_double),
+        ("bq_beta", C.c_double), ("bq_rho0", C.c_double), ("bq_Tref", C.c_double),
+        ("st_solid_mask", C.c_int32), ("storage", C.c_int32),
+    ]
+
+
+class Diag(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("sum_phi", C.c_double), ("sum_phic", C.c_double),
+        ("sum_solid", C.c_double), ("sum_liquid", C.c_double), ("sum_H", C.c_double),
+        ("max_u", C.c_double), ("h_c", C.c_double), ("nonfinite", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library():
+    """Load the in-tree gfx950 library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2403_16122_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    vp, dp = C.c_void_p, C.POINTER(C.c_double)
+    L.lbm_workspace_bytes.argtypes = [C.POINTER(Params), C.POINTER(C.c_size_t)]
+    L.lbm_init.argtypes = [C.POINTER(Params), dp, dp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lbm_step.argtypes = [vp, C.c_int32]
+    L.lbm_fields.argtypes = [vp, C.c_uint32, C.POINTER(dp)]
+    L.lbm_fields_device.argtypes = [vp, C.c_uint32, C.POINTER(vp)]
+    L.lbm_diag.argtypes = [vp, C.POINTER(Diag)]
+    L.lbm_pops.argtypes = [vp, C.c_int32, dp]
+    L.lbm_state_bytes.argtypes = [vp]
+    L.lbm_state_bytes.restype = C.c_size_t
+    L.lbm_save.argtypes = [vp, vp, C.c_size_t]
+    L.lbm_load.argtypes = [vp, vp, C.c_size_t]
+    L.lbm_step_count.argtypes = [vp]
+    L.lbm_step_count.restype = C.c_int64
+    L.lbm_sync.argtypes = [vp]
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_destroy.restype = None
+    L.lbm_strerror.argtypes = [C.c_int]
+    L.lbm_strerror.restype = C.c_char_p
+    L.lbm_last_error.argtypes = []
+    L.lbm_last_error.restype = C.c_char_p
+    L.lbm_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
+    _lib = L
+    return L
+
+
+def make_params(p: Dict) -> Params:
+    s = Params()
+    for name, _t in Params._fields_:
+        setattr(s, name, p[name])
+    return s
+
+
+def workspace_bytes(params: Dict) -> int:
+    L = load_library()
+    n = C.c_size_t()
+    rc = L.lbm_workspace_bytes(C.byref(make_params(params)), C.byref(n))
+    if rc != LBM_OK:
+        raise LbmError(rc, "lbm_workspace_bytes", L.lbm_strerror(rc).decode())
+    return int(n.value)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Solver:
+    """One simulation on one GPU.  ``step`` is asynchronous on the torch
+    stream that was current at construction."""
+
+    def __init__(self, params: Dict, phi0: np.ndarray, T0: np.ndarray, device: Optional[int] = None,
+                 stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the solver needs a ROCm GPU (no CPU fallback)")
+        self.L = load_library()
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        self.N = self.nx * self.ny
+        phi0 = np.ascontiguousarray(phi0, dtype=np.float64).reshape(-1)
+        T0 = np.ascontiguousarray(T0, dtype=np.float64).reshape(-1)
+        if phi0.size != self.N or T0.size != self.N:
+            raise ValueError("phi0/T0 must have nx*ny entries")
+        self._p = make_params(params)
+        nbytes = workspace_bytes(params)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            h = C.c_void_p()
+            rc = self.L.lbm_init(C.byref(self._p), _dptr(phi0), _dptr(T0), C.c_void_p(self.workspace.data_ptr()),
+                                 nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self._check(rc, "lbm_init")
+        self._h = h
+
+    def _check(self, rc: int, what: str):
+        if rc != LBM_OK:
+            raise LbmError(rc, what, self.L.lbm_last_error().decode())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.L.lbm_destroy(h)
+            self._h = None
+
+    def set_launch(self, tile: str = "64x4", xcd_remap: bool = True):
+        self._check(self.L.lbm_set_launch(self._h, TILE_VARIANTS[tile], int(bool(xcd_remap))), "lbm_set_launch")
+
+    def step(self, n: int = 1):
+        self._check(self.L.lbm_step(self._h, int(n)), "lbm_step")
+
+    def sync(self):
+        self._check(self.L.lbm_sync(self._h), "lbm_sync")
+
+    @property
+    def step_count(self) -> int:
+        return int(self.L.lbm_step_count(self._h))
+
+    def fields(self, names: Iterable[str] = ("phi", "T", "ux", "uy", "p")) -> Dict[str, np.ndarray]:
+        names = list(names)
+        mask = 0
+        for n in names:
+            mask |= 1 << FIELD_BITS[n]
+        order = sorted(names, key=lambda n: FIELD_BITS[n])
+        outs = [np.empty(self.N, dtype=np.float64) for _ in order]
+        arr = (C.POINTER(C.c_double) * len(outs))(*[_dptr(o) for o in outs])
+        self._check(self.L.lbm_fields(self._h, mask, arr), "lbm_fields")
+        return {n: o.reshape(self.ny, self.nx) for n, o in zip(order, outs)}
+
+    def fields_device(self, names: Iterable[str]) -> Dict[str, "object"]:
+        torch = self.torch
+        names = list(names)
+        mask = 0
+        for n in names:
+            mask |= 1 << FIELD_BITS[n]
+        order = sorted(names, key=lambda n: FIELD_BITS[n])
+        outs = [torch.empty(self.N, dtype=torch.float32, device=self.device) for _ in order]
+        arr = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        self._check(self.L.lbm_fields_device(self._h, mask, arr), "lbm_fields_device")
+        return {n: o.view(self.ny, self.nx) for n, o in zip(order, outs)}
+
+    def diag(self) -> Dict[str, float]:
+        d = Diag()
+        rc = self.L.lbm_diag(self._h, C.byref(d))
+        if rc not in (LBM_OK, LBM_ENONFINITE):
+            self._check(rc, "lbm_diag")
+        out = {name: getattr(d, name) for name, _ in Diag._fields_}
+        out["rc"] = rc
+        return out
+
+    def pops(self, lattice: str) -> np.ndarray:
+        out = np.empty(9 * self.N, dtype=np.float64)
+        self._check(self.L.lbm_pops(self._h, {"g": 0, "f": 1, "h": 2}[lattice], _dptr(out)), "lbm_pops")
+        return out.reshape(9, self.ny, self.nx)
+
+    def save(self) -> bytes:
+        n = self.L.lbm_state_bytes(self._h)
+        buf = C.create_string_buffer(n)
+        self._check(self.L.lbm_save(self._h, buf, n), "lbm_save")
+        return buf.raw
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(self.L.lbm_load(self._h, buf, len(blob)), "lbm_load")

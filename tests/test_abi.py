@@ -1,0 +1,48 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/lbm.h declares, and validates parameters without touching a GPU."""
+import os
+import re
+
+import pytest
+
+from paper_2403_16122_amd import lbm, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(lbm_[a-z_]+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("lbm_init", "lbm_step", "lbm_fields", "lbm_diag", "lbm_save", "lbm_load", "lbm_destroy"):
+        assert n in names
+    assert sorted(lbm.EXPORTED) == names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.load_library()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_workspace_size_and_validation():
+    p = W.default_params(128, 64)
+    n = lbm.workspace_bytes(p)
+    plane = (128 * 64 + 63) // 64 * 64
+    assert n >= (2 * 27 + 8 + 10) * plane * 4
+    for over in (dict(nx=2), dict(M=-1.0), dict(mu_l=0.0), dict(theta_bottom_deg=180.0),
+                 dict(latent=0.0), dict(storage=7), dict(k_g=float("inf"))):
+        q = dict(p, **over)
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.workspace_bytes(q)
+        assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_strerror_names_every_code():
+    L = lbm.load_library()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.lbm_strerror(code).decode() != "unknown error"

@@ -1,0 +1,255 @@
+"""GPU (HIP, FP32) vs FP64 oracle parity, through the C ABI.
+
+Tolerances.  The target for the 128x64 sessile droplet after 1000 steps is
+max|d phi| <= 1e-5, max|d T| <= 1e-5 and a relative L2 of u <= 1e-4.  The
+other cases use the same bounds; pressure, which is not in that list, is
+held to a relative L2 of 1e-3 of its own scale (it is ~1e-4 in absolute
+terms, so FP32 rounding of the 27 populations shows up relatively larger).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2403_16122_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi", "T", "ux", "uy", "p", "fs", "rho")
+
+
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_16122_amd import lbm
+
+    return lbm
+
+
+def relL2(a, b):
+    den = math.sqrt(float(np.sum(b * b)))
+    return math.sqrt(float(np.sum((a - b) ** 2))) / max(den, 1e-300)
+
+
+def compare(g, o, tag, phi_tol=1e-5, T_tol=1e-5, u_tol=1e-4, p_tol=1e-3):
+    dphi = np.abs(g["phi"] - o["phi"]).max()
+    dT = np.abs(g["T"] - o["T"]).max()
+    eu = relL2(np.stack([g["ux"], g["uy"]]), np.stack([o["ux"], o["uy"]]))
+    ep = relL2(g["p"], o["p"])
+    print(f"[{tag}] max|dphi|={dphi:.3e} max|dT|={dT:.3e} relL2(u)={eu:.3e} relL2(p)={ep:.3e}", flush=True)
+    assert dphi <= phi_tol, (tag, dphi)
+    assert dT <= T_tol, (tag, dT)
+    assert eu <= u_tol, (tag, eu)
+    assert ep <= p_tol, (tag, ep)
+
+
+def run_pair(oracle_mod, p, phi0, T0, steps, tile="64x4", xcd=True):
+    lbm = _gpu()
+    print(f"case nx={p['nx']} ny={p['ny']} steps={steps} tile={tile} xcd={xcd}", flush=True)
+    g = lbm.Solver(p, phi0, T0)
+    g.set_launch(tile, xcd)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    g.step(steps)
+    o.step(steps)
+    return g, o
+
+
+def test_sessile128_1000_steps(oracle_mod):
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    g, o = run_pair(oracle_mod, p, phi0, T0, 1000)
+    compare(g.fields(FIELDS), o.fields(FIELDS), "sessile128/1000")
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_sessile128_other_seeds_early(oracle_mod, seed):
+    p, phi0, T0, _ = W.workload("sessile128", seed=seed)
+    g, o = run_pair(oracle_mod, p, phi0, T0, 100)
+    compare(g.fields(FIELDS), o.fields(FIELDS), f"sessile128/seed{seed}/100")
+
+
+@pytest.mark.parametrize("seed,steps", [(1, 500), (2, 500), (0, 2000)])
+def test_within_the_methods_own_sensitivity(oracle_mod, seed, steps):
+    """Later in these runs the frozen rows develop order-parameter dips in
+    which the sharpening flux lambda*n switches direction at extrema, so the
+    method itself amplifies any perturbation.  The envelope is measured, not
+    assumed: the oracle against itself with the initial phi perturbed by
+    1e-7 (one FP32 ulp of an O(1) value, the rounding the FP32 path makes in
+    rho, tau_f and f_s every step), largest of two draws.  The GPU must stay
+    inside it."""
+    p, phi0, T0, _ = W.workload("sessile128", seed=seed)
+    g, o = run_pair(oracle_mod, p, phi0, T0, steps)
+    fg, fo = g.fields(FIELDS), o.fields(FIELDS)
+    env_phi, env_T, env_u = 1e-5, 1e-5, 1e-4
+    for draw in range(2):
+        z = np.random.default_rng(1000 + 10 * seed + draw).standard_normal(phi0.size)
+        o2 = oracle_mod.OracleSolver(p, phi0 + 1e-7 * z, T0)
+        o2.step(steps)
+        f2 = o2.fields(FIELDS)
+        env_phi = max(env_phi, np.abs(f2["phi"] - fo["phi"]).max())
+        env_T = max(env_T, np.abs(f2["T"] - fo["T"]).max())
+        env_u = max(env_u, relL2(np.stack([f2["ux"], f2["uy"]]), np.stack([fo["ux"], fo["uy"]])))
+    compare(fg, fo, f"sessile128/seed{seed}/{steps} (envelope phi {env_phi:.1e} T {env_T:.1e} u {env_u:.1e})",
+            phi_tol=env_phi, T_tol=env_T, u_tol=env_u, p_tol=max(1e-3, 10 * env_u))
+
+
+@pytest.mark.parametrize("nx,ny,tile", [(70, 13, "64x4"), (70, 13, "32x8"), (130, 19, "64x8"),
+                                        (3, 3, "64x4"), (5, 4, "32x8"), (67, 9, "64x4")])
+def test_ragged_and_tiny_grids(oracle_mod, nx, ny, tile):
+    p = W.default_params(nx, ny, rho_s=0.88, theta_bottom_deg=65.0, theta_top_deg=115.0,
+                         gx=2e-6, gy=-5e-6, cp_s=0.7, k_s=0.2, cp_g=0.9, k_g=0.05)
+    R = max(1.5, min(nx, ny) / 2.5)
+    phi0 = W.sessile_droplet(nx, ny, R, 90.0, min(4.0, max(1.5, R / 2)), x0=nx / 2.0 + 0.3)
+    T0 = W.temperature_noise(nx, ny, p["T_melt"], 1e-3, 4)
+    g, o = run_pair(oracle_mod, p, phi0, T0, 200, tile=tile)
+    compare(g.fields(FIELDS), o.fields(FIELDS), f"ragged {nx}x{ny} {tile}")
+
+
+def test_bubble_case_with_boussinesq(oracle_mod):
+    nx, ny = 96, 64
+    p = W.default_params(nx, ny, rho_s=0.9, st_solid_mask=1, gy=-1e-6, bq_beta=0.05, bq_rho0=1.0,
+                         bq_Tref=1.0, theta_bottom_deg=75.0)
+    phi0 = W.droplet_with_bubbles(nx, ny, 28.0, 75.0, 4.0, [(40.0, 10.0, 4.0), (56.0, 18.0, 5.0)])
+    T0 = W.temperature_noise(nx, ny, p["T_melt"], 1e-3, 9)
+    g, o = run_pair(oracle_mod, p, phi0, T0, 400)
+    compare(g.fields(FIELDS), o.fields(FIELDS), "bubbles+boussinesq")
+
+
+def test_tile_shapes_and_xcd_mapping_are_bitwise_identical():
+    lbm = _gpu()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    ref = None
+    for tile in ("64x4", "32x8", "64x8"):
+        for xcd in (True, False):
+            print(f"tile={tile} xcd={xcd}", flush=True)
+            g = lbm.Solver(p, phi0, T0)
+            g.set_launch(tile, xcd)
+            g.step(100)
+            f = g.fields(FIELDS)
+            if ref is None:
+                ref = f
+            else:
+                for k in FIELDS:
+                    assert np.array_equal(f[k], ref[k]), (tile, xcd, k)
+
+
+@pytest.mark.parametrize("name,steps", [("sessile512", 20), ("bubbles1024", 6)])
+def test_full_size_workloads(oracle_mod, name, steps):
+    p, phi0, T0, _ = W.workload(name, seed=0)
+    g, o = run_pair(oracle_mod, p, phi0, T0, steps)
+    compare(g.fields(FIELDS), o.fields(FIELDS), f"{name}/{steps}")
+
+
+def test_diagnostics_match_oracle(oracle_mod):
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    g, o = run_pair(oracle_mod, p, phi0, T0, 300)
+    dg, do = g.diag(), o.diag()
+    assert dg["rc"] == 0 and dg["nonfinite"] == 0 and dg["step"] == 300
+    for k in ("sum_phi", "sum_phic", "sum_solid", "sum_liquid", "sum_H"):
+        assert abs(dg[k] - do[k]) <= 2e-6 * max(1.0, abs(do[k])), (k, dg[k], do[k])
+    assert abs(dg["max_u"] - do["max_u"]) <= 1e-4 * do["max_u"]
+    assert abs(dg["h_c"] - do["h_c"]) <= 1e-4
+
+
+def test_sum_phi_conserved_on_gpu():
+    lbm = _gpu()
+    nx, ny = 96, 48
+    p = W.default_params(nx, ny, rho_s=1.0, theta_bottom_deg=60.0)
+    phi0 = W.sessile_droplet(nx, ny, 14.0, 90.0, 4.0)
+    g = lbm.Solver(p, phi0, W.temperature_noise(nx, ny, 1.0, 1e-3, 1))
+    s0 = g.diag()["sum_phi"]
+    g.step(2000)
+    d = g.diag()
+    # FP32 populations: each step rounds 9 values per node (~6e-8 relative)
+    assert abs(d["sum_phi"] - s0) < 2e-5 * s0
+    assert d["sum_solid"] > 1.0
+
+
+def test_checkpoint_roundtrip_bitwise():
+    lbm = _gpu()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    a = lbm.Solver(p, phi0, T0)
+    a.step(60)
+    b = lbm.Solver(p, phi0, T0)
+    b.step(30)
+    blob = b.save()
+    c = lbm.Solver(p, np.zeros_like(phi0), np.ones_like(T0))
+    c.load(blob)
+    assert c.step_count == 30
+    c.step(30)
+    fa, fc = a.fields(FIELDS), c.fields(FIELDS)
+    for k in FIELDS:
+        assert np.array_equal(fa[k], fc[k]), k
+
+
+def test_populations_match_oracle(oracle_mod):
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    g, o = run_pair(oracle_mod, p, phi0, T0, 50)
+    for lat, tol in (("g", 1e-6), ("f", 1e-7), ("h", 2e-6)):
+        d = np.abs(g.pops(lat) - o.pops(lat)).max()
+        print(f"pops {lat}: max abs diff {d:.3e}", flush=True)
+        assert d < tol, (lat, d)
+
+
+WT = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+ORACLE_MAGIC = 0x4F52434C4250484C
+
+
+def gpu_state_as_oracle_checkpoint(blob, p):
+    """Re-express a GPU checkpoint (FP32; g stored as g_i - w_i phi_ref with
+    phi_ref in the last plane; h relative to the liquid reference state and
+    its rest population relative to L f_s^H) as the oracle's FP64
+    checkpoint of the same state."""
+    N = p["nx"] * p["ny"]
+    step = np.frombuffer(blob[:32], dtype=np.int64)[3]
+    a = np.frombuffer(blob[32:], dtype=np.float32).astype(np.float64).reshape(33, N).copy()
+    a[:9] += WT[:, None] * a[32][None, :]
+    Tm, cpr, L = p["T_melt"], p["cp_ref"], p["latent"]
+    a[18] += (cpr * Tm + L) - cpr * Tm + WT[0] * cpr * Tm - L * a[29]
+    for i in range(1, 9):
+        a[18 + i] += WT[i] * cpr * Tm
+    return np.array([ORACLE_MAGIC, p["nx"], p["ny"], step], dtype=np.int64).tobytes() + a[:32].tobytes()
+
+
+@pytest.mark.parametrize("name,steps", [("sessile128", 0), ("sessile128", 700), ("sessile512", 40)])
+def test_one_step_from_identical_state(oracle_mod, name, steps):
+    """From the very same state (the GPU's, loaded into the oracle) one step
+    of each must agree to FP32 rounding of O(1) populations, everywhere."""
+    lbm = _gpu()
+    p, phi0, T0, _ = W.workload(name, seed=0)
+    g = lbm.Solver(p, phi0, T0)
+    g.step(steps)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    o.load(gpu_state_as_oracle_checkpoint(g.save(), p))
+    g.step(1)
+    o.step(1)
+    for lat, tol in (("g", 5e-7), ("f", 5e-8), ("h", 5e-7)):
+        d = np.abs(g.pops(lat) - o.pops(lat)).max()
+        print(f"{name}@{steps}+1 pops {lat}: {d:.2e}", flush=True)
+        assert d < tol, (lat, d)
+    fg, fo = g.fields(FIELDS), o.fields(FIELDS)
+    umax = max(np.abs(fo["ux"]).max(), np.abs(fo["uy"]).max())
+    for k, tol in (("phi", 1e-6), ("T", 1e-6), ("ux", 1e-4 * umax), ("uy", 1e-4 * umax), ("p", 1e-8)):
+        assert np.abs(fg[k] - fo[k]).max() < tol, k
+
+
+def test_nonfinite_is_reported():
+    lbm = _gpu()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    g = lbm.Solver(p, phi0, T0)
+    blob = bytearray(g.save())
+    # poison the first g population of node 100 (header is 4 int64)
+    off = 32 + 4 * 100
+    blob[off:off + 4] = np.array([np.nan], dtype=np.float32).tobytes()
+    g.load(bytes(blob))
+    d = g.diag()
+    assert d["rc"] == lbm.LBM_ENONFINITE and d["nonfinite"] == 1
+
+
+def test_invalid_parameters_rejected_at_init():
+    lbm = _gpu()
+    p = W.default_params(16, 8, M=0.0)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Solver(p, np.zeros(128), np.ones(128))
+    assert e.value.code == lbm.LBM_EINVAL
