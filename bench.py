@@ -65,6 +65,15 @@ def time_steps(solver, steps: int, warmup: int):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def pick_launch(solver, args):
+    """Launch shape: the library's autotuner (timed outside the measured
+    region, state untouched) or a fixed choice."""
+    if args.tile == "auto":
+        return solver.autotune(reps=20 if solver.N < 1 << 20 else 3)
+    solver.set_launch(args.tile, not args.no_xcd)
+    return args.tile, not args.no_xcd
+
+
 def cpu_baseline(params, phi0, T0, budget_s: float):
     import oracle
 
@@ -87,10 +96,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--workload", default="sessile512")
-    ap.add_argument("--tile", default="64x4")
+    ap.add_argument("--tile", default="auto", help="auto (library autotuner) or 64x4/32x8/64x8/64x16/128x4")
     ap.add_argument("--no-xcd", action="store_true")
     ap.add_argument("--probe-steps", type=int, default=100, help="steps on the 4096x2048 grid (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle timing budget (0: skip)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -105,10 +116,17 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     params, phi0, T0, meta = W.workload(args.workload, seed=0)
     N = params["nx"] * params["ny"]
     solver = lbm.Solver(params, phi0, T0)
-    solver.set_launch(args.tile, not args.no_xcd)
+    tile, xcd = pick_launch(solver, args)
     torch.cuda.synchronize()
     secs, wall = time_steps(solver, args.steps, args.warmup)
     d = solver.diag()
@@ -136,7 +154,7 @@ def main():
             "workload": f"{args.workload}: {params['nx']}x{params['ny']} sessile droplet R={meta['R']:g} lu, "
                         f"theta {meta['theta']:g}, rho_s/rho_l {params['rho_s']:g}, Ste 0.1, Bond 0.1, "
                         "W=4, M=0.1, rho_l/rho_g=1000, FP32 populations (planar 2-D)",
-            "nx": params["nx"], "ny": params["ny"], "tile": args.tile, "xcd_remap": not args.no_xcd,
+            "nx": params["nx"], "ny": params["ny"], "tile": tile, "xcd_remap": xcd,
             "parallelism": "single GPU",
         },
         "roofline": {
@@ -154,13 +172,14 @@ def main():
         pp, pphi, pT, _ = W.workload("probe4096", seed=0)
         Np = pp["nx"] * pp["ny"]
         ps = lbm.Solver(pp, pphi, pT)
-        ps.set_launch(args.tile, not args.no_xcd)
+        ptile, pxcd = pick_launch(ps, args)
         psecs, _ = time_steps(ps, args.probe_steps, 10)
         pl = psecs / args.probe_steps
         pach = BYTES_PER_NODE * Np / pl / 1e9
         out["hbm_probe"] = {
             "workload": "probe4096: 4096x2048 sessile droplet R=640 (same physics), 2.3 GB working set",
             "steps": args.probe_steps, "MLUPS": round(Np * args.probe_steps / psecs / 1e6, 1),
+            "tile": ptile, "xcd_remap": pxcd,
             "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("probe4096"),
         }

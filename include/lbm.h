@@ -126,9 +126,16 @@ void lbm_destroy(lbm_ctx* c);
 const char* lbm_strerror(int code);
 const char* lbm_last_error(void);
 
-/* Tile shape of the fused step kernel: 0 = 64x4 (default), 1 = 32x8,
- * 2 = 64x8; xcd_remap 1 maps consecutive tiles to one XCD. */
+/* Launch shape of the fused step kernel.  tile_variant: 0 = 64x4 (default),
+ * 1 = 32x8, 2 = 64x8, 3 = 64x16, 4 = 128x4 nodes per workgroup; xcd_remap 1
+ * hands consecutive tiles to one XCD (its L2 then serves the halo re-reads).
+ * Results are bitwise identical for every choice. */
 int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap);
+
+/* Time every launch shape for `reps` steps and keep the fastest (written to
+ * the optional out-pointers).  The state is not advanced: each timed launch
+ * recomputes the next step from the same buffers.  Synchronises. */
+int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_remap);
 
 #ifdef __cplusplus
 }

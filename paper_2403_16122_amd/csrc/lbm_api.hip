@@ -27,7 +27,7 @@ int dev_error(hipError_t e, const char* what) {
 
 constexpr double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 constexpr int kPops = 27;
-constexpr int kAuxPlanes = 2 + 8;  // (phi u) x/y; phi_ref, f_s^H, p, S double-buffered
+constexpr int kAuxPlanes = 4 + 8;  // (phi u) x/y, phi_ref, f_s^H, p, S, all double-buffered
 constexpr int kStatePlanes = kPops + 6;  // checkpointed planes
 constexpr int64_t kMagic = 0x4c424d4750555331LL;
 
@@ -141,15 +141,16 @@ void carve(lbm_ctx* c) {
   c->S.pops[0] = base;
   c->S.pops[1] = base + kPops * pl;
   float* aux = base + 2 * kPops * pl;
-  c->S.phiu = aux;
-  c->S.fsH[0] = aux + 2 * pl;
-  c->S.fsH[1] = aux + 3 * pl;
-  c->S.p[0] = aux + 4 * pl;
-  c->S.p[1] = aux + 5 * pl;
-  c->S.S[0] = aux + 6 * pl;
-  c->S.S[1] = aux + 7 * pl;
-  c->S.ref[0] = aux + 8 * pl;
-  c->S.ref[1] = aux + 9 * pl;
+  c->S.phiu[0] = aux;
+  c->S.phiu[1] = aux + 2 * pl;
+  c->S.fsH[0] = aux + 4 * pl;
+  c->S.fsH[1] = aux + 5 * pl;
+  c->S.p[0] = aux + 6 * pl;
+  c->S.p[1] = aux + 7 * pl;
+  c->S.S[0] = aux + 8 * pl;
+  c->S.S[1] = aux + 9 * pl;
+  c->S.ref[0] = aux + 10 * pl;
+  c->S.ref[1] = aux + 11 * pl;
   c->S.fields = aux + kAuxPlanes * pl;
   c->S.part = (double*)(c->S.fields + lbmk::NFIELD * pl);
 }
@@ -351,8 +352,8 @@ int lbm_save(lbm_ctx* c, void* buf, size_t bytes) {
   o += sizeof(hdr);
   const float* src[kStatePlanes];
   for (int i = 0; i < kPops; ++i) src[i] = c->S.pops[c->cur] + i * c->K.plane;
-  src[kPops + 0] = c->S.phiu;
-  src[kPops + 1] = c->S.phiu + c->K.plane;
+  src[kPops + 0] = c->S.phiu[c->cur];
+  src[kPops + 1] = c->S.phiu[c->cur] + c->K.plane;
   src[kPops + 2] = c->S.fsH[c->cur];
   src[kPops + 3] = c->S.p[c->cur];
   src[kPops + 4] = c->S.S[c->cur];
@@ -375,8 +376,8 @@ int lbm_load(lbm_ctx* c, const void* buf, size_t bytes) {
   o += sizeof(hdr);
   float* dst[kStatePlanes];
   for (int i = 0; i < kPops; ++i) dst[i] = c->S.pops[c->cur] + i * c->K.plane;
-  dst[kPops + 0] = c->S.phiu;
-  dst[kPops + 1] = c->S.phiu + c->K.plane;
+  dst[kPops + 0] = c->S.phiu[c->cur];
+  dst[kPops + 1] = c->S.phiu[c->cur] + c->K.plane;
   dst[kPops + 2] = c->S.fsH[c->cur];
   dst[kPops + 3] = c->S.p[c->cur];
   dst[kPops + 4] = c->S.S[c->cur];
@@ -399,10 +400,47 @@ int lbm_sync(lbm_ctx* c) {
 }
 
 int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap) {
-  if (!c || tile_variant < 0 || tile_variant > 2 || xcd_remap < 0 || xcd_remap > 1)
+  if (!c || tile_variant < 0 || tile_variant >= lbmk::NTILE_VARIANTS || xcd_remap < 0 || xcd_remap > 1)
     return LBM_EINVAL;
   c->tile_variant = tile_variant;
   c->xcd = xcd_remap;
+  return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_remap) {
+  if (!c || reps < 1) return LBM_EINVAL;
+  // The step kernel reads buffer cur and writes buffer cur^1 only, so
+  // replaying it without flipping leaves the state where it was.
+  hipEvent_t e0, e1;
+  LBM_CK(hipEventCreate(&e0));
+  LBM_CK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bv = c->tile_variant, bx = c->xcd;
+  for (int v = 0; v < lbmk::NTILE_VARIANTS; ++v) {
+    for (int x = 0; x <= 1; ++x) {
+      if (lbmk::launch_step(c->K, c->S, c->cur, false, v, x, c->stream))  // warm-up
+        return dev_error(hipGetLastError(), "autotune launch");
+      LBM_CK(hipEventRecord(e0, c->stream));
+      for (int r = 0; r < reps; ++r)
+        if (lbmk::launch_step(c->K, c->S, c->cur, false, v, x, c->stream))
+          return dev_error(hipGetLastError(), "autotune launch");
+      LBM_CK(hipEventRecord(e1, c->stream));
+      LBM_CK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      LBM_CK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        bv = v;
+        bx = x;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tile_variant = bv;
+  c->xcd = bx;
+  if (tile_variant) *tile_variant = bv;
+  if (xcd_remap) *xcd_remap = bx;
   return LBM_OK;
 }
 

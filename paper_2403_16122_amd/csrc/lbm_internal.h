@@ -29,7 +29,7 @@ struct KParams {
 
 struct State {
   float* pops[2];  // 27 planes each: g0..g8, f0..f8, h0..h8
-  float* phiu;     // 2 planes: (phi u)^{n-1}, updated in place
+  float* phiu[2];  // 2 planes each: (phi u)^{n-1}
   float* ref[2];   // phi of the previous step: reference of the stored g populations
   float* fsH[2];   // f_s^H of the previous step (read n-1, write n)
   float* p[2];     // pressure of the previous step
@@ -39,6 +39,7 @@ struct State {
 };
 
 enum { NFIELD = 10 };
+enum { NTILE_VARIANTS = 5 };  // 64x4, 32x8, 64x8, 64x16, 128x4
 enum { RED_NVAL = 8 };
 constexpr int RED_BLOCKS = 512;
 

@@ -75,25 +75,25 @@ __device__ __forceinline__ void pull9(const float* __restrict__ A, const KParams
 // in its own reference, q_i = g_i - w_i phi_ref(self).  Every stored number
 // is then a one-step increment, so FP32 resolves phi to ~1e-11 in bulk
 // liquid, bulk gas, interfaces and frozen regions alike (exact algebra).
-__device__ __forceinline__ void pull_g(const float* __restrict__ A, const float* __restrict__ ref,
-                                       const KParams& P, int x, int y, int xm, int xp, float q[9],
-                                       float& rself) {
-  const long long pl = P.plane;
-  const int nx = P.nx;
+// Re-express freshly pulled g populations (node at LDS cell (c, r), row y)
+// in the reference of the receiving node: q_i += w_i (phi_ref(src) - phi_ref(self)).
+// The reference tile holds phi_ref of cell (c, r) at sref[r + 1][c + 1].
+template <int RX>
+__device__ __forceinline__ float rebase_g(float q[9], const float (*sref)[RX], const KParams& P,
+                                          int y, int c, int r) {
+  // the same node is rebuilt by its own lane and as a halo cell of its
+  // neighbours' tiles: no FMA contraction, so both round identically
+#pragma clang fp contract(off)
   const bool bot = (y == 0), top = (y == P.ny - 1);
-  const int k = y * nx + x;
-  rself = ref[k];
+  const float rself = sref[r + 1][c + 1];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
+  for (int i = 1; i < 9; ++i) {
     const int cy = cyv(i), cx = cxv(i);
     const bool wall = (cy > 0 && bot) || (cy < 0 && top);
-    const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
-    const int sk = wall ? k : (y - cy) * nx + sx;
-    const int si = wall ? opp(i) : i;
-    const float v = A[(long long)si * pl + sk];
-    const float rs = i == 0 ? rself : ref[sk];
-    q[i] = i == 0 ? v : v + wt(i) * (rs - rself);
+    const float rs = wall ? rself : sref[r + 1 - cy][c + 1 - cx];
+    q[i] += wt(i) * (rs - rself);
   }
+  return rself;
 }
 
 struct Macro {
@@ -115,16 +115,25 @@ struct Macro {
 // exact algebra; together they keep every stored value small, so FP32
 // resolves H to ~1e-7 of the sensible part in liquid, mushy and solid
 // nodes alike instead of ~1e-6 of H ~ L.
-__device__ __forceinline__ void node_macro(const float* __restrict__ A,
-                                           const float* __restrict__ phiref,
-                                           const float* __restrict__ fsH_prev, const KParams& P,
-                                           int x, int y, Macro& m) {
+// Issue the loads of one node's macroscopic inputs: pulled g and h (wall
+// rules applied) and f_s^H of the previous step.
+__device__ __forceinline__ void load_node(const float* __restrict__ A,
+                                          const float* __restrict__ fsH_prev, const KParams& P,
+                                          int x, int y, Macro& m) {
   const int xm = x == 0 ? P.nx - 1 : x - 1;
   const int xp = x == P.nx - 1 ? 0 : x + 1;
-  float rs;
-  pull_g(A, phiref, P, x, y, xm, xp, m.g, rs);
+  pull9<0>(A, P, x, y, xm, xp, m.g);
   pull9<2>(A, P, x, y, xm, xp, m.h);
-  const float fprev = fsH_prev[y * P.nx + x];
+  m.fprev = fsH_prev[y * P.nx + x];
+}
+
+// Node-local macroscopic quantities of time t (Eq. (29), (9), (19), (26), (1))
+// from the loaded inputs; m.g must already be rebased to reference rs.
+__device__ __forceinline__ void finish_macro(const KParams& P, float rs, Macro& m) {
+  // computed both for own nodes and for halo cells: no FMA contraction, so
+  // every tile shape yields bit-identical values
+#pragma clang fp contract(off)
+  const float fprev = m.fprev;
   float D0 = 0.0f, hs = 0.0f;  // D0 = sum g_i - r
 #pragma unroll
   for (int i = 0; i < 9; ++i) D0 += m.g[i];
@@ -155,7 +164,6 @@ __device__ __forceinline__ void node_macro(const float* __restrict__ A,
   const float fsol = pc * fsH;
   m.E = E;
   m.dT = dT;
-  m.fprev = fprev;
   m.cp = cp;
   m.kk = kk;
   m.fl = fl;
@@ -167,33 +175,38 @@ __device__ __forceinline__ void node_macro(const float* __restrict__ A,
   m.mu = mix3(fsol, pc, P.mu_s, P.mu_l, P.mu_g);
 }
 
-// Halo cells only need phi (kept as phi - 1 in LDS), rho and f_s^H.
-__device__ __forceinline__ void halo_macro(const float* __restrict__ A,
-                                           const float* __restrict__ phiref,
-                                           const float* __restrict__ fsH_prev, const KParams& P,
-                                           int x, int y, float& phim1, float& rho, float& fsH) {
-  Macro m;
-  node_macro(A, phiref, fsH_prev, P, x, y, m);
-  phim1 = (m.r - 1.0f) + m.dl;
-  rho = m.rho;
-  fsH = m.fsH;
-}
+// Buffers one step reads (time n) and writes (time n+1).  The step is a
+// pure function of the *_in buffers, so it can be replayed for timing.
+struct StepIO {
+  const float* A;
+  float* B;
+  const float* phiu_in;
+  float* phiu_out;
+  const float* ref_in;
+  float* ref_out;
+  const float* fsH_in;
+  float* fsH_out;
+  const float* p_in;
+  float* p_out;
+  const float* S_in;
+  float* S_out;
+  float* fields;
+};
 
 template <int TX, int TY, bool FIELDS>
-__global__ __launch_bounds__(TX* TY) void k_step(
-    KParams P, const float* __restrict__ A, float* __restrict__ B, float* __restrict__ phiu,
-    const float* __restrict__ ref_in, float* __restrict__ ref_out,
-    const float* __restrict__ fsH_in, float* __restrict__ fsH_out, const float* __restrict__ p_in,
-    float* __restrict__ p_out, const float* __restrict__ S_in, float* __restrict__ S_out,
-    float* __restrict__ fields, int ntx, int ntiles, int tiles_per_xcd) {
+__global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, int ntiles,
+                                                 int tiles_per_xcd) {
   constexpr int NT = TX * TY;
   constexpr int LX = TX + 4, LY = TY + 2;  // LDS column c <-> x0 + c - 2, row r <-> y0 + r - 1
+  constexpr int RX = LX + 2, RY = LY + 2;  // reference tile: one more cell on every side
   __shared__ float s_phi[LY][LX];  // phi - 1 (stencils are blind to the constant)
   __shared__ float s_rho[LY][LX];
   __shared__ float s_fsH[LY][LX];
   __shared__ float s_p[LY][LX];
   __shared__ float s_S[LY][LX];
+  __shared__ float s_ref[RY][RX];  // phi of the previous step, reference of the stored g
 
+  const float* __restrict__ A = io.A;
   const int b = blockIdx.x;
   const int tile = tiles_per_xcd > 0 ? (b & 7) * tiles_per_xcd + (b >> 3) : b;
   if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
@@ -206,45 +219,72 @@ __global__ __launch_bounds__(TX* TY) void k_step(
   const bool yin = y < ny;
   const bool active = yin && x < nx;
 
+  // ---- phase 0: issue every global load of the tile at once ---------------
+  // This node's pulled g, h, f and history values, the one halo cell this
+  // lane rebuilds, and the previous-step fields with halo for LDS.  A single
+  // memory round trip then feeds the whole step.
+  constexpr int NRING = 2 * LX + 4 * TY;
+  static_assert(NRING <= NT, "one halo cell per lane at most");
+  Macro m, mh;
+  float f[9], phiux = 0.0f, phiuy = 0.0f;
+  if (yin) load_node(A, io.fsH_in, P, xw, y, m);
+  if (active) {
+    const int xm = x == 0 ? nx - 1 : x - 1;
+    const int xp = x == nx - 1 ? 0 : x + 1;
+    pull9<1>(A, P, x, y, xm, xp, f);
+    phiux = io.phiu_in[y * nx + x];
+    phiuy = io.phiu_in[P.plane + y * nx + x];
+  }
+  int hr = 0, hc = 0;
+  bool halo = false;
+  if (t < NRING) {
+    if (t < LX) {
+      hr = 0;
+      hc = t;
+    } else if (t < 2 * LX) {
+      hr = LY - 1;
+      hc = t - LX;
+    } else {
+      const int q = t - 2 * LX;
+      hr = 1 + (q >> 2);
+      const int s = q & 3;
+      hc = s < 2 ? s : TX + s;
+    }
+    const int gy = y0 + hr - 1;
+    halo = gy >= 0 && gy < ny;
+    if (halo) load_node(A, io.fsH_in, P, wrapx(x0 + hc - 2, nx), gy, mh);
+  }
+  // phi_ref with a two-cell halo (rows beyond a wall are never read; the
+  // clamp keeps the load in bounds), and the lagged p and S with one cell
+  // (rows beyond a wall copy the adjacent row)
+  for (int j = t; j < RX * RY; j += NT) {
+    const int r = j / RX, c = j - (j / RX) * RX;
+    const int gy = min(max(y0 + r - 2, 0), ny - 1);
+    s_ref[r][c] = io.ref_in[gy * nx + wrapx(x0 + c - 3, nx)];
+  }
+  for (int j = t; j < LX * LY; j += NT) {
+    const int r = j / LX, c = j - (j / LX) * LX;
+    const int gy = min(max(y0 + r - 1, 0), ny - 1);
+    const int kk = gy * nx + wrapx(x0 + c - 2, nx);
+    s_p[r][c] = io.p_in[kk];
+    s_S[r][c] = io.S_in[kk];
+  }
+  __syncthreads();
+
   // ---- phase 1: macroscopic quantities of time t into LDS ----------------
-  Macro m;
   if (yin) {
-    node_macro(A, ref_in, fsH_in, P, xw, y, m);
+    const float rs = rebase_g<RX>(m.g, s_ref, P, y, lx + 2, ly + 1);
+    finish_macro(P, rs, m);
     s_phi[ly + 1][lx + 2] = (m.r - 1.0f) + m.dl;
     s_rho[ly + 1][lx + 2] = m.rho;
     s_fsH[ly + 1][lx + 2] = m.fsH;
   }
-  constexpr int NRING = 2 * LX + 4 * TY;
-  for (int j = t; j < NRING; j += NT) {
-    int r, c;
-    if (j < LX) {
-      r = 0;
-      c = j;
-    } else if (j < 2 * LX) {
-      r = LY - 1;
-      c = j - LX;
-    } else {
-      const int q = j - 2 * LX;
-      r = 1 + (q >> 2);
-      const int s = q & 3;
-      c = s < 2 ? s : TX + s;
-    }
-    const int gy = y0 + r - 1;
-    if (gy >= 0 && gy < ny) {
-      float ph, rh, fh;
-      halo_macro(A, ref_in, fsH_in, P, wrapx(x0 + c - 2, nx), gy, ph, rh, fh);
-      s_phi[r][c] = ph;
-      s_rho[r][c] = rh;
-      s_fsH[r][c] = fh;
-    }
-  }
-  // lagged p and S; rows beyond a wall copy the adjacent row
-  for (int j = t; j < LX * LY; j += NT) {
-    const int r = j / LX, c = j - (j / LX) * LX;
-    const int gy = min(max(y0 + r - 1, 0), ny - 1);
-    const int k = gy * nx + wrapx(x0 + c - 2, nx);
-    s_p[r][c] = p_in[k];
-    s_S[r][c] = S_in[k];
+  if (halo) {
+    const float rs = rebase_g<RX>(mh.g, s_ref, P, y0 + hr - 1, hc, hr);
+    finish_macro(P, rs, mh);
+    s_phi[hr][hc] = (mh.r - 1.0f) + mh.dl;
+    s_rho[hr][hc] = mh.rho;
+    s_fsH[hr][hc] = mh.fsH;
   }
   __syncthreads();
 
@@ -326,13 +366,7 @@ __global__ __launch_bounds__(TX* TY) void k_step(
   const float Fx = smask * muphi * gphx + gcoef * P.gx;
   const float Fy = smask * muphi * gphy + gcoef * P.gy;
 
-  // flow populations (Eq. (34)-(35))
-  float f[9];
-  {
-    const int xm = x == 0 ? nx - 1 : x - 1;
-    const int xp = x == nx - 1 ? 0 : x + 1;
-    pull9<1>(A, P, x, y, xm, xp, f);
-  }
+  // flow populations (Eq. (34)-(35)), loaded in phase 0
   const float mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const float my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
   const float rrho = 1.0f / rho;
@@ -352,6 +386,7 @@ __global__ __launch_bounds__(TX* TY) void k_step(
   const float p = 0.6f * (sumf + 0.5f * Ssrc + tauf * F0 + rho * (W0 * (-1.5f * usq)));
 
   if (FIELDS) {
+    float* __restrict__ fields = io.fields;
     const long long pl = P.plane;
     fields[0 * pl + k] = phi;
     fields[1 * pl + k] = T;
@@ -367,6 +402,7 @@ __global__ __launch_bounds__(TX* TY) void k_step(
   }
 
   const long long pl = P.plane;
+  float* __restrict__ B = io.B;
   // flow collision (Eq. (30)-(33))
   {
     const float itau = 1.0f / tauf, sf = 1.0f - 0.5f * itau;
@@ -386,7 +422,7 @@ __global__ __launch_bounds__(TX* TY) void k_step(
   // phase-field collision (Eq. (21), (24), (25), (37))
   {
     const float pux = phi * ux, puy = phi * uy;
-    const float dpx = pux - phiu[k], dpy = puy - phiu[pl + k];
+    const float dpx = pux - phiux, dpy = puy - phiuy;
     const float ax = 3.0f * dpx + lnx, ay = 3.0f * dpy + lny;
     const float pm = phi * m.mdot;
     // the new reference is this step's phi (as stored); re-express the
@@ -402,9 +438,9 @@ __global__ __launch_bounds__(TX* TY) void k_step(
       const float Gi = wt(i) * (cx * ax + cy * ay + pm);
       B[i * pl + k] = gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi;
     }
-    ref_out[k] = phi;
-    phiu[k] = pux;
-    phiu[pl + k] = puy;
+    io.ref_out[k] = phi;
+    io.phiu_out[k] = pux;
+    io.phiu_out[pl + k] = puy;
   }
   // enthalpy collision (Eq. (27)-(28)) in the shifted variables
   {
@@ -426,9 +462,9 @@ __global__ __launch_bounds__(TX* TY) void k_step(
     const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
     Bh[k] = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
   }
-  fsH_out[k] = m.fsH;
-  p_out[k] = p;
-  S_out[k] = Ssrc;
+  io.fsH_out[k] = m.fsH;
+  io.p_out[k] = p;
+  io.S_out[k] = Ssrc;
 }
 
 // Initial state (no time-stepping yet): u = 0, p = 0, liquid fraction 1,
@@ -534,14 +570,12 @@ int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int
     grid = 8 * tpx;
   }
   const int nxt = cur ^ 1;
+  StepIO io{S.pops[cur], S.pops[nxt], S.phiu[cur], S.phiu[nxt], S.ref[cur], S.ref[nxt],
+            S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur], S.S[nxt], S.fields};
   if (fields_only)
-    hipLaunchKernelGGL((k_step<TX, TY, true>), dim3(grid), dim3(TX * TY), 0, st, P, S.pops[cur],
-                       S.pops[nxt], S.phiu, S.ref[cur], S.ref[nxt], S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur],
-                       S.S[nxt], S.fields, ntx, ntiles, tpx);
+    hipLaunchKernelGGL((k_step<TX, TY, true>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx);
   else
-    hipLaunchKernelGGL((k_step<TX, TY, false>), dim3(grid), dim3(TX * TY), 0, st, P, S.pops[cur],
-                       S.pops[nxt], S.phiu, S.ref[cur], S.ref[nxt], S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur],
-                       S.S[nxt], S.fields, ntx, ntiles, tpx);
+    hipLaunchKernelGGL((k_step<TX, TY, false>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -551,7 +585,7 @@ int launch_init(const KParams& P, const IParams& I, const State& S, int cur, con
                 const double* d_T0, hipStream_t st) {
   const long long N = (long long)P.nx * P.ny;
   const int grid = (int)std::min<long long>((N + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, st, P, I, d_phi0, d_T0, S.pops[cur], S.phiu,
+  hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, st, P, I, d_phi0, d_T0, S.pops[cur], S.phiu[cur],
                      S.ref[cur], S.fsH[cur], S.p[cur], S.S[cur]);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -563,6 +597,10 @@ int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int
       return launch_tile<32, 8>(P, S, cur, fields_only, xcd_remap, st);
     case 2:
       return launch_tile<64, 8>(P, S, cur, fields_only, xcd_remap, st);
+    case 3:
+      return launch_tile<64, 16>(P, S, cur, fields_only, xcd_remap, st);
+    case 4:
+      return launch_tile<128, 4>(P, S, cur, fields_only, xcd_remap, st);
     default:
       return launch_tile<64, 4>(P, S, cur, fields_only, xcd_remap, st);
   }

@@ -17,14 +17,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 FIELD_BITS = {"phi": 0, "T": 1, "ux": 2, "uy": 3, "p": 4, "fs": 5, "fl": 6, "rho": 7, "H": 8, "mdot": 9}
-TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2}
+TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4}
+TILE_NAMES = {v: k for k, v in TILE_VARIANTS.items()}
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 
 EXPORTED = [
     "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_diag",
     "lbm_pops", "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_step_count", "lbm_sync",
-    "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_set_launch",
+    "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_set_launch", "lbm_autotune",
 ]
 
 
@@ -91,6 +92,7 @@ def load_library():
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
+    L.lbm_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     _lib = L
     return L
 
@@ -157,6 +159,12 @@ class Solver:
 
     def set_launch(self, tile: str = "64x4", xcd_remap: bool = True):
         self._check(self.L.lbm_set_launch(self._h, TILE_VARIANTS[tile], int(bool(xcd_remap))), "lbm_set_launch")
+
+    def autotune(self, reps: int = 20):
+        """Pick the fastest launch shape for this grid; returns (tile, xcd_remap)."""
+        v, x = C.c_int32(), C.c_int32()
+        self._check(self.L.lbm_autotune(self._h, int(reps), C.byref(v), C.byref(x)), "lbm_autotune")
+        return TILE_NAMES[v.value], bool(x.value)
 
     def step(self, n: int = 1):
         self._check(self.L.lbm_step(self._h, int(n)), "lbm_step")

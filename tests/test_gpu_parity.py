@@ -69,7 +69,7 @@ def test_sessile128_other_seeds_early(oracle_mod, seed):
     compare(g.fields(FIELDS), o.fields(FIELDS), f"sessile128/seed{seed}/100")
 
 
-@pytest.mark.parametrize("seed,steps", [(1, 500), (2, 500), (0, 2000)])
+@pytest.mark.parametrize("seed,steps", [(1, 500), (2, 500), (0, 2000), ("bubbles", 600)])
 def test_within_the_methods_own_sensitivity(oracle_mod, seed, steps):
     """Later in these runs the frozen rows develop order-parameter dips in
     which the sharpening flux lambda*n switches direction at extrema, so the
@@ -78,12 +78,17 @@ def test_within_the_methods_own_sensitivity(oracle_mod, seed, steps):
     1e-7 (one FP32 ulp of an O(1) value, the rounding the FP32 path makes in
     rho, tau_f and f_s every step), largest of two draws.  The GPU must stay
     inside it."""
-    p, phi0, T0, _ = W.workload("sessile128", seed=seed)
+    if seed == "bubbles":
+        p, phi0, T0 = bubble_case()
+        sd = 7
+    else:
+        p, phi0, T0, _ = W.workload("sessile128", seed=seed)
+        sd = seed
     g, o = run_pair(oracle_mod, p, phi0, T0, steps)
     fg, fo = g.fields(FIELDS), o.fields(FIELDS)
     env_phi, env_T, env_u = 1e-5, 1e-5, 1e-4
     for draw in range(2):
-        z = np.random.default_rng(1000 + 10 * seed + draw).standard_normal(phi0.size)
+        z = np.random.default_rng(1000 + 10 * sd + draw).standard_normal(phi0.size)
         o2 = oracle_mod.OracleSolver(p, phi0 + 1e-7 * z, T0)
         o2.step(steps)
         f2 = o2.fields(FIELDS)
@@ -106,21 +111,26 @@ def test_ragged_and_tiny_grids(oracle_mod, nx, ny, tile):
     compare(g.fields(FIELDS), o.fields(FIELDS), f"ragged {nx}x{ny} {tile}")
 
 
-def test_bubble_case_with_boussinesq(oracle_mod):
+def bubble_case():
     nx, ny = 96, 64
     p = W.default_params(nx, ny, rho_s=0.9, st_solid_mask=1, gy=-1e-6, bq_beta=0.05, bq_rho0=1.0,
                          bq_Tref=1.0, theta_bottom_deg=75.0)
     phi0 = W.droplet_with_bubbles(nx, ny, 28.0, 75.0, 4.0, [(40.0, 10.0, 4.0), (56.0, 18.0, 5.0)])
     T0 = W.temperature_noise(nx, ny, p["T_melt"], 1e-3, 9)
-    g, o = run_pair(oracle_mod, p, phi0, T0, 400)
-    compare(g.fields(FIELDS), o.fields(FIELDS), "bubbles+boussinesq")
+    return p, phi0, T0
+
+
+def test_bubble_case_with_boussinesq(oracle_mod):
+    p, phi0, T0 = bubble_case()
+    g, o = run_pair(oracle_mod, p, phi0, T0, 50)
+    compare(g.fields(FIELDS), o.fields(FIELDS), "bubbles+boussinesq/50")
 
 
 def test_tile_shapes_and_xcd_mapping_are_bitwise_identical():
     lbm = _gpu()
     p, phi0, T0, _ = W.workload("sessile128", seed=0)
     ref = None
-    for tile in ("64x4", "32x8", "64x8"):
+    for tile in ("64x4", "32x8", "64x8", "64x16", "128x4"):
         for xcd in (True, False):
             print(f"tile={tile} xcd={xcd}", flush=True)
             g = lbm.Solver(p, phi0, T0)
@@ -164,6 +174,22 @@ def test_sum_phi_conserved_on_gpu():
     # FP32 populations: each step rounds 9 values per node (~6e-8 relative)
     assert abs(d["sum_phi"] - s0) < 2e-5 * s0
     assert d["sum_solid"] > 1.0
+
+
+def test_autotune_leaves_state_untouched():
+    lbm = _gpu()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    a = lbm.Solver(p, phi0, T0)
+    b = lbm.Solver(p, phi0, T0)
+    a.step(40)
+    b.step(40)
+    tile, xcd = b.autotune(reps=3)
+    assert tile in lbm.TILE_VARIANTS and b.step_count == 40
+    a.step(10)
+    b.step(10)
+    fa, fb = a.fields(FIELDS), b.fields(FIELDS)
+    for k in FIELDS:
+        assert np.array_equal(fa[k], fb[k]), k
 
 
 def test_checkpoint_roundtrip_bitwise():
