@@ -39,7 +39,7 @@ struct State {
 };
 
 enum { NFIELD = 10 };
-enum { NTILE_VARIANTS = 5 };  // 64x4, 32x8, 64x8, 64x16, 128x4
+enum { NTILE_VARIANTS = 8 };  // tiles 64x4, 32x8, 64x8, 64x16, 128x4; strips 64x32, 64x64, 128x32
 enum { RED_NVAL = 8 };
 constexpr int RED_BLOCKS = 512;
 

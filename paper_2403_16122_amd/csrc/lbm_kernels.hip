@@ -193,6 +193,160 @@ struct StepIO {
   float* fields;
 };
 
+// Gradients and Laplacian of Eq. (38) at one node: phi (with its
+// Laplacian) and rho at time t, lagged p and S.
+struct Grads {
+  float phx, phy, lphi, rx, ry, px, py, Sx, Sy;
+};
+
+// 3 sum_{i>0} w_i c_i z_i and 6 sum_{i>0} w_i (z_i - z_0) over the 8 neighbours.
+__device__ __forceinline__ void stencil(float C, float E, float Wv, float N, float S, float NE,
+                                        float NW, float SW, float SE, float& gx, float& gy,
+                                        float* lap) {
+#pragma clang fp contract(off)
+  gx = (E - Wv) * (1.0f / 3.0f) + (NE - NW - SW + SE) * (1.0f / 12.0f);
+  gy = (N - S) * (1.0f / 3.0f) + (NE + NW - SW - SE) * (1.0f / 12.0f);
+  if (lap)
+    *lap = (E + N + Wv + S - 4.0f * C) * (2.0f / 3.0f) + (NE + NW + SW + SE - 4.0f * C) * (1.0f / 6.0f);
+}
+
+// Wetting ghost value (Eq. (39)-(41)) beyond a wall row: a0 = phi - 1 of
+// the adjacent row at columns c-1, c, c+1 and a1 the same for the next row;
+// returns phi - 1 of the ghost cell.
+__device__ __forceinline__ float wetting_ghost(float a0m, float a0c, float a0p, float a1m, float a1p,
+                                               float tv) {
+#pragma clang fp contract(off)
+  const float d0 = 0.5f * (a0p - a0m);
+  const float d1 = 0.5f * (a1p - a1m);
+  return a0c + tv * fabsf(1.5f * d0 - 0.5f * d1);
+}
+
+// Everything after the stencils for one node k: interface terms (Eq. (3),
+// (12), (13)), forces (Eq. (11)), flow macros (Eq. (34)-(36)) and the three
+// BGK collisions with their stores, or the output fields when FIELDS.
+template <bool FIELDS>
+__device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, const Macro& m,
+                                            const float f[9], float phiux, float phiuy,
+                                            const Grads& d, int k) {
+  const float phi = m.phi, rho = m.rho;
+  const float om = (1.0f - m.r) - m.dl;  // 1 - phi without cancellation in either bulk
+  // interface terms (Eq. (3), (12), (13))
+  const float lam = P.four_over_W * phi * om;
+  const float gn2 = d.phx * d.phx + d.phy * d.phy;
+  float lnx = 0.0f, lny = 0.0f;
+  if (gn2 > 1e-24f) {
+    const float s = lam * rsqrtf(gn2);
+    lnx = s * d.phx;
+    lny = s * d.phy;
+  }
+  const float muphi = -P.beta4 * phi * om * (phi - 0.5f) - P.kappa * d.lphi;
+  const float smask = 1.0f - P.chi * m.fsol;
+  const float T = P.T_melt + m.dT;
+  const float gcoef = rho - P.bq_coef * (T - P.bq_Tref);
+  const float Fx = smask * muphi * d.phx + gcoef * P.gx;
+  const float Fy = smask * muphi * d.phy + gcoef * P.gy;
+
+  // flow populations (Eq. (34)-(35)), loaded in phase 0
+  const float mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const float my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  const float rrho = 1.0f / rho;
+  const float usx = (mx + 0.5f * Fx) * rrho, usy = (my + 0.5f * Fy) * rrho;
+  const float fbx = -m.fsol * usx, fby = -m.fsol * usy;  // f = f_s (u_s - u*), u_s = 0
+  const float ux = usx + 0.5f * fbx, uy = usy + 0.5f * fby;
+  const float Ssrc = rho * m.mdot + ux * d.rx + uy * d.ry;
+  const float Ftx = Fx - d.px + (1.0f / 3.0f) * (d.rx + d.Sx);
+  const float Fty = Fy - d.py + (1.0f / 3.0f) * (d.ry + d.Sy);
+  const float uFt = ux * Ftx + uy * Fty;
+  const float usq = ux * ux + uy * uy;
+  const float tauf = 3.0f * m.mu * rrho + 0.5f;
+  const float F0 = W0 * (Ssrc - 3.0f * uFt);
+  float sumf = 0.0f;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) sumf += f[i];
+  const float p = 0.6f * (sumf + 0.5f * Ssrc + tauf * F0 + rho * (W0 * (-1.5f * usq)));
+
+  if (FIELDS) {
+    float* __restrict__ fields = io.fields;
+    const long long pl = P.plane;
+    fields[0 * pl + k] = phi;
+    fields[1 * pl + k] = T;
+    fields[2 * pl + k] = ux;
+    fields[3 * pl + k] = uy;
+    fields[4 * pl + k] = p;
+    fields[5 * pl + k] = m.fsol;
+    fields[6 * pl + k] = m.fl;
+    fields[7 * pl + k] = rho;
+    fields[8 * pl + k] = m.E - P.latent * m.fprev - (P.cp_ref - m.cp) * P.T_melt;
+    fields[9 * pl + k] = m.mdot;
+    return;
+  }
+
+  const long long pl = P.plane;
+  float* __restrict__ B = io.B;
+  // flow collision (Eq. (30)-(33))
+  {
+    const float itau = 1.0f / tauf, sf = 1.0f - 0.5f * itau;
+    const float Gx = Fx + rho * fbx, Gy = Fy + rho * fby;
+    float* Bf = B + 9 * pl;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const float cx = (float)cxv(i), cy = (float)cyv(i);
+      const float cu = cx * ux + cy * uy;
+      const float si = wt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq);
+      const float feq = 3.0f * p * (wt(i) - (i == 0 ? 1.0f : 0.0f)) + rho * si;
+      const float cF = cx * Ftx + cy * Fty;
+      const float Fi = wt(i) * (Ssrc + 3.0f * (cx * Gx + cy * Gy) + 9.0f * cu * cF - 3.0f * uFt);
+      Bf[i * pl + k] = f[i] - (f[i] - feq) * itau + sf * Fi;
+    }
+  }
+  // phase-field collision (Eq. (21), (24), (25), (37))
+  {
+    const float pux = phi * ux, puy = phi * uy;
+    const float dpx = pux - phiux, dpy = puy - phiuy;
+    const float ax = 3.0f * dpx + lnx, ay = 3.0f * dpy + lny;
+    const float pm = phi * m.mdot;
+    // the new reference is this step's phi (as stored); re-express the
+    // populations and the equilibrium relative to it
+    const float dr = m.r - phi;   // exact for nearby floats
+    const float dln = m.dl + dr;  // phi - phi_ref(new)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const float cx = (float)cxv(i), cy = (float)cyv(i);
+      const float cu = cx * ux + cy * uy;
+      const float gi = m.g[i] + wt(i) * dr;                 // g_i - w_i phi_ref
+      const float geq = wt(i) * (dln + 3.0f * phi * cu);  // g_i^eq - w_i phi_ref
+      const float Gi = wt(i) * (cx * ax + cy * ay + pm);
+      B[i * pl + k] = gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi;
+    }
+    io.ref_out[k] = phi;
+    io.phiu_out[k] = pux;
+    io.phiu_out[pl + k] = puy;
+  }
+  // enthalpy collision (Eq. (27)-(28)) in the shifted variables
+  {
+    const float itau = 1.0f / (m.kk * P.three_over_cpref + 0.5f);
+    const float cpT = m.cp * T;
+    const float crd = P.cp_ref * m.dT;
+    float* Bh = B + 18 * pl;
+    float hs = 0.0f;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const float cx = (float)cxv(i), cy = (float)cyv(i);
+      const float cu = cx * ux + cy * uy;
+      const float heq = wt(i) * (crd + cpT * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+      Bh[i * pl + k] = m.h[i] - (m.h[i] - heq) * itau;
+      hs += m.h[i];
+    }
+    // rest population: h0eq - h0 = sum_{i>0} h_i - cp_ref dT + w0 (cp_ref dT - 1.5 cp T u.u);
+    // the stored value moves by that relaxation plus L (f_s^H(n) - f_s^H(n-1))
+    const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
+    Bh[k] = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
+  }
+  io.fsH_out[k] = m.fsH;
+  io.p_out[k] = p;
+  io.S_out[k] = Ssrc;
+}
+
 template <int TX, int TY, bool FIELDS>
 __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, int ntiles,
                                                  int tiles_per_xcd) {
@@ -310,9 +464,8 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
         r1 = r - 2;
         tv = P.tan_t;
       }
-      const float d0 = 0.5f * (s_phi[r0][c + 1] - s_phi[r0][c - 1]);
-      const float d1 = 0.5f * (s_phi[r1][c + 1] - s_phi[r1][c - 1]);
-      const float pg = s_phi[r0][c] + tv * fabsf(1.5f * d0 - 0.5f * d1);
+      const float pg = wetting_ghost(s_phi[r0][c - 1], s_phi[r0][c], s_phi[r0][c + 1],
+                                     s_phi[r1][c - 1], s_phi[r1][c + 1], tv);
       const float pcg = clamp01(1.0f + pg);
       s_phi[r][c] = pg;
       s_rho[r][c] = mix3(pcg * s_fsH[r0][c], pcg, P.rho_s, P.rho_l, P.rho_g);
@@ -324,147 +477,165 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
   // ---- phase 2: stencils (Eq. (38)), forces, flow macros, collisions -----
   const int r = ly + 1, c = lx + 2;
   const int k = y * nx + x;
-  float gphx, gphy, lphi, grx, gry, gpx, gpy, gSx, gSy;
-  {
-    const float C = s_phi[r][c];
-    const float E = s_phi[r][c + 1], Wv = s_phi[r][c - 1], N = s_phi[r + 1][c], S = s_phi[r - 1][c];
-    const float NE = s_phi[r + 1][c + 1], NW = s_phi[r + 1][c - 1];
-    const float SW = s_phi[r - 1][c - 1], SE = s_phi[r - 1][c + 1];
-    // 3 sum w_i c_i z_i and 6 sum w_i (z_i - z_0)
-    gphx = (E - Wv) * (1.0f / 3.0f) + (NE - NW - SW + SE) * (1.0f / 12.0f);
-    gphy = (N - S) * (1.0f / 3.0f) + (NE + NW - SW - SE) * (1.0f / 12.0f);
-    lphi = (E + N + Wv + S - 4.0f * C) * (2.0f / 3.0f) + (NE + NW + SW + SE - 4.0f * C) * (1.0f / 6.0f);
-  }
-#define LBM_GRAD(arr, ox, oy)                                                                   \
-  {                                                                                             \
-    const float E = arr[r][c + 1], Wv = arr[r][c - 1], N = arr[r + 1][c], S = arr[r - 1][c];    \
-    const float NE = arr[r + 1][c + 1], NW = arr[r + 1][c - 1];                                 \
-    const float SW = arr[r - 1][c - 1], SE = arr[r - 1][c + 1];                                 \
-    ox = (E - Wv) * (1.0f / 3.0f) + (NE - NW - SW + SE) * (1.0f / 12.0f);                       \
-    oy = (N - S) * (1.0f / 3.0f) + (NE + NW - SW - SE) * (1.0f / 12.0f);                        \
-  }
-  LBM_GRAD(s_rho, grx, gry)
-  LBM_GRAD(s_p, gpx, gpy)
-  LBM_GRAD(s_S, gSx, gSy)
-#undef LBM_GRAD
+  Grads d;
+#define LBM_TILE_STENCIL(arr, ox, oy, lap)                                                       \
+  stencil(arr[r][c], arr[r][c + 1], arr[r][c - 1], arr[r + 1][c], arr[r - 1][c], arr[r + 1][c + 1], \
+          arr[r + 1][c - 1], arr[r - 1][c - 1], arr[r - 1][c + 1], ox, oy, lap)
+  LBM_TILE_STENCIL(s_phi, d.phx, d.phy, &d.lphi);
+  LBM_TILE_STENCIL(s_rho, d.rx, d.ry, nullptr);
+  LBM_TILE_STENCIL(s_p, d.px, d.py, nullptr);
+  LBM_TILE_STENCIL(s_S, d.Sx, d.Sy, nullptr);
+#undef LBM_TILE_STENCIL
+  update_node<FIELDS>(P, io, m, f, phiux, phiuy, d, k);
+}
 
-  const float phi = m.phi, rho = m.rho;
-  const float om = (1.0f - m.r) - m.dl;  // 1 - phi without cancellation in either bulk
-  // interface terms (Eq. (3), (12), (13))
-  const float lam = P.four_over_W * phi * om;
-  const float gn2 = gphx * gphx + gphy * gphy;
-  float lnx = 0.0f, lny = 0.0f;
-  if (gn2 > 1e-24f) {
-    const float s = lam * rsqrtf(gn2);
-    lnx = s * gphx;
-    lny = s * gphy;
-  }
-  const float muphi = -P.beta4 * phi * om * (phi - 0.5f) - P.kappa * lphi;
-  const float smask = 1.0f - P.chi * m.fsol;
-  const float T = P.T_melt + m.dT;
-  const float gcoef = rho - P.bq_coef * (T - P.bq_Tref);
-  const float Fx = smask * muphi * gphx + gcoef * P.gx;
-  const float Fy = smask * muphi * gphy + gcoef * P.gy;
+// Sliding-window variant for large grids.  A workgroup of TX lanes owns a
+// TX-wide strip of up to SY rows and walks it upwards: each iteration
+// rebuilds the macroscopic quantities of the row above the one it updates
+// into 4-slot LDS rings (phi - 1, rho, f_s^H with two halo columns; lagged p
+// and S with one; phi_ref with three), then updates its row.  Every
+// population is fetched once as the window passes, so the only redundant
+// work is four halo columns per strip and one extra row at the strip start.
+// Arithmetic is shared with k_step, so both give bit-identical results.
+template <int TX, int SY, bool FIELDS>
+__global__ __launch_bounds__(TX) void k_column(KParams P, StepIO io, int nsx, int nstrips,
+                                               int tiles_per_xcd) {
+  constexpr int LW = TX + 4;  // phi/rho/f_s^H: columns x0-2 .. x0+TX+1
+  constexpr int LP = TX + 2;  // p/S:           columns x0-1 .. x0+TX
+  constexpr int LR = TX + 6;  // phi_ref:       columns x0-3 .. x0+TX+2
+  __shared__ float s_phi[4][LW];
+  __shared__ float s_rho[4][LW];
+  __shared__ float s_fsH[4][LW];
+  __shared__ float s_p[4][LP];
+  __shared__ float s_S[4][LP];
+  __shared__ float s_ref[4][LR];
 
-  // flow populations (Eq. (34)-(35)), loaded in phase 0
-  const float mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-  const float my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-  const float rrho = 1.0f / rho;
-  const float usx = (mx + 0.5f * Fx) * rrho, usy = (my + 0.5f * Fy) * rrho;
-  const float fbx = -m.fsol * usx, fby = -m.fsol * usy;  // f = f_s (u_s - u*), u_s = 0
-  const float ux = usx + 0.5f * fbx, uy = usy + 0.5f * fby;
-  const float Ssrc = rho * m.mdot + ux * grx + uy * gry;
-  const float Ftx = Fx - gpx + (1.0f / 3.0f) * (grx + gSx);
-  const float Fty = Fy - gpy + (1.0f / 3.0f) * (gry + gSy);
-  const float uFt = ux * Ftx + uy * Fty;
-  const float usq = ux * ux + uy * uy;
-  const float tauf = 3.0f * m.mu * rrho + 0.5f;
-  const float F0 = W0 * (Ssrc - 3.0f * uFt);
-  float sumf = 0.0f;
-#pragma unroll
-  for (int i = 1; i < 9; ++i) sumf += f[i];
-  const float p = 0.6f * (sumf + 0.5f * Ssrc + tauf * F0 + rho * (W0 * (-1.5f * usq)));
+  const float* __restrict__ A = io.A;
+  const int b = blockIdx.x;
+  const int strip = tiles_per_xcd > 0 ? (b & 7) * tiles_per_xcd + (b >> 3) : b;
+  if (strip >= nstrips) return;  // whole workgroup leaves before any barrier
+  const int nx = P.nx, ny = P.ny;
+  const int x0 = (strip % nsx) * TX, y0 = (strip / nsx) * SY;
+  const int yend = min(y0 + SY, ny);
+  const int t = threadIdx.x;
+  const int x = x0 + t;
+  const int xw = wrapx(x, nx);
+  const bool xin = x < nx;
+  const bool hl = t < 4;                // lanes 0..3 also rebuild one halo column
+  const int hc = t < 2 ? t : TX + t;    // LDS columns 0, 1, TX+2, TX+3
+  const int hxw = wrapx(x0 + hc - 2, nx);
+#define SLOT(gy) (((gy) + 4) & 3)
 
-  if (FIELDS) {
-    float* __restrict__ fields = io.fields;
-    const long long pl = P.plane;
-    fields[0 * pl + k] = phi;
-    fields[1 * pl + k] = T;
-    fields[2 * pl + k] = ux;
-    fields[3 * pl + k] = uy;
-    fields[4 * pl + k] = p;
-    fields[5 * pl + k] = m.fsol;
-    fields[6 * pl + k] = m.fl;
-    fields[7 * pl + k] = rho;
-    fields[8 * pl + k] = m.E - P.latent * m.fprev - (P.cp_ref - m.cp) * P.T_melt;
-    fields[9 * pl + k] = m.mdot;
-    return;
-  }
-
-  const long long pl = P.plane;
-  float* __restrict__ B = io.B;
-  // flow collision (Eq. (30)-(33))
-  {
-    const float itau = 1.0f / tauf, sf = 1.0f - 0.5f * itau;
-    const float Gx = Fx + rho * fbx, Gy = Fy + rho * fby;
-    float* Bf = B + 9 * pl;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const float cx = (float)cxv(i), cy = (float)cyv(i);
-      const float cu = cx * ux + cy * uy;
-      const float si = wt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq);
-      const float feq = 3.0f * p * (wt(i) - (i == 0 ? 1.0f : 0.0f)) + rho * si;
-      const float cF = cx * Ftx + cy * Fty;
-      const float Fi = wt(i) * (Ssrc + 3.0f * (cx * Gx + cy * Gy) + 9.0f * cu * cF - 3.0f * uFt);
-      Bf[i * pl + k] = f[i] - (f[i] - feq) * itau + sf * Fi;
+  // one row of phi_ref (clamped beyond the walls, where it is never read)
+  // and of the lagged p, S (rows beyond a wall copy the adjacent row)
+  auto load_ref = [&](int gy) {
+    const int cy = min(max(gy, 0), ny - 1);
+    for (int j = t; j < LR; j += TX) s_ref[SLOT(gy)][j] = io.ref_in[cy * nx + wrapx(x0 + j - 3, nx)];
+  };
+  auto load_pS = [&](int gy) {
+    const int cy = min(max(gy, 0), ny - 1);
+    for (int j = t; j < LP; j += TX) {
+      const int kk = cy * nx + wrapx(x0 + j - 1, nx);
+      s_p[SLOT(gy)][j] = io.p_in[kk];
+      s_S[SLOT(gy)][j] = io.S_in[kk];
     }
-  }
-  // phase-field collision (Eq. (21), (24), (25), (37))
-  {
-    const float pux = phi * ux, puy = phi * uy;
-    const float dpx = pux - phiux, dpy = puy - phiuy;
-    const float ax = 3.0f * dpx + lnx, ay = 3.0f * dpy + lny;
-    const float pm = phi * m.mdot;
-    // the new reference is this step's phi (as stored); re-express the
-    // populations and the equilibrium relative to it
-    const float dr = m.r - phi;   // exact for nearby floats
-    const float dln = m.dl + dr;  // phi - phi_ref(new)
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const float cx = (float)cxv(i), cy = (float)cyv(i);
-      const float cu = cx * ux + cy * uy;
-      const float gi = m.g[i] + wt(i) * dr;                 // g_i - w_i phi_ref
-      const float geq = wt(i) * (dln + 3.0f * phi * cu);  // g_i^eq - w_i phi_ref
-      const float Gi = wt(i) * (cx * ax + cy * ay + pm);
-      B[i * pl + k] = gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi;
-    }
-    io.ref_out[k] = phi;
-    io.phiu_out[k] = pux;
-    io.phiu_out[pl + k] = puy;
-  }
-  // enthalpy collision (Eq. (27)-(28)) in the shifted variables
-  {
-    const float itau = 1.0f / (m.kk * P.three_over_cpref + 0.5f);
-    const float cpT = m.cp * T;
-    const float crd = P.cp_ref * m.dT;
-    float* Bh = B + 18 * pl;
-    float hs = 0.0f;
+  };
+  // g of a node in row gy, LDS column c, re-expressed in its own reference
+  auto rebase = [&](float q[9], int gy, int c) -> float {
+#pragma clang fp contract(off)
+    const bool bot = (gy == 0), top = (gy == ny - 1);
+    const float rself = s_ref[SLOT(gy)][c + 1];
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-      const float cx = (float)cxv(i), cy = (float)cyv(i);
-      const float cu = cx * ux + cy * uy;
-      const float heq = wt(i) * (crd + cpT * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
-      Bh[i * pl + k] = m.h[i] - (m.h[i] - heq) * itau;
-      hs += m.h[i];
+      const int cy = cyv(i), cx = cxv(i);
+      const bool wall = (cy > 0 && bot) || (cy < 0 && top);
+      const float rs = wall ? rself : s_ref[SLOT(gy - cy)][c + 1 - cx];
+      q[i] += wt(i) * (rs - rself);
     }
-    // rest population: h0eq - h0 = sum_{i>0} h_i - cp_ref dT + w0 (cp_ref dT - 1.5 cp T u.u);
-    // the stored value moves by that relaxation plus L (f_s^H(n) - f_s^H(n-1))
-    const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
-    Bh[k] = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
+    return rself;
+  };
+  // macroscopic quantities of row gy into the rings; the lane's own node is
+  // returned in `mine`, lanes 0..3 also fill one halo column each
+  auto macro_row = [&](int gy, Macro& mine) {
+    if (hl) {
+      Macro mh;
+      load_node(A, io.fsH_in, P, hxw, gy, mh);
+      const float rs = rebase(mh.g, gy, hc);
+      finish_macro(P, rs, mh);
+      s_phi[SLOT(gy)][hc] = (mh.r - 1.0f) + mh.dl;
+      s_rho[SLOT(gy)][hc] = mh.rho;
+      s_fsH[SLOT(gy)][hc] = mh.fsH;
+    }
+    load_node(A, io.fsH_in, P, xw, gy, mine);
+    const float rs = rebase(mine.g, gy, t + 2);
+    finish_macro(P, rs, mine);
+    s_phi[SLOT(gy)][t + 2] = (mine.r - 1.0f) + mine.dl;
+    s_rho[SLOT(gy)][t + 2] = mine.rho;
+    s_fsH[SLOT(gy)][t + 2] = mine.fsH;
+  };
+  // wetting ghost row gg from rows ga (adjacent) and gb (next)
+  auto ghost_row = [&](int gg, int ga, int gb, float tv) {
+    for (int c = 1 + t; c < LW - 1; c += TX) {
+      const float pg = wetting_ghost(s_phi[SLOT(ga)][c - 1], s_phi[SLOT(ga)][c], s_phi[SLOT(ga)][c + 1],
+                                     s_phi[SLOT(gb)][c - 1], s_phi[SLOT(gb)][c + 1], tv);
+      const float pcg = clamp01(1.0f + pg);
+      s_phi[SLOT(gg)][c] = pg;
+      s_rho[SLOT(gg)][c] = mix3(pcg * s_fsH[SLOT(ga)][c], pcg, P.rho_s, P.rho_l, P.rho_g);
+    }
+  };
+
+  // prologue: rows y0-1 (halo row below the strip, if inside the domain) and y0
+  for (int gy = y0 - 2; gy <= y0 + 1; ++gy) load_ref(gy);
+  load_pS(y0 - 1);
+  load_pS(y0);
+  __syncthreads();
+  Macro mc;
+  if (y0 >= 1) {
+    Macro tmp;
+    macro_row(y0 - 1, tmp);
   }
-  io.fsH_out[k] = m.fsH;
-  io.p_out[k] = p;
-  io.S_out[k] = Ssrc;
+  macro_row(y0, mc);
+  __syncthreads();
+
+  for (int y = y0; y < yend; ++y) {
+    // this node's flow populations and (phi u)^{n-1}, in flight meanwhile
+    float f[9], phiux = 0.0f, phiuy = 0.0f;
+    const int k = y * nx + xw;
+    if (xin) {
+      const int xm = x == 0 ? nx - 1 : x - 1;
+      const int xp = x == nx - 1 ? 0 : x + 1;
+      pull9<1>(A, P, x, y, xm, xp, f);
+      phiux = io.phiu_in[k];
+      phiuy = io.phiu_in[P.plane + k];
+    }
+    load_ref(y + 2);
+    load_pS(y + 1);
+    __syncthreads();
+    Macro ml;
+    const int yl = y + 1;
+    if (yl < ny) macro_row(yl, ml);
+    __syncthreads();
+    const bool gtop = (yl == ny), gbot = (y == 0);
+    if (gtop) ghost_row(ny, ny - 1, ny - 2, P.tan_t);
+    if (gbot) ghost_row(-1, 0, 1, P.tan_b);
+    if (gtop || gbot) __syncthreads();
+    if (xin) {
+      const int a = SLOT(y - 1), c0 = SLOT(y), u = SLOT(y + 1);
+      const int c = t + 2, cp = t + 1;
+      Grads d;
+      stencil(s_phi[c0][c], s_phi[c0][c + 1], s_phi[c0][c - 1], s_phi[u][c], s_phi[a][c], s_phi[u][c + 1],
+              s_phi[u][c - 1], s_phi[a][c - 1], s_phi[a][c + 1], d.phx, d.phy, &d.lphi);
+      stencil(s_rho[c0][c], s_rho[c0][c + 1], s_rho[c0][c - 1], s_rho[u][c], s_rho[a][c], s_rho[u][c + 1],
+              s_rho[u][c - 1], s_rho[a][c - 1], s_rho[a][c + 1], d.rx, d.ry, nullptr);
+      stencil(s_p[c0][cp], s_p[c0][cp + 1], s_p[c0][cp - 1], s_p[u][cp], s_p[a][cp], s_p[u][cp + 1],
+              s_p[u][cp - 1], s_p[a][cp - 1], s_p[a][cp + 1], d.px, d.py, nullptr);
+      stencil(s_S[c0][cp], s_S[c0][cp + 1], s_S[c0][cp - 1], s_S[u][cp], s_S[a][cp], s_S[u][cp + 1],
+              s_S[u][cp - 1], s_S[a][cp - 1], s_S[a][cp + 1], d.Sx, d.Sy, nullptr);
+      update_node<FIELDS>(P, io, mc, f, phiux, phiuy, d, k);
+    }
+    mc = ml;
+  }
+#undef SLOT
 }
 
 // Initial state (no time-stepping yet): u = 0, p = 0, liquid fraction 1,
@@ -579,6 +750,25 @@ int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <int TX, int SY>
+int launch_column(const KParams& P, const State& S, int cur, bool fields_only, int xcd, hipStream_t st) {
+  const int nsx = (P.nx + TX - 1) / TX, nsy = (P.ny + SY - 1) / SY;
+  const int nstrips = nsx * nsy;
+  int tpx = 0, grid = nstrips;
+  if (xcd) {
+    tpx = (nstrips + 7) / 8;
+    grid = 8 * tpx;
+  }
+  const int nxt = cur ^ 1;
+  StepIO io{S.pops[cur], S.pops[nxt], S.phiu[cur], S.phiu[nxt], S.ref[cur], S.ref[nxt],
+            S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur], S.S[nxt], S.fields};
+  if (fields_only)
+    hipLaunchKernelGGL((k_column<TX, SY, true>), dim3(grid), dim3(TX), 0, st, P, io, nsx, nstrips, tpx);
+  else
+    hipLaunchKernelGGL((k_column<TX, SY, false>), dim3(grid), dim3(TX), 0, st, P, io, nsx, nstrips, tpx);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 }  // namespace
 
 int launch_init(const KParams& P, const IParams& I, const State& S, int cur, const double* d_phi0,
@@ -601,6 +791,12 @@ int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int
       return launch_tile<64, 16>(P, S, cur, fields_only, xcd_remap, st);
     case 4:
       return launch_tile<128, 4>(P, S, cur, fields_only, xcd_remap, st);
+    case 5:
+      return launch_column<64, 32>(P, S, cur, fields_only, xcd_remap, st);
+    case 6:
+      return launch_column<64, 64>(P, S, cur, fields_only, xcd_remap, st);
+    case 7:
+      return launch_column<128, 32>(P, S, cur, fields_only, xcd_remap, st);
     default:
       return launch_tile<64, 4>(P, S, cur, fields_only, xcd_remap, st);
   }

@@ -100,7 +100,8 @@ def test_within_the_methods_own_sensitivity(oracle_mod, seed, steps):
 
 
 @pytest.mark.parametrize("nx,ny,tile", [(70, 13, "64x4"), (70, 13, "32x8"), (130, 19, "64x8"),
-                                        (3, 3, "64x4"), (5, 4, "32x8"), (67, 9, "64x4")])
+                                        (3, 3, "64x4"), (5, 4, "32x8"), (67, 9, "64x4"),
+                                        (70, 37, "strip64x32"), (3, 3, "strip64x32"), (131, 20, "strip128x32")])
 def test_ragged_and_tiny_grids(oracle_mod, nx, ny, tile):
     p = W.default_params(nx, ny, rho_s=0.88, theta_bottom_deg=65.0, theta_top_deg=115.0,
                          gx=2e-6, gy=-5e-6, cp_s=0.7, k_s=0.2, cp_g=0.9, k_g=0.05)
@@ -130,7 +131,7 @@ def test_tile_shapes_and_xcd_mapping_are_bitwise_identical():
     lbm = _gpu()
     p, phi0, T0, _ = W.workload("sessile128", seed=0)
     ref = None
-    for tile in ("64x4", "32x8", "64x8", "64x16", "128x4"):
+    for tile in ("64x4", "32x8", "64x8", "64x16", "128x4", "strip64x32", "strip64x64", "strip128x32"):
         for xcd in (True, False):
             print(f"tile={tile} xcd={xcd}", flush=True)
             g = lbm.Solver(p, phi0, T0)
@@ -174,6 +175,29 @@ def test_sum_phi_conserved_on_gpu():
     # FP32 populations: each step rounds 9 values per node (~6e-8 relative)
     assert abs(d["sum_phi"] - s0) < 2e-5 * s0
     assert d["sum_solid"] > 1.0
+
+
+@pytest.mark.parametrize("nx,ny,tile", [(131, 70, "strip128x32"), (5, 66, "strip64x64"), (64, 66, "strip64x64"),
+                                        (200, 33, "strip64x32"), (3, 97, "strip64x32")])
+def test_strips_equal_tiles_bitwise_on_ragged_grids(nx, ny, tile):
+    """The column-strip kernels must reproduce the 2-D tile kernel bit for
+    bit on grids that are ragged in both directions (and narrower than a
+    strip)."""
+    lbm = _gpu()
+    p = W.default_params(nx, ny, rho_s=0.88, theta_bottom_deg=65.0, theta_top_deg=115.0,
+                         gx=2e-6, gy=-5e-6, cp_s=0.7, k_s=0.2, cp_g=0.9, k_g=0.05)
+    R = max(2.0, min(nx, ny, 40) / 2.5)
+    phi0 = W.sessile_droplet(nx, ny, R, 90.0, 4.0, x0=nx / 2.0 + 0.3)
+    T0 = W.temperature_noise(nx, ny, p["T_melt"], 1e-3, 4)
+    a = lbm.Solver(p, phi0, T0)
+    a.set_launch("64x4", True)
+    b = lbm.Solver(p, phi0, T0)
+    b.set_launch(tile, True)
+    a.step(30)
+    b.step(30)
+    fa, fb = a.fields(FIELDS), b.fields(FIELDS)
+    for k in FIELDS:
+        assert np.array_equal(fa[k], fb[k]), k
 
 
 def test_autotune_leaves_state_untouched():
