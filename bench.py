@@ -70,8 +70,9 @@ def pick_launch(solver, args):
     region, state untouched) or a fixed choice."""
     if args.tile == "auto":
         return solver.autotune(reps=20 if solver.N < 1 << 20 else 3)
-    solver.set_launch(args.tile, not args.no_xcd)
-    return args.tile, not args.no_xcd
+    mode = args.xcd if args.xcd is not None else (0 if args.no_xcd else 1)
+    solver.set_launch(args.tile, mode)
+    return args.tile, mode
 
 
 def cpu_baseline(params, phi0, T0, budget_s: float):
@@ -97,7 +98,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--workload", default="sessile512")
     ap.add_argument("--tile", default="auto", help="auto (library autotuner) or 64x4/32x8/64x8/64x16/128x4")
-    ap.add_argument("--no-xcd", action="store_true")
+    ap.add_argument("--no-xcd", action="store_true", help="round-robin workgroup dispatch (xcd mode 0)")
+    ap.add_argument("--xcd", type=int, default=None, help="workgroup-to-XCD mapping mode 0/1 (fixed tiles only)")
     ap.add_argument("--probe-steps", type=int, default=100, help="steps on the 4096x2048 grid (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle timing budget (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,

@@ -128,10 +128,11 @@ const char* lbm_last_error(void);
 
 /* Launch shape of the fused step.  tile_variant 0..4: 2-D tiles of 64x4
  * (default), 32x8, 64x8, 64x16, 128x4 nodes per workgroup, halo macros
- * recomputed per tile; 5..7: column strips of 64x32, 64x64, 128x32 nodes
- * walked row by row (halo only at the strip sides, for large grids).
- * xcd_remap 1 hands consecutive tiles to one XCD (its L2 then serves the
- * halo re-reads).  Results are bitwise identical for every choice. */
+ * recomputed per tile; 5..7: column strips 60 nodes wide and 32, 64, 128
+ * rows high, walked row by row (halo only at the strip sides, for large grids).
+ * xcd_remap: 0 keeps the hardware's round-robin of workgroups over the 8
+ * XCDs; 1 gives each XCD one contiguous band of tiles (its L2 then serves
+ * the halo re-reads).  Results are bitwise identical for every choice. */
 int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap);
 
 /* Time every launch shape for `reps` steps and keep the fastest (written to

@@ -48,7 +48,7 @@ bool all_finite(const lbm_params* p) {
 int validate(const lbm_params* p) {
   if (!p) return LBM_EINVAL;
   if (p->nx < 3 || p->ny < 3) return LBM_EINVAL;
-  if ((long long)p->nx * p->ny > (1LL << 31) / 32) return LBM_EINVAL;  // 32-bit node indices
+  if ((long long)p->nx * p->ny > (1LL << 32) / 80) return LBM_EINVAL;  // 32-bit element indices over the workspace
   if (!all_finite(p)) return LBM_EINVAL;
   if (!(p->W > 0) || !(p->M > 0) || p->sigma < 0) return LBM_EINVAL;
   if (!(p->rho_l > 0 && p->rho_g > 0 && p->rho_s > 0)) return LBM_EINVAL;
@@ -101,7 +101,7 @@ void fill_kparams(lbm_ctx* c) {
   lbmk::KParams& K = c->K;
   K.nx = p.nx;
   K.ny = p.ny;
-  K.plane = plane_floats(&p);
+  K.plane = (unsigned)plane_floats(&p);
   const double tau_g = 3.0 * p.M + 0.5;
   K.inv_tau_g = (float)(1.0 / tau_g);
   K.src_g = (float)(1.0 - 0.5 / tau_g);

@@ -11,7 +11,7 @@ namespace lbmk {
 // Precomputed lattice-unit constants handed to every kernel by value.
 struct KParams {
   int nx, ny;
-  long long plane;  // floats per population/field plane (padded to 64)
+  unsigned plane;  // floats per population/field plane (padded to 64); every index fits 32 bits
   // phase field (Sec. 3.1)
   float inv_tau_g, src_g;          // 1/tau_g and 1 - 1/(2 tau_g)
   float four_over_W, beta4, kappa; // 4/W, 4 beta, kappa
@@ -39,7 +39,7 @@ struct State {
 };
 
 enum { NFIELD = 10 };
-enum { NTILE_VARIANTS = 8 };  // tiles 64x4, 32x8, 64x8, 64x16, 128x4; strips 64x32, 64x64, 128x32
+enum { NTILE_VARIANTS = 8 };  // tiles 64x4, 32x8, 64x8, 64x16, 128x4; strips 60x32, 60x64, 60x128
 enum { RED_NVAL = 8 };
 constexpr int RED_BLOCKS = 512;
 

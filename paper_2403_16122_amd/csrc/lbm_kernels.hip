@@ -37,10 +37,25 @@ __device__ __forceinline__ float mix3(float fs, float pc, float zs, float zl, fl
   // Eq. (1) with the clamped order parameter
   return fs * zs + (1.0f - fs) * (pc * zl + (1.0f - pc) * zg);
 }
+// Periodic x: one compare-and-shift covers |x| < 2 nx; the modulo only
+// runs for grids narrower than a tile.
 __device__ __forceinline__ int wrapx(int x, int nx) {
-  int r = x % nx;
-  return r < 0 ? r + nx : r;
+  int r = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+  if ((unsigned)r >= (unsigned)nx) r = ((x % nx) + nx) % nx;
+  return r;
 }
+
+// Element access by a 32-bit index: the byte offset is formed in 32 bits so
+// the load/store uses the scalar-base + 32-bit-vector-offset addressing form.
+__device__ __forceinline__ float ld(const float* __restrict__ base, unsigned idx) {
+  return *(const float*)((const char*)base + (idx << 2));
+}
+__device__ __forceinline__ void st(float* __restrict__ base, unsigned idx, float v) {
+  *(float*)((char*)base + (idx << 2)) = v;
+}
+
+// Hardware reciprocal (1 ulp); used identically wherever a node is rebuilt.
+__device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
 // Pull-stream the 9 populations of one lattice into node (x, y).  Sources
 // beyond a wall are replaced by the bounce-back of the node's own opposite
@@ -50,31 +65,26 @@ __device__ __forceinline__ int wrapx(int x, int nx) {
 template <int LAT>
 __device__ __forceinline__ void pull9(const float* __restrict__ A, const KParams& P, int x, int y,
                                       int xm, int xp, float q[9]) {
-  const long long pl = P.plane;
-  const float* base = A + (long long)(LAT * 9) * pl;
-  const int nx = P.nx;
+  // 32-bit element indices: a scalar plane base plus one vector offset per load
+  const unsigned pl = P.plane;
+  const unsigned nx = (unsigned)P.nx;
   const bool bot = (y == 0), top = (y == P.ny - 1);
-  const int k = y * nx + x;
+  const unsigned rowc = (unsigned)y * nx;
+  const unsigned rowd = rowc - nx, rowu = rowc + nx;  // used only away from the walls
+  const unsigned k = rowc + (unsigned)x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int cy = cyv(i), cx = cxv(i);
     const bool wall = (cy > 0 && bot) || (cy < 0 && top);
-    const int sx = cx > 0 ? xm : (cx < 0 ? xp : x);
-    const int sk = (y - cy) * nx + sx;
-    const long long addr = wall ? (long long)opp(i) * pl + k : (long long)i * pl + sk;
-    float v = base[addr];
+    const unsigned sx = (unsigned)(cx > 0 ? xm : (cx < 0 ? xp : x));
+    const unsigned sk = (cy > 0 ? rowd : (cy < 0 ? rowu : rowc)) + sx;
+    const unsigned idx = wall ? (unsigned)(LAT * 9 + opp(i)) * pl + k : (unsigned)(LAT * 9 + i) * pl + sk;
+    float v = ld(A, idx);
     if (LAT == 2 && cy > 0) v = bot ? (P.hwall[i] - v) : v;
     q[i] = v;
   }
 }
 
-// The phase-field populations are stored relative to the rest state of
-// the node that wrote them: node x stores g_i(x) - w_i phi_ref(x), where
-// phi_ref(x) is its order parameter of that step, kept in its own plane.
-// A receiving node adds back w_i phi_ref(source) and re-expresses all nine
-// in its own reference, q_i = g_i - w_i phi_ref(self).  Every stored number
-// is then a one-step increment, so FP32 resolves phi to ~1e-11 in bulk
-// liquid, bulk gas, interfaces and frozen regions alike (exact algebra).
 // Re-express freshly pulled g populations (node at LDS cell (c, r), row y)
 // in the reference of the receiving node: q_i += w_i (phi_ref(src) - phi_ref(self)).
 // The reference tile holds phi_ref of cell (c, r) at sref[r + 1][c + 1].
@@ -124,7 +134,7 @@ __device__ __forceinline__ void load_node(const float* __restrict__ A,
   const int xp = x == P.nx - 1 ? 0 : x + 1;
   pull9<0>(A, P, x, y, xm, xp, m.g);
   pull9<2>(A, P, x, y, xm, xp, m.h);
-  m.fprev = fsH_prev[y * P.nx + x];
+  m.fprev = ld(fsH_prev, (unsigned)(y * P.nx + x));
 }
 
 // Node-local macroscopic quantities of time t (Eq. (29), (9), (19), (26), (1))
@@ -150,12 +160,12 @@ __device__ __forceinline__ void finish_macro(const KParams& P, float rs, Macro& 
   const float dHl = E - P.latent * fprev;
   const float dHs = E + P.latent * (1.0f - fprev);
   const float fl = clamp01(E * P.inv_latent + (1.0f - fprev));
-  const float rcp = 1.0f / cp;
-  const float dT = dHs < 0.0f ? dHs * rcp : (dHl > 0.0f ? dHl * rcp : 0.0f);
+  const float rcpc = rcp(cp);
+  const float dT = dHs < 0.0f ? dHs * rcpc : (dHl > 0.0f ? dHl * rcpc : 0.0f);
   const float fsH = 1.0f - fl;
   const float mdot = P.mdot_coef * pc0 * (fsH - fprev);
   // phi from Eq. (26) with div(u) = mdot; phi - r = (D0 + r mdot/2)/(1 - mdot/2)
-  const float rden = 1.0f / (1.0f - 0.5f * mdot);
+  const float rden = rcp(1.0f - 0.5f * mdot);
   const float dl = (D0 + 0.5f * rs * mdot) * rden;
   const float phi = rs + dl;
   const float pc = clamp01(phi);
@@ -227,7 +237,7 @@ __device__ __forceinline__ float wetting_ghost(float a0m, float a0c, float a0p, 
 template <bool FIELDS>
 __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, const Macro& m,
                                             const float f[9], float phiux, float phiuy,
-                                            const Grads& d, int k) {
+                                            const Grads& d, unsigned k) {
   const float phi = m.phi, rho = m.rho;
   const float om = (1.0f - m.r) - m.dl;  // 1 - phi without cancellation in either bulk
   // interface terms (Eq. (3), (12), (13))
@@ -249,7 +259,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
   // flow populations (Eq. (34)-(35)), loaded in phase 0
   const float mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const float my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-  const float rrho = 1.0f / rho;
+  const float rrho = rcp(rho);
   const float usx = (mx + 0.5f * Fx) * rrho, usy = (my + 0.5f * Fy) * rrho;
   const float fbx = -m.fsol * usx, fby = -m.fsol * usy;  // f = f_s (u_s - u*), u_s = 0
   const float ux = usx + 0.5f * fbx, uy = usy + 0.5f * fby;
@@ -267,25 +277,25 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
 
   if (FIELDS) {
     float* __restrict__ fields = io.fields;
-    const long long pl = P.plane;
-    fields[0 * pl + k] = phi;
-    fields[1 * pl + k] = T;
-    fields[2 * pl + k] = ux;
-    fields[3 * pl + k] = uy;
-    fields[4 * pl + k] = p;
-    fields[5 * pl + k] = m.fsol;
-    fields[6 * pl + k] = m.fl;
-    fields[7 * pl + k] = rho;
-    fields[8 * pl + k] = m.E - P.latent * m.fprev - (P.cp_ref - m.cp) * P.T_melt;
-    fields[9 * pl + k] = m.mdot;
+    const unsigned pl = P.plane;
+    st(fields, 0 * pl + k, phi);
+    st(fields, 1 * pl + k, T);
+    st(fields, 2 * pl + k, ux);
+    st(fields, 3 * pl + k, uy);
+    st(fields, 4 * pl + k, p);
+    st(fields, 5 * pl + k, m.fsol);
+    st(fields, 6 * pl + k, m.fl);
+    st(fields, 7 * pl + k, rho);
+    st(fields, 8 * pl + k, m.E - P.latent * m.fprev - (P.cp_ref - m.cp) * P.T_melt);
+    st(fields, 9 * pl + k, m.mdot);
     return;
   }
 
-  const long long pl = P.plane;
+  const unsigned pl = P.plane;
   float* __restrict__ B = io.B;
   // flow collision (Eq. (30)-(33))
   {
-    const float itau = 1.0f / tauf, sf = 1.0f - 0.5f * itau;
+    const float itau = rcp(tauf), sf = 1.0f - 0.5f * itau;
     const float Gx = Fx + rho * fbx, Gy = Fy + rho * fby;
     float* Bf = B + 9 * pl;
 #pragma unroll
@@ -296,7 +306,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float feq = 3.0f * p * (wt(i) - (i == 0 ? 1.0f : 0.0f)) + rho * si;
       const float cF = cx * Ftx + cy * Fty;
       const float Fi = wt(i) * (Ssrc + 3.0f * (cx * Gx + cy * Gy) + 9.0f * cu * cF - 3.0f * uFt);
-      Bf[i * pl + k] = f[i] - (f[i] - feq) * itau + sf * Fi;
+      st(Bf, i * pl + k, f[i] - (f[i] - feq) * itau + sf * Fi);
     }
   }
   // phase-field collision (Eq. (21), (24), (25), (37))
@@ -316,15 +326,15 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float gi = m.g[i] + wt(i) * dr;                 // g_i - w_i phi_ref
       const float geq = wt(i) * (dln + 3.0f * phi * cu);  // g_i^eq - w_i phi_ref
       const float Gi = wt(i) * (cx * ax + cy * ay + pm);
-      B[i * pl + k] = gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi;
+      st(B, i * pl + k, gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi);
     }
-    io.ref_out[k] = phi;
-    io.phiu_out[k] = pux;
-    io.phiu_out[pl + k] = puy;
+    st(io.ref_out, k, phi);
+    st(io.phiu_out, k, pux);
+    st(io.phiu_out, pl + k, puy);
   }
   // enthalpy collision (Eq. (27)-(28)) in the shifted variables
   {
-    const float itau = 1.0f / (m.kk * P.three_over_cpref + 0.5f);
+    const float itau = rcp(m.kk * P.three_over_cpref + 0.5f);
     const float cpT = m.cp * T;
     const float crd = P.cp_ref * m.dT;
     float* Bh = B + 18 * pl;
@@ -334,22 +344,30 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float cx = (float)cxv(i), cy = (float)cyv(i);
       const float cu = cx * ux + cy * uy;
       const float heq = wt(i) * (crd + cpT * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
-      Bh[i * pl + k] = m.h[i] - (m.h[i] - heq) * itau;
+      st(Bh, i * pl + k, m.h[i] - (m.h[i] - heq) * itau);
       hs += m.h[i];
     }
     // rest population: h0eq - h0 = sum_{i>0} h_i - cp_ref dT + w0 (cp_ref dT - 1.5 cp T u.u);
     // the stored value moves by that relaxation plus L (f_s^H(n) - f_s^H(n-1))
     const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
-    Bh[k] = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
+    st(Bh, k, m.h[0] + d0 + P.latent * (m.fsH - m.fprev));
   }
-  io.fsH_out[k] = m.fsH;
-  io.p_out[k] = p;
-  io.S_out[k] = Ssrc;
+  st(io.fsH_out, k, m.fsH);
+  st(io.p_out, k, p);
+  st(io.S_out, k, Ssrc);
+}
+
+// Workgroup -> tile.  Workgroups are dispatched round-robin over the 8
+// XCDs (block b runs on XCD b mod 8).  Mode 0 keeps that order; mode 1
+// hands each XCD one contiguous band of tiles_per_xcd tiles, so the halo
+// re-reads of neighbouring tiles meet in one L2.
+__device__ __forceinline__ int map_tile(int b, int mode, int tiles_per_xcd) {
+  return mode == 1 ? (b & 7) * tiles_per_xcd + (b >> 3) : b;
 }
 
 template <int TX, int TY, bool FIELDS>
 __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, int ntiles,
-                                                 int tiles_per_xcd) {
+                                                 int tiles_per_xcd, int mode) {
   constexpr int NT = TX * TY;
   constexpr int LX = TX + 4, LY = TY + 2;  // LDS column c <-> x0 + c - 2, row r <-> y0 + r - 1
   constexpr int RX = LX + 2, RY = LY + 2;  // reference tile: one more cell on every side
@@ -361,8 +379,7 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
   __shared__ float s_ref[RY][RX];  // phi of the previous step, reference of the stored g
 
   const float* __restrict__ A = io.A;
-  const int b = blockIdx.x;
-  const int tile = tiles_per_xcd > 0 ? (b & 7) * tiles_per_xcd + (b >> 3) : b;
+  const int tile = map_tile(blockIdx.x, mode, tiles_per_xcd);
   if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
   const int nx = P.nx, ny = P.ny;
   const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
@@ -386,8 +403,8 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
     const int xm = x == 0 ? nx - 1 : x - 1;
     const int xp = x == nx - 1 ? 0 : x + 1;
     pull9<1>(A, P, x, y, xm, xp, f);
-    phiux = io.phiu_in[y * nx + x];
-    phiuy = io.phiu_in[P.plane + y * nx + x];
+    phiux = ld(io.phiu_in, (unsigned)(y * nx + x));
+    phiuy = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
   }
   int hr = 0, hc = 0;
   bool halo = false;
@@ -414,14 +431,14 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
   for (int j = t; j < RX * RY; j += NT) {
     const int r = j / RX, c = j - (j / RX) * RX;
     const int gy = min(max(y0 + r - 2, 0), ny - 1);
-    s_ref[r][c] = io.ref_in[gy * nx + wrapx(x0 + c - 3, nx)];
+    s_ref[r][c] = ld(io.ref_in, (unsigned)(gy * nx + wrapx(x0 + c - 3, nx)));
   }
   for (int j = t; j < LX * LY; j += NT) {
     const int r = j / LX, c = j - (j / LX) * LX;
     const int gy = min(max(y0 + r - 1, 0), ny - 1);
     const int kk = gy * nx + wrapx(x0 + c - 2, nx);
-    s_p[r][c] = io.p_in[kk];
-    s_S[r][c] = io.S_in[kk];
+    s_p[r][c] = ld(io.p_in, (unsigned)kk);
+    s_S[r][c] = ld(io.S_in, (unsigned)kk);
   }
   __syncthreads();
 
@@ -489,139 +506,192 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
   update_node<FIELDS>(P, io, m, f, phiux, phiuy, d, k);
 }
 
-// Sliding-window variant for large grids.  A workgroup of TX lanes owns a
-// TX-wide strip of up to SY rows and walks it upwards: each iteration
-// rebuilds the macroscopic quantities of the row above the one it updates
-// into 4-slot LDS rings (phi - 1, rho, f_s^H with two halo columns; lagged p
-// and S with one; phi_ref with three), then updates its row.  Every
-// population is fetched once as the window passes, so the only redundant
-// work is four halo columns per strip and one extra row at the strip start.
-// Arithmetic is shared with k_step, so both give bit-identical results.
-template <int TX, int SY, bool FIELDS>
-__global__ __launch_bounds__(TX) void k_column(KParams P, StepIO io, int nsx, int nstrips,
-                                               int tiles_per_xcd) {
-  constexpr int LW = TX + 4;  // phi/rho/f_s^H: columns x0-2 .. x0+TX+1
-  constexpr int LP = TX + 2;  // p/S:           columns x0-1 .. x0+TX
-  constexpr int LR = TX + 6;  // phi_ref:       columns x0-3 .. x0+TX+2
-  __shared__ float s_phi[4][LW];
-  __shared__ float s_rho[4][LW];
-  __shared__ float s_fsH[4][LW];
+// Sliding-window variant for large grids.  A workgroup is one wavefront
+// whose 64 lanes own 64 consecutive columns: 60 that it updates and two
+// halo columns on each side whose macroscopic quantities it only rebuilds.
+// It walks a strip of up to SY rows upwards.  Each iteration rebuilds the
+// row above the one it updates into 4-slot LDS rings (phi - 1, rho, f_s^H;
+// lagged p and S; phi_ref), then updates its row.  Loads run one row ahead
+// (software pipelining), every population is fetched once as the window
+// passes, and a lane holds only raw inputs across iterations: the node
+// macros of the row being updated are recomputed from them.  Arithmetic is
+// shared with k_step, so both give bit-identical results.
+constexpr int CW = 64;        // lanes per strip
+constexpr int CI = CW - 4;    // columns updated per strip
+
+struct RawNode {
+  float g[9], h[9], fprev;
+};
+
+template <int SY, bool FIELDS>
+__global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx, int nstrips,
+                                                  int tiles_per_xcd, int mode) {
+  constexpr int LR = CW + 2;  // phi_ref: columns x0-3 .. x0+CW-2
+  constexpr int LP = CW - 2;  // p/S:     columns x0-1 .. x0+CW-4
+  __shared__ float s_phi[4][CW];  // lane t <-> column x0 - 2 + t
+  __shared__ float s_rho[4][CW];
+  __shared__ float s_fsH[4][CW];
   __shared__ float s_p[4][LP];
   __shared__ float s_S[4][LP];
   __shared__ float s_ref[4][LR];
 
   const float* __restrict__ A = io.A;
-  const int b = blockIdx.x;
-  const int strip = tiles_per_xcd > 0 ? (b & 7) * tiles_per_xcd + (b >> 3) : b;
-  if (strip >= nstrips) return;  // whole workgroup leaves before any barrier
+  const int strip = map_tile(blockIdx.x, mode, tiles_per_xcd);
+  if (strip >= nstrips) return;
   const int nx = P.nx, ny = P.ny;
-  const int x0 = (strip % nsx) * TX, y0 = (strip / nsx) * SY;
+  const int x0 = (strip % nsx) * CI, y0 = (strip / nsx) * SY;
   const int yend = min(y0 + SY, ny);
   const int t = threadIdx.x;
-  const int x = x0 + t;
-  const int xw = wrapx(x, nx);
-  const bool xin = x < nx;
-  const bool hl = t < 4;                // lanes 0..3 also rebuild one halo column
-  const int hc = t < 2 ? t : TX + t;    // LDS columns 0, 1, TX+2, TX+3
-  const int hxw = wrapx(x0 + hc - 2, nx);
+  const int xg = x0 - 2 + t;              // this lane's column (unwrapped)
+  const int xw = wrapx(xg, nx);
+  const bool own = t >= 2 && t < CW - 2 && xg < nx;  // updated by this strip
+  const int xm = xw == 0 ? nx - 1 : xw - 1;
+  const int xp = xw == nx - 1 ? 0 : xw + 1;
+  // columns of the reference and p/S rows this lane loads (second entry for lanes 0, 1)
+  const int rj1 = t + CW;
+  const int rx0 = wrapx(x0 - 3 + t, nx), rx1 = wrapx(x0 - 3 + rj1, nx);
+  const int px0 = wrapx(x0 - 1 + t, nx);
 #define SLOT(gy) (((gy) + 4) & 3)
+#define CLAMPY(gy) min(max((gy), 0), ny - 1)
 
-  // one row of phi_ref (clamped beyond the walls, where it is never read)
-  // and of the lagged p, S (rows beyond a wall copy the adjacent row)
-  auto load_ref = [&](int gy) {
-    const int cy = min(max(gy, 0), ny - 1);
-    for (int j = t; j < LR; j += TX) s_ref[SLOT(gy)][j] = io.ref_in[cy * nx + wrapx(x0 + j - 3, nx)];
+  auto load_raw = [&](int gy, RawNode& w) {
+    pull9<0>(A, P, xw, gy, xm, xp, w.g);
+    pull9<2>(A, P, xw, gy, xm, xp, w.h);
+    w.fprev = io.fsH_in[gy * nx + xw];
   };
-  auto load_pS = [&](int gy) {
-    const int cy = min(max(gy, 0), ny - 1);
-    for (int j = t; j < LP; j += TX) {
-      const int kk = cy * nx + wrapx(x0 + j - 1, nx);
-      s_p[SLOT(gy)][j] = io.p_in[kk];
-      s_S[SLOT(gy)][j] = io.S_in[kk];
-    }
-  };
-  // g of a node in row gy, LDS column c, re-expressed in its own reference
-  auto rebase = [&](float q[9], int gy, int c) -> float {
+  auto rebase = [&](float q[9], int gy) -> float {
 #pragma clang fp contract(off)
     const bool bot = (gy == 0), top = (gy == ny - 1);
-    const float rself = s_ref[SLOT(gy)][c + 1];
+    const float rself = s_ref[SLOT(gy)][t + 1];
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const int cy = cyv(i), cx = cxv(i);
       const bool wall = (cy > 0 && bot) || (cy < 0 && top);
-      const float rs = wall ? rself : s_ref[SLOT(gy - cy)][c + 1 - cx];
+      const float rs = wall ? rself : s_ref[SLOT(gy - cy)][t + 1 - cx];
       q[i] += wt(i) * (rs - rself);
     }
     return rself;
   };
-  // macroscopic quantities of row gy into the rings; the lane's own node is
-  // returned in `mine`, lanes 0..3 also fill one halo column each
-  auto macro_row = [&](int gy, Macro& mine) {
-    if (hl) {
-      Macro mh;
-      load_node(A, io.fsH_in, P, hxw, gy, mh);
-      const float rs = rebase(mh.g, gy, hc);
-      finish_macro(P, rs, mh);
-      s_phi[SLOT(gy)][hc] = (mh.r - 1.0f) + mh.dl;
-      s_rho[SLOT(gy)][hc] = mh.rho;
-      s_fsH[SLOT(gy)][hc] = mh.fsH;
+  // node macros of row gy from raw inputs (copied, so the raw set survives)
+  auto macro_of = [&](const RawNode& w, int gy, Macro& m) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      m.g[i] = w.g[i];
+      m.h[i] = w.h[i];
     }
-    load_node(A, io.fsH_in, P, xw, gy, mine);
-    const float rs = rebase(mine.g, gy, t + 2);
-    finish_macro(P, rs, mine);
-    s_phi[SLOT(gy)][t + 2] = (mine.r - 1.0f) + mine.dl;
-    s_rho[SLOT(gy)][t + 2] = mine.rho;
-    s_fsH[SLOT(gy)][t + 2] = mine.fsH;
+    m.fprev = w.fprev;
+    const float rs = rebase(m.g, gy);
+    finish_macro(P, rs, m);
   };
-  // wetting ghost row gg from rows ga (adjacent) and gb (next)
+  auto to_rings = [&](const Macro& m, int gy) {
+    s_phi[SLOT(gy)][t] = (m.r - 1.0f) + m.dl;
+    s_rho[SLOT(gy)][t] = m.rho;
+    s_fsH[SLOT(gy)][t] = m.fsH;
+  };
   auto ghost_row = [&](int gg, int ga, int gb, float tv) {
-    for (int c = 1 + t; c < LW - 1; c += TX) {
-      const float pg = wetting_ghost(s_phi[SLOT(ga)][c - 1], s_phi[SLOT(ga)][c], s_phi[SLOT(ga)][c + 1],
-                                     s_phi[SLOT(gb)][c - 1], s_phi[SLOT(gb)][c + 1], tv);
+    if (t >= 1 && t < CW - 1) {
+      const float pg = wetting_ghost(s_phi[SLOT(ga)][t - 1], s_phi[SLOT(ga)][t], s_phi[SLOT(ga)][t + 1],
+                                     s_phi[SLOT(gb)][t - 1], s_phi[SLOT(gb)][t + 1], tv);
       const float pcg = clamp01(1.0f + pg);
-      s_phi[SLOT(gg)][c] = pg;
-      s_rho[SLOT(gg)][c] = mix3(pcg * s_fsH[SLOT(ga)][c], pcg, P.rho_s, P.rho_l, P.rho_g);
+      s_phi[SLOT(gg)][t] = pg;
+      s_rho[SLOT(gg)][t] = mix3(pcg * s_fsH[SLOT(ga)][t], pcg, P.rho_s, P.rho_l, P.rho_g);
     }
   };
 
-  // prologue: rows y0-1 (halo row below the strip, if inside the domain) and y0
-  for (int gy = y0 - 2; gy <= y0 + 1; ++gy) load_ref(gy);
-  load_pS(y0 - 1);
-  load_pS(y0);
-  __syncthreads();
-  Macro mc;
-  if (y0 >= 1) {
-    Macro tmp;
-    macro_row(y0 - 1, tmp);
+  // ---- prologue ------------------------------------------------------------
+  for (int gy = y0 - 2; gy <= y0 + 1; ++gy) {
+    const int cy = CLAMPY(gy);
+    s_ref[SLOT(gy)][t] = io.ref_in[cy * nx + rx0];
+    if (rj1 < LR) s_ref[SLOT(gy)][rj1] = io.ref_in[cy * nx + rx1];
   }
-  macro_row(y0, mc);
+  for (int gy = y0 - 1; gy <= y0; ++gy) {
+    if (t < LP) {
+      const int kk = CLAMPY(gy) * nx + px0;
+      s_p[SLOT(gy)][t] = io.p_in[kk];
+      s_S[SLOT(gy)][t] = io.S_in[kk];
+    }
+  }
+  RawNode rawC, rawL;  // rows y (being updated) and y+1 (lead)
+  if (y0 >= 1) load_raw(y0 - 1, rawL);
+  load_raw(y0, rawC);
+  __syncthreads();
+  {
+    Macro m;
+    if (y0 >= 1) {
+      macro_of(rawL, y0 - 1, m);
+      to_rings(m, y0 - 1);
+    }
+    macro_of(rawC, y0, m);
+    to_rings(m, y0);
+  }
+  // first prefetch: lead row y0+1, reference row y0+2, p/S row y0+1, f of row y0
+  if (y0 + 1 < ny) load_raw(y0 + 1, rawL);
+  float refV0, refV1 = 0.0f, pV = 0.0f, SV = 0.0f;
+  {
+    const int cy = CLAMPY(y0 + 2);
+    refV0 = io.ref_in[cy * nx + rx0];
+    if (rj1 < LR) refV1 = io.ref_in[cy * nx + rx1];
+    if (t < LP) {
+      const int kk = CLAMPY(y0 + 1) * nx + px0;
+      pV = io.p_in[kk];
+      SV = io.S_in[kk];
+    }
+  }
+  float fC[9], puxC = 0.0f, puyC = 0.0f;
+  if (own) {
+    pull9<1>(A, P, xw, y0, xm, xp, fC);
+    puxC = io.phiu_in[y0 * nx + xw];
+    puyC = io.phiu_in[P.plane + y0 * nx + xw];
+  }
   __syncthreads();
 
   for (int y = y0; y < yend; ++y) {
-    // this node's flow populations and (phi u)^{n-1}, in flight meanwhile
-    float f[9], phiux = 0.0f, phiuy = 0.0f;
-    const int k = y * nx + xw;
-    if (xin) {
-      const int xm = x == 0 ? nx - 1 : x - 1;
-      const int xp = x == nx - 1 ? 0 : x + 1;
-      pull9<1>(A, P, x, y, xm, xp, f);
-      phiux = io.phiu_in[k];
-      phiuy = io.phiu_in[P.plane + k];
-    }
-    load_ref(y + 2);
-    load_pS(y + 1);
-    __syncthreads();
-    Macro ml;
     const int yl = y + 1;
-    if (yl < ny) macro_row(yl, ml);
+    // (1) prefetched LDS rows
+    s_ref[SLOT(y + 2)][t] = refV0;
+    if (rj1 < LR) s_ref[SLOT(y + 2)][rj1] = refV1;
+    if (t < LP) {
+      s_p[SLOT(yl)][t] = pV;
+      s_S[SLOT(yl)][t] = SV;
+    }
+    __syncthreads();
+    // (2) lead row macros into the rings
+    if (yl < ny) {
+      Macro m;
+      macro_of(rawL, yl, m);
+      to_rings(m, yl);
+    }
     __syncthreads();
     const bool gtop = (yl == ny), gbot = (y == 0);
     if (gtop) ghost_row(ny, ny - 1, ny - 2, P.tan_t);
     if (gbot) ghost_row(-1, 0, 1, P.tan_b);
     if (gtop || gbot) __syncthreads();
-    if (xin) {
+    // (3) prefetch the next iteration's inputs
+    const bool more = yl < yend;
+    RawNode rawN;
+    if (more && y + 2 < ny) load_raw(y + 2, rawN);
+    if (more) {
+      const int cy = CLAMPY(y + 3);
+      refV0 = io.ref_in[cy * nx + rx0];
+      if (rj1 < LR) refV1 = io.ref_in[cy * nx + rx1];
+      if (t < LP) {
+        const int kk = CLAMPY(y + 2) * nx + px0;
+        pV = io.p_in[kk];
+        SV = io.S_in[kk];
+      }
+    }
+    float fN[9], puxN = 0.0f, puyN = 0.0f;
+    if (own && more) {
+      pull9<1>(A, P, xw, yl, xm, xp, fN);
+      puxN = io.phiu_in[yl * nx + xw];
+      puyN = io.phiu_in[P.plane + yl * nx + xw];
+    }
+    // (4) update row y
+    if (own) {
+      Macro mc;
+      macro_of(rawC, y, mc);
       const int a = SLOT(y - 1), c0 = SLOT(y), u = SLOT(y + 1);
-      const int c = t + 2, cp = t + 1;
+      const int c = t, cp = t - 1;
       Grads d;
       stencil(s_phi[c0][c], s_phi[c0][c + 1], s_phi[c0][c - 1], s_phi[u][c], s_phi[a][c], s_phi[u][c + 1],
               s_phi[u][c - 1], s_phi[a][c - 1], s_phi[a][c + 1], d.phx, d.phy, &d.lphi);
@@ -631,11 +701,19 @@ __global__ __launch_bounds__(TX) void k_column(KParams P, StepIO io, int nsx, in
               s_p[u][cp - 1], s_p[a][cp - 1], s_p[a][cp + 1], d.px, d.py, nullptr);
       stencil(s_S[c0][cp], s_S[c0][cp + 1], s_S[c0][cp - 1], s_S[u][cp], s_S[a][cp], s_S[u][cp + 1],
               s_S[u][cp - 1], s_S[a][cp - 1], s_S[a][cp + 1], d.Sx, d.Sy, nullptr);
-      update_node<FIELDS>(P, io, mc, f, phiux, phiuy, d, k);
+      update_node<FIELDS>(P, io, mc, fC, puxC, puyC, d, y * nx + xw);
     }
-    mc = ml;
+    __syncthreads();  // rings are overwritten from the next iteration on
+    // (5) rotate the pipeline
+    rawC = rawL;
+    rawL = rawN;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fC[i] = fN[i];
+    puxC = puxN;
+    puyC = puyN;
   }
 #undef SLOT
+#undef CLAMPY
 }
 
 // Initial state (no time-stepping yet): u = 0, p = 0, liquid fraction 1,
@@ -736,7 +814,7 @@ int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int
   const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
   const int ntiles = ntx * nty;
   int tpx = 0, grid = ntiles;
-  if (xcd) {
+  if (xcd == 1) {
     tpx = (ntiles + 7) / 8;
     grid = 8 * tpx;
   }
@@ -744,18 +822,18 @@ int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int
   StepIO io{S.pops[cur], S.pops[nxt], S.phiu[cur], S.phiu[nxt], S.ref[cur], S.ref[nxt],
             S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur], S.S[nxt], S.fields};
   if (fields_only)
-    hipLaunchKernelGGL((k_step<TX, TY, true>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx);
+    hipLaunchKernelGGL((k_step<TX, TY, true>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx, xcd);
   else
-    hipLaunchKernelGGL((k_step<TX, TY, false>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx);
+    hipLaunchKernelGGL((k_step<TX, TY, false>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx, xcd);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int TX, int SY>
+template <int SY>
 int launch_column(const KParams& P, const State& S, int cur, bool fields_only, int xcd, hipStream_t st) {
-  const int nsx = (P.nx + TX - 1) / TX, nsy = (P.ny + SY - 1) / SY;
+  const int nsx = (P.nx + CI - 1) / CI, nsy = (P.ny + SY - 1) / SY;
   const int nstrips = nsx * nsy;
   int tpx = 0, grid = nstrips;
-  if (xcd) {
+  if (xcd == 1) {
     tpx = (nstrips + 7) / 8;
     grid = 8 * tpx;
   }
@@ -763,9 +841,9 @@ int launch_column(const KParams& P, const State& S, int cur, bool fields_only, i
   StepIO io{S.pops[cur], S.pops[nxt], S.phiu[cur], S.phiu[nxt], S.ref[cur], S.ref[nxt],
             S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur], S.S[nxt], S.fields};
   if (fields_only)
-    hipLaunchKernelGGL((k_column<TX, SY, true>), dim3(grid), dim3(TX), 0, st, P, io, nsx, nstrips, tpx);
+    hipLaunchKernelGGL((k_column<SY, true>), dim3(grid), dim3(CW), 0, st, P, io, nsx, nstrips, tpx, xcd);
   else
-    hipLaunchKernelGGL((k_column<TX, SY, false>), dim3(grid), dim3(TX), 0, st, P, io, nsx, nstrips, tpx);
+    hipLaunchKernelGGL((k_column<SY, false>), dim3(grid), dim3(CW), 0, st, P, io, nsx, nstrips, tpx, xcd);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -792,11 +870,11 @@ int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int
     case 4:
       return launch_tile<128, 4>(P, S, cur, fields_only, xcd_remap, st);
     case 5:
-      return launch_column<64, 32>(P, S, cur, fields_only, xcd_remap, st);
+      return launch_column<32>(P, S, cur, fields_only, xcd_remap, st);
     case 6:
-      return launch_column<64, 64>(P, S, cur, fields_only, xcd_remap, st);
+      return launch_column<64>(P, S, cur, fields_only, xcd_remap, st);
     case 7:
-      return launch_column<128, 32>(P, S, cur, fields_only, xcd_remap, st);
+      return launch_column<128>(P, S, cur, fields_only, xcd_remap, st);
     default:
       return launch_tile<64, 4>(P, S, cur, fields_only, xcd_remap, st);
   }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 FIELD_BITS = {"phi": 0, "T": 1, "ux": 2, "uy": 3, "p": 4, "fs": 5, "fl": 6, "rho": 7, "H": 8, "mdot": 9}
 TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4,
-                 "strip64x32": 5, "strip64x64": 6, "strip128x32": 7}
+                 "strip60x32": 5, "strip60x64": 6, "strip60x128": 7}
 TILE_NAMES = {v: k for k, v in TILE_VARIANTS.items()}
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
@@ -158,14 +158,15 @@ class Solver:
             self.L.lbm_destroy(h)
             self._h = None
 
-    def set_launch(self, tile: str = "64x4", xcd_remap: bool = True):
-        self._check(self.L.lbm_set_launch(self._h, TILE_VARIANTS[tile], int(bool(xcd_remap))), "lbm_set_launch")
+    def set_launch(self, tile: str = "64x4", xcd_remap=1):
+        """xcd_remap: 0 round-robin dispatch over the XCDs, 1 one contiguous band per XCD."""
+        self._check(self.L.lbm_set_launch(self._h, TILE_VARIANTS[tile], int(xcd_remap)), "lbm_set_launch")
 
     def autotune(self, reps: int = 20):
         """Pick the fastest launch shape for this grid; returns (tile, xcd_remap)."""
         v, x = C.c_int32(), C.c_int32()
         self._check(self.L.lbm_autotune(self._h, int(reps), C.byref(v), C.byref(x)), "lbm_autotune")
-        return TILE_NAMES[v.value], bool(x.value)
+        return TILE_NAMES[v.value], int(x.value)
 
     def step(self, n: int = 1):
         self._check(self.L.lbm_step(self._h, int(n)), "lbm_step")

@@ -101,7 +101,7 @@ def test_within_the_methods_own_sensitivity(oracle_mod, seed, steps):
 
 @pytest.mark.parametrize("nx,ny,tile", [(70, 13, "64x4"), (70, 13, "32x8"), (130, 19, "64x8"),
                                         (3, 3, "64x4"), (5, 4, "32x8"), (67, 9, "64x4"),
-                                        (70, 37, "strip64x32"), (3, 3, "strip64x32"), (131, 20, "strip128x32")])
+                                        (70, 37, "strip60x32"), (3, 3, "strip60x32"), (131, 20, "strip60x128")])
 def test_ragged_and_tiny_grids(oracle_mod, nx, ny, tile):
     p = W.default_params(nx, ny, rho_s=0.88, theta_bottom_deg=65.0, theta_top_deg=115.0,
                          gx=2e-6, gy=-5e-6, cp_s=0.7, k_s=0.2, cp_g=0.9, k_g=0.05)
@@ -131,8 +131,8 @@ def test_tile_shapes_and_xcd_mapping_are_bitwise_identical():
     lbm = _gpu()
     p, phi0, T0, _ = W.workload("sessile128", seed=0)
     ref = None
-    for tile in ("64x4", "32x8", "64x8", "64x16", "128x4", "strip64x32", "strip64x64", "strip128x32"):
-        for xcd in (True, False):
+    for tile in ("64x4", "32x8", "64x8", "64x16", "128x4", "strip60x32", "strip60x64", "strip60x128"):
+        for xcd in (0, 1):
             print(f"tile={tile} xcd={xcd}", flush=True)
             g = lbm.Solver(p, phi0, T0)
             g.set_launch(tile, xcd)
@@ -177,8 +177,8 @@ def test_sum_phi_conserved_on_gpu():
     assert d["sum_solid"] > 1.0
 
 
-@pytest.mark.parametrize("nx,ny,tile", [(131, 70, "strip128x32"), (5, 66, "strip64x64"), (64, 66, "strip64x64"),
-                                        (200, 33, "strip64x32"), (3, 97, "strip64x32")])
+@pytest.mark.parametrize("nx,ny,tile", [(131, 70, "strip60x128"), (5, 66, "strip60x64"), (64, 66, "strip60x64"),
+                                        (200, 33, "strip60x32"), (3, 97, "strip60x32"), (61, 129, "strip60x128")])
 def test_strips_equal_tiles_bitwise_on_ragged_grids(nx, ny, tile):
     """The column-strip kernels must reproduce the 2-D tile kernel bit for
     bit on grids that are ragged in both directions (and narrower than a
