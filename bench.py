@@ -23,7 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-BYTES_PER_NODE = 256  # 27 populations + 5 history values, FP32, read and written once
+# algorithmic bytes per node update: 27 populations and 5 FP32 history
+# values, each read and written once
+BYTES_PER_NODE = {"fp32": 27 * 8 + 40, "fp16": 27 * 4 + 40, "bf16": 27 * 4 + 40}
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS (φ+flow+T lattices), % HBM peak; batched sweep droplets/s vs plain"
 
@@ -36,10 +38,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, storage: str = "fp32"):
     """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs stored
     under profiles/, valid only for the kernel source they were taken on."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    tag = workload if storage == "fp32" else f"{workload}_{storage}"
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -100,6 +103,10 @@ def main():
     ap.add_argument("--tile", default="auto", help="auto (library autotuner) or 64x4/32x8/64x8/64x16/128x4")
     ap.add_argument("--no-xcd", action="store_true", help="round-robin workgroup dispatch (xcd mode 0)")
     ap.add_argument("--xcd", type=int, default=None, help="workgroup-to-XCD mapping mode 0/1 (fixed tiles only)")
+    ap.add_argument("--storage", default="fp32", choices=("fp32", "fp16", "bf16"),
+                    help="population storage format (compute is FP32 in every case)")
+    ap.add_argument("--no-storage-variants", dest="storage_variants", action="store_false",
+                    help="skip the FP16/BF16 storage runs on the 4096x2048 probe")
     ap.add_argument("--probe-steps", type=int, default=100, help="steps on the 4096x2048 grid (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle timing budget (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -126,6 +133,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     params, phi0, T0, meta = W.workload(args.workload, seed=0)
+    params["storage"] = lbm.STORAGE[args.storage]
+    bpn = BYTES_PER_NODE[args.storage]
     N = params["nx"] * params["ny"]
     solver = lbm.Solver(params, phi0, T0)
     tile, xcd = pick_launch(solver, args)
@@ -137,8 +146,8 @@ def main():
         sys.exit(3)
     mlups = N * args.steps / secs / 1e6
     launch_s = secs / args.steps
-    achieved = BYTES_PER_NODE * N / launch_s / 1e9
-    traffic = measured_traffic(args.workload)
+    achieved = bpn * N / launch_s / 1e9
+    traffic = measured_traffic(args.workload, args.storage)
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -155,15 +164,15 @@ def main():
         "config": {
             "workload": f"{args.workload}: {params['nx']}x{params['ny']} sessile droplet R={meta['R']:g} lu, "
                         f"theta {meta['theta']:g}, rho_s/rho_l {params['rho_s']:g}, Ste 0.1, Bond 0.1, "
-                        "W=4, M=0.1, rho_l/rho_g=1000, FP32 populations (planar 2-D)",
-            "nx": params["nx"], "ny": params["ny"], "tile": tile, "xcd_remap": xcd,
+                        f"W=4, M=0.1, rho_l/rho_g=1000, {args.storage.upper()} populations (planar 2-D)",
+            "nx": params["nx"], "ny": params["ny"], "tile": tile, "xcd_remap": xcd, "storage": args.storage,
             "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_step (fused collide + pull-stream)",
-            "bytes_per_launch": BYTES_PER_NODE * N,
+            "bytes_per_launch": bpn * N,
             "note": "working set fits the 256 MB Infinity Cache at this size; see hbm_probe",
         },
         "wall_s": round(wall, 3),
@@ -172,21 +181,40 @@ def main():
     torch.cuda.empty_cache()
     if args.probe_steps > 0:
         pp, pphi, pT, _ = W.workload("probe4096", seed=0)
+        pp["storage"] = params["storage"]
         Np = pp["nx"] * pp["ny"]
         ps = lbm.Solver(pp, pphi, pT)
         ptile, pxcd = pick_launch(ps, args)
         psecs, _ = time_steps(ps, args.probe_steps, 10)
         pl = psecs / args.probe_steps
-        pach = BYTES_PER_NODE * Np / pl / 1e9
+        pach = bpn * Np / pl / 1e9
         out["hbm_probe"] = {
             "workload": "probe4096: 4096x2048 sessile droplet R=640 (same physics), 2.3 GB working set",
             "steps": args.probe_steps, "MLUPS": round(Np * args.probe_steps / psecs / 1e6, 1),
             "tile": ptile, "xcd_remap": pxcd,
             "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("probe4096"),
+            "traffic": measured_traffic("probe4096", args.storage),
         }
         del ps
         torch.cuda.empty_cache()
+        # the same probe with 16-bit population storage (FP32 compute)
+        if args.storage == "fp32" and args.storage_variants:
+            out["storage_variants"] = {}
+            for st in ("fp16", "bf16"):
+                pp["storage"] = lbm.STORAGE[st]
+                vs = lbm.Solver(pp, pphi, pT)
+                vtile, vxcd = pick_launch(vs, args)
+                vsecs, _ = time_steps(vs, args.probe_steps, 10)
+                vl = vsecs / args.probe_steps
+                vach = BYTES_PER_NODE[st] * Np / vl / 1e9
+                out["storage_variants"][st] = {
+                    "workload": "probe4096", "MLUPS": round(Np * args.probe_steps / vsecs / 1e6, 1),
+                    "tile": vtile, "xcd_remap": vxcd, "bytes_per_node": BYTES_PER_NODE[st],
+                    "achieved": round(vach, 1), "unit": "GB/s", "frac": round(vach / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic("probe4096", st),
+                }
+                del vs
+                torch.cuda.empty_cache()
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(params, phi0, T0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -45,7 +45,11 @@ enum {
   LBM_ESTATE = -5      /* checkpoint does not match this context */
 };
 
-enum { LBM_STORE_FP32 = 0 };
+enum {
+  LBM_STORE_FP32 = 0,        /* populations stored as FP32 */
+  LBM_STORE_FP16_SHIFT = 1,  /* shifted populations rounded to FP16 (per-lattice power-of-two scale) */
+  LBM_STORE_BF16_SHIFT = 2   /* shifted populations rounded to BF16 */
+};
 
 /* Physical parameters in lattice units.  Mixture properties follow Eq. (1)
  * with subscripts s (solid), l (liquid), g (gas). */
@@ -129,7 +133,8 @@ const char* lbm_last_error(void);
 /* Launch shape of the fused step.  tile_variant 0..4: 2-D tiles of 64x4
  * (default), 32x8, 64x8, 64x16, 128x4 nodes per workgroup, halo macros
  * recomputed per tile; 5..7: column strips 60 nodes wide and 32, 64, 128
- * rows high, walked row by row (halo only at the strip sides, for large grids).
+ * rows high, walked row by row (halo only at the strip sides; FP32 storage
+ * only, LBM_EINVAL otherwise).
  * xcd_remap: 0 keeps the hardware's round-robin of workgroups over the 8
  * XCDs; 1 gives each XCD one contiguous band of tiles (its L2 then serves
  * the halo re-reads).  Results are bitwise identical for every choice. */

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/lbm.h: parameter validation,
 // workspace layout, launches on the caller's stream, read-back and
 // checkpointing.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -27,7 +28,7 @@ int dev_error(hipError_t e, const char* what) {
 
 constexpr double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 constexpr int kPops = 27;
-constexpr int kAuxPlanes = 4 + 8;  // (phi u) x/y, phi_ref, f_s^H, p, S, all double-buffered
+constexpr int kAuxPlanes = 4 + 8;  // (phi u) x/y, node references, f_s^H, p, S, all double-buffered
 constexpr int kStatePlanes = kPops + 6;  // checkpointed planes
 constexpr int64_t kMagic = 0x4c424d4750555331LL;
 
@@ -59,9 +60,13 @@ int validate(const lbm_params* p) {
   if (!(p->theta_bottom_deg > 0 && p->theta_bottom_deg < 180)) return LBM_EINVAL;
   if (!(p->theta_top_deg > 0 && p->theta_top_deg < 180)) return LBM_EINVAL;
   if (p->st_solid_mask != 0 && p->st_solid_mask != 1) return LBM_EINVAL;
-  if (p->storage != LBM_STORE_FP32) return LBM_EINVAL;
+  if (p->storage != LBM_STORE_FP32 && p->storage != LBM_STORE_FP16_SHIFT && p->storage != LBM_STORE_BF16_SHIFT)
+    return LBM_EINVAL;
   return LBM_OK;
 }
+
+size_t pop_bytes(const lbm_params* p) { return p->storage == LBM_STORE_FP32 ? 4 : 2; }
+bool is_strip(int tile_variant) { return tile_variant >= 5; }
 
 long long plane_floats(const lbm_params* p) {
   const long long n = (long long)p->nx * p->ny;
@@ -72,7 +77,25 @@ size_t part_bytes() { return (size_t)(lbmk::RED_BLOCKS + 1) * lbmk::RED_NVAL * s
 
 size_t ws_size(const lbm_params* p) {
   const long long pl = plane_floats(p);
-  return (size_t)(2 * kPops + kAuxPlanes + lbmk::NFIELD) * pl * sizeof(float) + part_bytes();
+  return (size_t)2 * kPops * pl * pop_bytes(p) + (size_t)(kAuxPlanes + lbmk::NFIELD) * pl * sizeof(float) +
+         part_bytes();
+}
+
+// FP16 scales (powers of two).  g and the shifted h stay O(1) and f is
+// O(pressure + rho u); the scales lift their small values out of the FP16
+// subnormals while leaving a wide margin below its maximum 65504: |g| < 256,
+// |f| < 64, and h within 16x of the largest enthalpy excess the parameters
+// and the initial temperature imply.
+void fp16_scales(const lbm_params& p, double tspan, lbmk::KParams& K) {
+  const double cpmax = std::max(std::max(p.cp_l, p.cp_g), std::max(p.cp_s, p.cp_ref));
+  const double hmax = cpmax * std::max(tspan, 1.0) + p.latent;
+  double sh = 16.0;
+  while (sh > 1.0 / 1024 && sh * hmax * 16.0 > 65504.0) sh *= 0.5;
+  const double sc[3] = {256.0, 1024.0, sh};
+  for (int j = 0; j < 3; ++j) {
+    K.sc_st[j] = (float)sc[j];
+    K.sc_ld[j] = (float)(1.0 / sc[j]);
+  }
 }
 
 }  // namespace
@@ -127,6 +150,8 @@ void fill_kparams(lbm_ctx* c) {
   K.bq_coef = (float)(p.bq_rho0 * p.bq_beta);
   K.bq_Tref = (float)p.bq_Tref;
   K.chi = (float)p.st_solid_mask;
+  K.storage = p.storage;
+  for (int j = 0; j < 3; ++j) K.sc_st[j] = K.sc_ld[j] = 1.0f;
   c->I.cp_l = p.cp_l;
   c->I.cp_g = p.cp_g;
   c->I.cp_ref = p.cp_ref;
@@ -137,10 +162,11 @@ void fill_kparams(lbm_ctx* c) {
 
 void carve(lbm_ctx* c) {
   const long long pl = c->K.plane;
-  float* base = (float*)c->ws;
+  const size_t popbuf = (size_t)kPops * pl * pop_bytes(&c->P);  // multiple of 256 bytes
+  char* base = (char*)c->ws;
   c->S.pops[0] = base;
-  c->S.pops[1] = base + kPops * pl;
-  float* aux = base + 2 * kPops * pl;
+  c->S.pops[1] = base + popbuf;
+  float* aux = (float*)(base + 2 * popbuf);
   c->S.phiu[0] = aux;
   c->S.phiu[1] = aux + 2 * pl;
   c->S.fsH[0] = aux + 4 * pl;
@@ -158,6 +184,31 @@ void carve(lbm_ctx* c) {
 int run_fields(lbm_ctx* c) {
   if (lbmk::launch_step(c->K, c->S, c->cur, true, c->tile_variant, c->xcd, c->stream))
     return dev_error(hipGetLastError(), "fields kernel launch");
+  return LBM_OK;
+}
+
+// Host <-> device copy of the checkpointed planes of the current buffer:
+// the populations in their storage format, then the FP32 history planes.
+int copy_state(lbm_ctx* c, char* host, bool save) {
+  const size_t N = (size_t)c->P.nx * c->P.ny;
+  const size_t pb = pop_bytes(&c->P);
+  void* dev[kStatePlanes];
+  for (int i = 0; i < kPops; ++i) dev[i] = (char*)c->S.pops[c->cur] + (size_t)i * c->K.plane * pb;
+  dev[kPops + 0] = c->S.phiu[c->cur];
+  dev[kPops + 1] = c->S.phiu[c->cur] + c->K.plane;
+  dev[kPops + 2] = c->S.fsH[c->cur];
+  dev[kPops + 3] = c->S.p[c->cur];
+  dev[kPops + 4] = c->S.S[c->cur];
+  dev[kPops + 5] = c->S.ref[c->cur];
+  for (int i = 0; i < kStatePlanes; ++i) {
+    const size_t nb = N * (i < kPops ? pb : sizeof(float));
+    if (save)
+      LBM_CK(hipMemcpyAsync(host, dev[i], nb, hipMemcpyDeviceToHost, c->stream));
+    else
+      LBM_CK(hipMemcpyAsync(dev[i], host, nb, hipMemcpyHostToDevice, c->stream));
+    host += nb;
+  }
+  LBM_CK(hipStreamSynchronize(c->stream));
   return LBM_OK;
 }
 
@@ -194,6 +245,15 @@ int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_
       g_last_error = "non-finite initial field";
       return LBM_EINVAL;
     }
+  // Temperatures stay within the initial and wall values (maximum
+  // principle); 16-bit storage keeps T - T_m of every node as an FP16
+  // reference, which needs that span well inside FP16's range.
+  double tspan = std::fabs(p->T_bottom - p->T_melt);
+  for (long long k = 0; k < N; ++k) tspan = std::max(tspan, std::fabs(T0[k] - p->T_melt));
+  if (p->storage != LBM_STORE_FP32 && !(tspan < 3.0e4)) {
+    g_last_error = "temperature span too wide for the FP16 node references of 16-bit storage";
+    return LBM_EINVAL;
+  }
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return LBM_ENOMEM;
   c->P = *p;
@@ -208,6 +268,7 @@ int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_
     return dev_error(e, "hipGetDevice");
   }
   fill_kparams(c);
+  if (p->storage == LBM_STORE_FP16_SHIFT) fp16_scales(*p, tspan, c->K);
   if (d_workspace) {
     c->ws = d_workspace;
     c->own_ws = false;
@@ -312,25 +373,34 @@ int lbm_diag(lbm_ctx* c, lbm_diag_t* out) {
 int lbm_pops(lbm_ctx* c, int32_t lattice, double* host_out) {
   if (!c || !host_out || lattice < 0 || lattice > 2) return LBM_EINVAL;
   const long long N = (long long)c->P.nx * c->P.ny;
+  const bool noderef = c->P.storage != LBM_STORE_FP32;
   c->stage.resize(N);
   const double cpr = c->P.cp_ref, Tm = c->P.T_melt;
-  // g is stored relative to w_i phi_ref, the rest h population relative to L f_s^H
-  std::vector<float> fs;
-  if (lattice != 1) {
-    fs.resize(N);
-    LBM_CK(hipMemcpyAsync(fs.data(), lattice == 0 ? c->S.ref[c->cur] : c->S.fsH[c->cur],
-                          N * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-  }
+  // Undo the storage shifts: g is kept relative to w_i phi_ref and the rest h
+  // population relative to L f_s^H (under 16-bit storage the expand kernel
+  // has already added the node references back).
+  std::vector<float> ref1;
+  auto fetch = [&](std::vector<float>& v, const float* d) -> int {
+    v.resize(N);
+    LBM_CK(hipMemcpyAsync(v.data(), d, N * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    return LBM_OK;
+  };
+  int rc = LBM_OK;
+  if (lattice == 0 && !noderef) rc = fetch(ref1, (const float*)c->S.ref[c->cur]);
+  if (lattice == 2) rc = fetch(ref1, c->S.fsH[c->cur]);
+  if (rc) return rc;
+  if (lbmk::launch_expand(c->K, c->S, c->cur, lattice, c->stream))
+    return dev_error(hipGetLastError(), "expand launch");
   for (int i = 0; i < 9; ++i) {
-    LBM_CK(hipMemcpyAsync(c->stage.data(), c->S.pops[c->cur] + (lattice * 9 + i) * c->K.plane,
-                          N * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    LBM_CK(hipMemcpyAsync(c->stage.data(), c->S.fields + i * c->K.plane, N * sizeof(float),
+                          hipMemcpyDeviceToHost, c->stream));
     LBM_CK(hipStreamSynchronize(c->stream));
     double add = 0.0;
     if (lattice == 2) add = i == 0 ? c->Href - cpr * Tm + kW[0] * cpr * Tm : kW[i] * cpr * Tm;
     for (long long k = 0; k < N; ++k) {
       double v = (double)c->stage[k] + add;
-      if (lattice == 2 && i == 0) v -= c->P.latent * (double)fs[k];
-      if (lattice == 0) v += kW[i] * (double)fs[k];  // stored g_i - w_i phi_ref
+      if (lattice == 0 && !noderef) v += kW[i] * (double)ref1[k];
+      if (lattice == 2 && i == 0) v -= c->P.latent * (double)ref1[k];
       host_out[i * N + k] = v;
     }
   }
@@ -340,53 +410,25 @@ int lbm_pops(lbm_ctx* c, int32_t lattice, double* host_out) {
 size_t lbm_state_bytes(const lbm_ctx* c) {
   if (!c) return 0;
   const size_t N = (size_t)c->P.nx * c->P.ny;
-  return 4 * sizeof(int64_t) + (size_t)kStatePlanes * N * sizeof(float);
+  return 4 * sizeof(int64_t) + (size_t)kPops * N * pop_bytes(&c->P) +
+         (size_t)(kStatePlanes - kPops) * N * sizeof(float);
 }
 
 int lbm_save(lbm_ctx* c, void* buf, size_t bytes) {
   if (!c || !buf || bytes < lbm_state_bytes(c)) return LBM_EINVAL;
-  const size_t N = (size_t)c->P.nx * c->P.ny;
-  int64_t hdr[4] = {kMagic, c->P.nx, c->P.ny, c->step};
+  int64_t hdr[4] = {kMagic + c->P.storage, c->P.nx, c->P.ny, c->step};
   char* o = (char*)buf;
   std::memcpy(o, hdr, sizeof(hdr));
-  o += sizeof(hdr);
-  const float* src[kStatePlanes];
-  for (int i = 0; i < kPops; ++i) src[i] = c->S.pops[c->cur] + i * c->K.plane;
-  src[kPops + 0] = c->S.phiu[c->cur];
-  src[kPops + 1] = c->S.phiu[c->cur] + c->K.plane;
-  src[kPops + 2] = c->S.fsH[c->cur];
-  src[kPops + 3] = c->S.p[c->cur];
-  src[kPops + 4] = c->S.S[c->cur];
-  src[kPops + 5] = c->S.ref[c->cur];
-  for (int i = 0; i < kStatePlanes; ++i) {
-    LBM_CK(hipMemcpyAsync(o, src[i], N * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-    o += N * sizeof(float);
-  }
-  LBM_CK(hipStreamSynchronize(c->stream));
-  return LBM_OK;
+  return copy_state(c, o + sizeof(hdr), true);
 }
 
 int lbm_load(lbm_ctx* c, const void* buf, size_t bytes) {
   if (!c || !buf || bytes < lbm_state_bytes(c)) return LBM_EINVAL;
-  const size_t N = (size_t)c->P.nx * c->P.ny;
   int64_t hdr[4];
-  const char* o = (const char*)buf;
-  std::memcpy(hdr, o, sizeof(hdr));
-  if (hdr[0] != kMagic || hdr[1] != c->P.nx || hdr[2] != c->P.ny) return LBM_ESTATE;
-  o += sizeof(hdr);
-  float* dst[kStatePlanes];
-  for (int i = 0; i < kPops; ++i) dst[i] = c->S.pops[c->cur] + i * c->K.plane;
-  dst[kPops + 0] = c->S.phiu[c->cur];
-  dst[kPops + 1] = c->S.phiu[c->cur] + c->K.plane;
-  dst[kPops + 2] = c->S.fsH[c->cur];
-  dst[kPops + 3] = c->S.p[c->cur];
-  dst[kPops + 4] = c->S.S[c->cur];
-  dst[kPops + 5] = c->S.ref[c->cur];
-  for (int i = 0; i < kStatePlanes; ++i) {
-    LBM_CK(hipMemcpyAsync(dst[i], o, N * sizeof(float), hipMemcpyHostToDevice, c->stream));
-    o += N * sizeof(float);
-  }
-  LBM_CK(hipStreamSynchronize(c->stream));
+  std::memcpy(hdr, buf, sizeof(hdr));
+  if (hdr[0] != kMagic + c->P.storage || hdr[1] != c->P.nx || hdr[2] != c->P.ny) return LBM_ESTATE;
+  int rc = copy_state(c, (char*)buf + sizeof(hdr), false);
+  if (rc) return rc;
   c->step = hdr[3];
   return LBM_OK;
 }
@@ -402,6 +444,10 @@ int lbm_sync(lbm_ctx* c) {
 int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap) {
   if (!c || tile_variant < 0 || tile_variant >= lbmk::NTILE_VARIANTS || xcd_remap < 0 || xcd_remap > 1)
     return LBM_EINVAL;
+  if (is_strip(tile_variant) && c->P.storage != LBM_STORE_FP32) {
+    g_last_error = "column strips support FP32 population storage only";
+    return LBM_EINVAL;
+  }
   c->tile_variant = tile_variant;
   c->xcd = xcd_remap;
   return LBM_OK;
@@ -411,12 +457,20 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_r
   if (!c || reps < 1) return LBM_EINVAL;
   // The step kernel reads buffer cur and writes buffer cur^1 only, so
   // replaying it without flipping leaves the state where it was.
-  hipEvent_t e0, e1;
-  LBM_CK(hipEventCreate(&e0));
-  LBM_CK(hipEventCreate(&e1));
+  struct Events {  // destroyed on every return path
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  LBM_CK(hipEventCreate(&ev.a));
+  LBM_CK(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   float best = 1e30f;
   int bv = c->tile_variant, bx = c->xcd;
   for (int v = 0; v < lbmk::NTILE_VARIANTS; ++v) {
+    if (is_strip(v) && c->P.storage != LBM_STORE_FP32) continue;
     for (int x = 0; x <= 1; ++x) {
       if (lbmk::launch_step(c->K, c->S, c->cur, false, v, x, c->stream))  // warm-up
         return dev_error(hipGetLastError(), "autotune launch");
@@ -435,8 +489,6 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_r
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   c->tile_variant = bv;
   c->xcd = bx;
   if (tile_variant) *tile_variant = bv;

@@ -25,12 +25,17 @@ struct KParams {
   float tan_b, tan_t;              // tan(pi/2 - theta) at the bottom / top wall
   float gx, gy, bq_coef, bq_Tref;  // body force
   float chi;                       // surface-tension solid mask
+  int storage;                     // STORE_FP32 / STORE_FP16 / STORE_BF16
+  float sc_st[3], sc_ld[3];        // FP16 only: per-lattice power-of-two scale on store / load
 };
 
+enum { STORE_FP32 = 0, STORE_FP16 = 1, STORE_BF16 = 2 };
+
 struct State {
-  float* pops[2];  // 27 planes each: g0..g8, f0..f8, h0..h8
+  void* pops[2];   // 27 planes each: g0..g8, f0..f8, h0..h8 (FP32, FP16 or BF16)
   float* phiu[2];  // 2 planes each: (phi u)^{n-1}
-  float* ref[2];   // phi of the previous step: reference of the stored g populations
+  void* ref[2];    // node references of the stored populations: FP32 phi_ref, or
+                   // (16-bit storage) FP16 pairs (phi_ref, T - T_m)
   float* fsH[2];   // f_s^H of the previous step (read n-1, write n)
   float* p[2];     // pressure of the previous step
   float* S[2];     // mass-source term S of the previous step
@@ -52,6 +57,9 @@ int launch_init(const KParams& P, const IParams& I, const State& S, int cur, con
                 const double* d_T0, hipStream_t st);
 int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int tile_variant,
                 int xcd_remap, hipStream_t st);
+// The 9 populations of `lattice` as FP32 (shifted variables) into the first
+// nine field planes.
+int launch_expand(const KParams& P, const State& S, int cur, int lattice, hipStream_t st);
 // Reduces the field planes into RED_NVAL doubles at part[RED_BLOCKS * RED_NVAL].
 int launch_reduce(const KParams& P, const State& S, double Href, hipStream_t st);
 

@@ -57,13 +57,110 @@ __device__ __forceinline__ void st(float* __restrict__ base, unsigned idx, float
 // Hardware reciprocal (1 ulp); used identically wherever a node is rebuilt.
 __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
+// Population storage.  FP32 keeps the shifted populations as computed.  The
+// 16-bit formats round them to nearest-even; FP16 first multiplies by a
+// per-lattice power of two (exact in FP32, undone on load) so that the
+// small shifted values stay in its normal range.  BF16 has FP32's exponent
+// range and is not scaled.  Compute is FP32 throughout.
+template <class PT>
+struct PopIO;
+// kNodeRef: the 16-bit formats keep h relative to the writing node's own
+// temperature as well (exact algebra, like the phi reference of g), so the
+// stored h values are non-equilibrium-sized; FP32 resolves the coarser
+// shift relative to T_m well enough.  f is stored as computed in every
+// format.
+template <>
+struct PopIO<float> {
+  static constexpr bool kNodeRef = false;
+  static constexpr bool kScaled = false;
+  static __device__ __forceinline__ float get(const void* b, unsigned idx) { return ld((const float*)b, idx); }
+  static __device__ __forceinline__ void put(void* b, unsigned idx, float v) { st((float*)b, idx, v); }
+};
+template <>
+struct PopIO<_Float16> {
+  static constexpr bool kNodeRef = true;
+  static constexpr bool kScaled = true;
+  static __device__ __forceinline__ float get(const void* b, unsigned idx) {
+    return (float)*(const _Float16*)((const char*)b + (idx << 1));
+  }
+  static __device__ __forceinline__ void put(void* b, unsigned idx, float v) {
+    *(_Float16*)((char*)b + (idx << 1)) = (_Float16)v;
+  }
+};
+template <>
+struct PopIO<__bf16> {
+  static constexpr bool kNodeRef = true;
+  static constexpr bool kScaled = false;
+  static __device__ __forceinline__ float get(const void* b, unsigned idx) {
+    return (float)*(const __bf16*)((const char*)b + (idx << 1));
+  }
+  static __device__ __forceinline__ void put(void* b, unsigned idx, float v) {
+    *(__bf16*)((char*)b + (idx << 1)) = (__bf16)v;
+  }
+};
+// Node references.  FP32 storage keeps phi_ref, the reference of the stored
+// g, as an FP32 plane.  The node-reference formats keep the pair
+// (phi_ref, th) as two FP16 values in one 32-bit word per node: the writer
+// first rounds its phi and T - T_m to FP16 and shifts by the rounded
+// values, so writer and readers use identical references.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+template <bool NR>
+struct RefIO;
+template <>
+struct RefIO<false> {
+  static __device__ __forceinline__ void load(const void* b, unsigned k, float& r, float& th) {
+    r = ld((const float*)b, k);
+    th = 0.0f;
+  }
+  static __device__ __forceinline__ void round(float phi, float dT, float& r, float& th) {
+    r = phi;
+    th = 0.0f;
+  }
+  static __device__ __forceinline__ void store(void* b, unsigned k, float r, float) { st((float*)b, k, r); }
+};
+template <>
+struct RefIO<true> {
+  static __device__ __forceinline__ void load(const void* b, unsigned k, float& r, float& th) {
+    const half2v v = *(const half2v*)((const char*)b + (k << 2));
+    r = (float)v.x;
+    th = (float)v.y;
+  }
+  static __device__ __forceinline__ void round(float phi, float dT, float& r, float& th) {
+    r = (float)(_Float16)phi;
+    th = (float)(_Float16)dT;
+  }
+  static __device__ __forceinline__ void store(void* b, unsigned k, float r, float th) {
+    half2v v;
+    v.x = (_Float16)r;  // exact: r and th are already FP16 values
+    v.y = (_Float16)th;
+    *(half2v*)((char*)b + (k << 2)) = v;
+  }
+};
+
+template <class PT, int LAT>
+__device__ __forceinline__ float pop_ld(const void* A, unsigned idx, const KParams& P) {
+  float v = PopIO<PT>::get(A, idx);
+  if constexpr (PopIO<PT>::kScaled) v *= P.sc_ld[LAT];
+  return v;
+}
+template <class PT, int LAT>
+__device__ __forceinline__ void pop_st(void* B, unsigned idx, float v, const KParams& P) {
+  if constexpr (PopIO<PT>::kScaled) v *= P.sc_st[LAT];
+  PopIO<PT>::put(B, idx, v);
+}
+// Plane `j` of a population buffer.
+template <class PT>
+__device__ __forceinline__ void* pop_plane(void* B, unsigned j, unsigned pl) {
+  return (char*)B + (size_t)j * pl * sizeof(PT);
+}
+
 // Pull-stream the 9 populations of one lattice into node (x, y).  Sources
 // beyond a wall are replaced by the bounce-back of the node's own opposite
 // population (half-way rule); for h at the bottom wall by the
 // anti-bounce-back Dirichlet value -h_opp + 2 w_i cp_ref (T_w - T_m) in the
 // shifted variables.
-template <int LAT>
-__device__ __forceinline__ void pull9(const float* __restrict__ A, const KParams& P, int x, int y,
+template <int LAT, class PT>
+__device__ __forceinline__ void pull9(const void* __restrict__ A, const KParams& P, int x, int y,
                                       int xm, int xp, float q[9]) {
   // 32-bit element indices: a scalar plane base plus one vector offset per load
   const unsigned pl = P.plane;
@@ -79,7 +176,7 @@ __device__ __forceinline__ void pull9(const float* __restrict__ A, const KParams
     const unsigned sx = (unsigned)(cx > 0 ? xm : (cx < 0 ? xp : x));
     const unsigned sk = (cy > 0 ? rowd : (cy < 0 ? rowu : rowc)) + sx;
     const unsigned idx = wall ? (unsigned)(LAT * 9 + opp(i)) * pl + k : (unsigned)(LAT * 9 + i) * pl + sk;
-    float v = ld(A, idx);
+    float v = pop_ld<PT, LAT>(A, idx, P);
     if (LAT == 2 && cy > 0) v = bot ? (P.hwall[i] - v) : v;
     q[i] = v;
   }
@@ -106,6 +203,30 @@ __device__ __forceinline__ float rebase_g(float q[9], const float (*sref)[RX], c
   return rself;
 }
 
+// The same for h under the node-reference storage: stored h_i is relative
+// to w_i cp_ref th(writer), th = T - T_m of the writer's step.  Received
+// populations move to the receiver's reference; the anti-bounce-back ones
+// at the bottom wall (built from the node's own populations) to
+// -h_opp + 2 w_i cp_ref (T_w - T_m - th) in that reference.
+template <int RX>
+__device__ __forceinline__ float rebase_h(float q[9], const float (*sth)[RX], const KParams& P,
+                                          int y, int c, int r) {
+#pragma clang fp contract(off)
+  const bool bot = (y == 0), top = (y == P.ny - 1);
+  const float tself = sth[r + 1][c + 1];
+  const float cw = P.cp_ref * tself;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int cy = cyv(i), cx = cxv(i);
+    if (cy > 0 && bot) {
+      q[i] -= (2.0f * wt(i)) * cw;
+    } else if (!(cy < 0 && top)) {
+      q[i] += wt(i) * (P.cp_ref * sth[r + 1 - cy][c + 1 - cx] - cw);
+    }
+  }
+  return tself;
+}
+
 struct Macro {
   float g[9], h[9];
   float E;      // H - H_l + L f_s^H(n-1): the enthalpy excess over the stored latent part
@@ -114,6 +235,7 @@ struct Macro {
   float cp, kk, fl, fsH, mdot, phi, fsol, rho, mu;
   float r;      // reference phi of the received g populations (own previous phi)
   float dl;     // phi - r, resolved to the precision of the small stored numbers
+  float th;     // reference T - T_m of the received h populations (node-reference storage)
 };
 
 // Node-local macroscopic quantities of time t (Eq. (29), (9), (19), (26), (1)).
@@ -127,18 +249,21 @@ struct Macro {
 // nodes alike instead of ~1e-6 of H ~ L.
 // Issue the loads of one node's macroscopic inputs: pulled g and h (wall
 // rules applied) and f_s^H of the previous step.
-__device__ __forceinline__ void load_node(const float* __restrict__ A,
+template <class PT>
+__device__ __forceinline__ void load_node(const void* __restrict__ A,
                                           const float* __restrict__ fsH_prev, const KParams& P,
                                           int x, int y, Macro& m) {
   const int xm = x == 0 ? P.nx - 1 : x - 1;
   const int xp = x == P.nx - 1 ? 0 : x + 1;
-  pull9<0>(A, P, x, y, xm, xp, m.g);
-  pull9<2>(A, P, x, y, xm, xp, m.h);
+  pull9<0, PT>(A, P, x, y, xm, xp, m.g);
+  pull9<2, PT>(A, P, x, y, xm, xp, m.h);
   m.fprev = ld(fsH_prev, (unsigned)(y * P.nx + x));
 }
 
 // Node-local macroscopic quantities of time t (Eq. (29), (9), (19), (26), (1))
-// from the loaded inputs; m.g must already be rebased to reference rs.
+// from the loaded inputs; m.g must already be rebased to reference rs and,
+// under NODEREF, m.h to m.th.
+template <bool NODEREF>
 __device__ __forceinline__ void finish_macro(const KParams& P, float rs, Macro& m) {
   // computed both for own nodes and for halo cells: no FMA contraction, so
   // every tile shape yields bit-identical values
@@ -156,7 +281,8 @@ __device__ __forceinline__ void finish_macro(const KParams& P, float rs, Macro& 
   const float kk = mix3(fs_lag, pc0, P.k_s, P.k_l, P.k_g);
   // H - H_l = E - L f_s^H(n-1) and H - H_s = E + L (1 - f_s^H(n-1)) for
   // H_s = cp T_m, H_l = cp T_m + L (Eq. (9))
-  const float E = hs + m.h[0] + (P.cp_ref - cp) * P.T_melt;
+  float E = hs + m.h[0] + (P.cp_ref - cp) * P.T_melt;
+  if (NODEREF) E = E + P.cp_ref * m.th;
   const float dHl = E - P.latent * fprev;
   const float dHs = E + P.latent * (1.0f - fprev);
   const float fl = clamp01(E * P.inv_latent + (1.0f - fprev));
@@ -188,12 +314,12 @@ __device__ __forceinline__ void finish_macro(const KParams& P, float rs, Macro& 
 // Buffers one step reads (time n) and writes (time n+1).  The step is a
 // pure function of the *_in buffers, so it can be replayed for timing.
 struct StepIO {
-  const float* A;
-  float* B;
+  const void* A;  // populations of time n (storage type of the instantiation)
+  void* B;        // populations of time n+1
   const float* phiu_in;
   float* phiu_out;
-  const float* ref_in;
-  float* ref_out;
+  const void* ref_in;  // node references (FP32 phi_ref, or FP16 pairs (phi_ref, th))
+  void* ref_out;
   const float* fsH_in;
   float* fsH_out;
   const float* p_in;
@@ -234,7 +360,7 @@ __device__ __forceinline__ float wetting_ghost(float a0m, float a0c, float a0p, 
 // Everything after the stencils for one node k: interface terms (Eq. (3),
 // (12), (13)), forces (Eq. (11)), flow macros (Eq. (34)-(36)) and the three
 // BGK collisions with their stores, or the output fields when FIELDS.
-template <bool FIELDS>
+template <bool FIELDS, class PT>
 __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, const Macro& m,
                                             const float f[9], float phiux, float phiuy,
                                             const Grads& d, unsigned k) {
@@ -292,12 +418,13 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
   }
 
   const unsigned pl = P.plane;
-  float* __restrict__ B = io.B;
+  void* __restrict__ B = io.B;
+  float r_new, th_new;  // references the stored g and h take this step
   // flow collision (Eq. (30)-(33))
   {
     const float itau = rcp(tauf), sf = 1.0f - 0.5f * itau;
     const float Gx = Fx + rho * fbx, Gy = Fy + rho * fby;
-    float* Bf = B + 9 * pl;
+    void* Bf = pop_plane<PT>(B, 9, pl);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const float cx = (float)cxv(i), cy = (float)cyv(i);
@@ -306,7 +433,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float feq = 3.0f * p * (wt(i) - (i == 0 ? 1.0f : 0.0f)) + rho * si;
       const float cF = cx * Ftx + cy * Fty;
       const float Fi = wt(i) * (Ssrc + 3.0f * (cx * Gx + cy * Gy) + 9.0f * cu * cF - 3.0f * uFt);
-      st(Bf, i * pl + k, f[i] - (f[i] - feq) * itau + sf * Fi);
+      pop_st<PT, 1>(Bf, i * pl + k, f[i] - (f[i] - feq) * itau + sf * Fi, P);
     }
   }
   // phase-field collision (Eq. (21), (24), (25), (37))
@@ -317,7 +444,8 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
     const float pm = phi * m.mdot;
     // the new reference is this step's phi (as stored); re-express the
     // populations and the equilibrium relative to it
-    const float dr = m.r - phi;   // exact for nearby floats
+    RefIO<PopIO<PT>::kNodeRef>::round(phi, m.dT, r_new, th_new);
+    const float dr = m.r - r_new;  // exact for nearby floats
     const float dln = m.dl + dr;  // phi - phi_ref(new)
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -326,31 +454,38 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float gi = m.g[i] + wt(i) * dr;                 // g_i - w_i phi_ref
       const float geq = wt(i) * (dln + 3.0f * phi * cu);  // g_i^eq - w_i phi_ref
       const float Gi = wt(i) * (cx * ax + cy * ay + pm);
-      st(B, i * pl + k, gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi);
+      pop_st<PT, 0>(B, i * pl + k, gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi, P);
     }
-    st(io.ref_out, k, phi);
+    RefIO<PopIO<PT>::kNodeRef>::store(io.ref_out, k, r_new, th_new);
     st(io.phiu_out, k, pux);
     st(io.phiu_out, pl + k, puy);
   }
   // enthalpy collision (Eq. (27)-(28)) in the shifted variables
+  constexpr bool NR = PopIO<PT>::kNodeRef;
   {
     const float itau = rcp(m.kk * P.three_over_cpref + 0.5f);
     const float cpT = m.cp * T;
-    const float crd = P.cp_ref * m.dT;
-    float* Bh = B + 18 * pl;
+    const float crd = NR ? P.cp_ref * (m.dT - m.th) : P.cp_ref * m.dT;
+    // node reference: move from the received reference th to this step's
+    const float cmove = NR ? P.cp_ref * (m.th - th_new) : 0.0f;
+    void* Bh = pop_plane<PT>(B, 18, pl);
     float hs = 0.0f;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const float cx = (float)cxv(i), cy = (float)cyv(i);
       const float cu = cx * ux + cy * uy;
       const float heq = wt(i) * (crd + cpT * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
-      st(Bh, i * pl + k, m.h[i] - (m.h[i] - heq) * itau);
+      float hn = m.h[i] - (m.h[i] - heq) * itau;
+      if (NR) hn += wt(i) * cmove;
+      pop_st<PT, 2>(Bh, i * pl + k, hn, P);
       hs += m.h[i];
     }
     // rest population: h0eq - h0 = sum_{i>0} h_i - cp_ref dT + w0 (cp_ref dT - 1.5 cp T u.u);
     // the stored value moves by that relaxation plus L (f_s^H(n) - f_s^H(n-1))
     const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
-    st(Bh, k, m.h[0] + d0 + P.latent * (m.fsH - m.fprev));
+    float h0 = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
+    if (NR) h0 += W0 * cmove;
+    pop_st<PT, 2>(Bh, k, h0, P);
   }
   st(io.fsH_out, k, m.fsH);
   st(io.p_out, k, p);
@@ -365,8 +500,8 @@ __device__ __forceinline__ int map_tile(int b, int mode, int tiles_per_xcd) {
   return mode == 1 ? (b & 7) * tiles_per_xcd + (b >> 3) : b;
 }
 
-template <int TX, int TY, bool FIELDS>
-__global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, int ntiles,
+template <int TX, int TY, bool FIELDS, class PT>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) void k_step(KParams P, StepIO io, int ntx, int ntiles,
                                                  int tiles_per_xcd, int mode) {
   constexpr int NT = TX * TY;
   constexpr int LX = TX + 4, LY = TY + 2;  // LDS column c <-> x0 + c - 2, row r <-> y0 + r - 1
@@ -377,8 +512,10 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
   __shared__ float s_p[LY][LX];
   __shared__ float s_S[LY][LX];
   __shared__ float s_ref[RY][RX];  // phi of the previous step, reference of the stored g
+  constexpr bool NR = PopIO<PT>::kNodeRef;
+  __shared__ float s_th[NR ? RY : 1][NR ? RX : 1];  // reference T - T_m of the stored h
 
-  const float* __restrict__ A = io.A;
+  const void* __restrict__ A = io.A;
   const int tile = map_tile(blockIdx.x, mode, tiles_per_xcd);
   if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
   const int nx = P.nx, ny = P.ny;
@@ -398,11 +535,11 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
   static_assert(NRING <= NT, "one halo cell per lane at most");
   Macro m, mh;
   float f[9], phiux = 0.0f, phiuy = 0.0f;
-  if (yin) load_node(A, io.fsH_in, P, xw, y, m);
+  if (yin) load_node<PT>(A, io.fsH_in, P, xw, y, m);
   if (active) {
     const int xm = x == 0 ? nx - 1 : x - 1;
     const int xp = x == nx - 1 ? 0 : x + 1;
-    pull9<1>(A, P, x, y, xm, xp, f);
+    pull9<1, PT>(A, P, x, y, xm, xp, f);
     phiux = ld(io.phiu_in, (unsigned)(y * nx + x));
     phiuy = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
   }
@@ -423,7 +560,7 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
     }
     const int gy = y0 + hr - 1;
     halo = gy >= 0 && gy < ny;
-    if (halo) load_node(A, io.fsH_in, P, wrapx(x0 + hc - 2, nx), gy, mh);
+    if (halo) load_node<PT>(A, io.fsH_in, P, wrapx(x0 + hc - 2, nx), gy, mh);
   }
   // phi_ref with a two-cell halo (rows beyond a wall are never read; the
   // clamp keeps the load in bounds), and the lagged p and S with one cell
@@ -431,7 +568,10 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
   for (int j = t; j < RX * RY; j += NT) {
     const int r = j / RX, c = j - (j / RX) * RX;
     const int gy = min(max(y0 + r - 2, 0), ny - 1);
-    s_ref[r][c] = ld(io.ref_in, (unsigned)(gy * nx + wrapx(x0 + c - 3, nx)));
+    float rv, tv;
+    RefIO<NR>::load(io.ref_in, (unsigned)(gy * nx + wrapx(x0 + c - 3, nx)), rv, tv);
+    s_ref[r][c] = rv;
+    if constexpr (NR) s_th[r][c] = tv;
   }
   for (int j = t; j < LX * LY; j += NT) {
     const int r = j / LX, c = j - (j / LX) * LX;
@@ -445,14 +585,16 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
   // ---- phase 1: macroscopic quantities of time t into LDS ----------------
   if (yin) {
     const float rs = rebase_g<RX>(m.g, s_ref, P, y, lx + 2, ly + 1);
-    finish_macro(P, rs, m);
+    if constexpr (NR) m.th = rebase_h<RX>(m.h, s_th, P, y, lx + 2, ly + 1);
+    finish_macro<NR>(P, rs, m);
     s_phi[ly + 1][lx + 2] = (m.r - 1.0f) + m.dl;
     s_rho[ly + 1][lx + 2] = m.rho;
     s_fsH[ly + 1][lx + 2] = m.fsH;
   }
   if (halo) {
     const float rs = rebase_g<RX>(mh.g, s_ref, P, y0 + hr - 1, hc, hr);
-    finish_macro(P, rs, mh);
+    if constexpr (NR) mh.th = rebase_h<RX>(mh.h, s_th, P, y0 + hr - 1, hc, hr);
+    finish_macro<NR>(P, rs, mh);
     s_phi[hr][hc] = (mh.r - 1.0f) + mh.dl;
     s_rho[hr][hc] = mh.rho;
     s_fsH[hr][hc] = mh.fsH;
@@ -503,7 +645,7 @@ __global__ __launch_bounds__(TX* TY) void k_step(KParams P, StepIO io, int ntx, 
   LBM_TILE_STENCIL(s_p, d.px, d.py, nullptr);
   LBM_TILE_STENCIL(s_S, d.Sx, d.Sy, nullptr);
 #undef LBM_TILE_STENCIL
-  update_node<FIELDS>(P, io, m, f, phiux, phiuy, d, k);
+  update_node<FIELDS, PT>(P, io, m, f, phiux, phiuy, d, k);
 }
 
 // Sliding-window variant for large grids.  A workgroup is one wavefront
@@ -523,9 +665,10 @@ struct RawNode {
   float g[9], h[9], fprev;
 };
 
-template <int SY, bool FIELDS>
+template <int SY, bool FIELDS, class PT>
 __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx, int nstrips,
                                                   int tiles_per_xcd, int mode) {
+  static_assert(!PopIO<PT>::kNodeRef, "column strips implement the FP32 storage shifts only");
   constexpr int LR = CW + 2;  // phi_ref: columns x0-3 .. x0+CW-2
   constexpr int LP = CW - 2;  // p/S:     columns x0-1 .. x0+CW-4
   __shared__ float s_phi[4][CW];  // lane t <-> column x0 - 2 + t
@@ -535,7 +678,7 @@ __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx,
   __shared__ float s_S[4][LP];
   __shared__ float s_ref[4][LR];
 
-  const float* __restrict__ A = io.A;
+  const void* __restrict__ A = io.A;
   const int strip = map_tile(blockIdx.x, mode, tiles_per_xcd);
   if (strip >= nstrips) return;
   const int nx = P.nx, ny = P.ny;
@@ -555,8 +698,8 @@ __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx,
 #define CLAMPY(gy) min(max((gy), 0), ny - 1)
 
   auto load_raw = [&](int gy, RawNode& w) {
-    pull9<0>(A, P, xw, gy, xm, xp, w.g);
-    pull9<2>(A, P, xw, gy, xm, xp, w.h);
+    pull9<0, PT>(A, P, xw, gy, xm, xp, w.g);
+    pull9<2, PT>(A, P, xw, gy, xm, xp, w.h);
     w.fprev = io.fsH_in[gy * nx + xw];
   };
   auto rebase = [&](float q[9], int gy) -> float {
@@ -581,7 +724,7 @@ __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx,
     }
     m.fprev = w.fprev;
     const float rs = rebase(m.g, gy);
-    finish_macro(P, rs, m);
+    finish_macro<false>(P, rs, m);
   };
   auto to_rings = [&](const Macro& m, int gy) {
     s_phi[SLOT(gy)][t] = (m.r - 1.0f) + m.dl;
@@ -601,8 +744,8 @@ __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx,
   // ---- prologue ------------------------------------------------------------
   for (int gy = y0 - 2; gy <= y0 + 1; ++gy) {
     const int cy = CLAMPY(gy);
-    s_ref[SLOT(gy)][t] = io.ref_in[cy * nx + rx0];
-    if (rj1 < LR) s_ref[SLOT(gy)][rj1] = io.ref_in[cy * nx + rx1];
+    s_ref[SLOT(gy)][t] = ((const float*)io.ref_in)[cy * nx + rx0];
+    if (rj1 < LR) s_ref[SLOT(gy)][rj1] = ((const float*)io.ref_in)[cy * nx + rx1];
   }
   for (int gy = y0 - 1; gy <= y0; ++gy) {
     if (t < LP) {
@@ -629,8 +772,8 @@ __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx,
   float refV0, refV1 = 0.0f, pV = 0.0f, SV = 0.0f;
   {
     const int cy = CLAMPY(y0 + 2);
-    refV0 = io.ref_in[cy * nx + rx0];
-    if (rj1 < LR) refV1 = io.ref_in[cy * nx + rx1];
+    refV0 = ((const float*)io.ref_in)[cy * nx + rx0];
+    if (rj1 < LR) refV1 = ((const float*)io.ref_in)[cy * nx + rx1];
     if (t < LP) {
       const int kk = CLAMPY(y0 + 1) * nx + px0;
       pV = io.p_in[kk];
@@ -639,7 +782,7 @@ __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx,
   }
   float fC[9], puxC = 0.0f, puyC = 0.0f;
   if (own) {
-    pull9<1>(A, P, xw, y0, xm, xp, fC);
+    pull9<1, PT>(A, P, xw, y0, xm, xp, fC);
     puxC = io.phiu_in[y0 * nx + xw];
     puyC = io.phiu_in[P.plane + y0 * nx + xw];
   }
@@ -672,8 +815,8 @@ __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx,
     if (more && y + 2 < ny) load_raw(y + 2, rawN);
     if (more) {
       const int cy = CLAMPY(y + 3);
-      refV0 = io.ref_in[cy * nx + rx0];
-      if (rj1 < LR) refV1 = io.ref_in[cy * nx + rx1];
+      refV0 = ((const float*)io.ref_in)[cy * nx + rx0];
+      if (rj1 < LR) refV1 = ((const float*)io.ref_in)[cy * nx + rx1];
       if (t < LP) {
         const int kk = CLAMPY(y + 2) * nx + px0;
         pV = io.p_in[kk];
@@ -682,7 +825,7 @@ __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx,
     }
     float fN[9], puxN = 0.0f, puyN = 0.0f;
     if (own && more) {
-      pull9<1>(A, P, xw, yl, xm, xp, fN);
+      pull9<1, PT>(A, P, xw, yl, xm, xp, fN);
       puxN = io.phiu_in[yl * nx + xw];
       puyN = io.phiu_in[P.plane + yl * nx + xw];
     }
@@ -701,7 +844,7 @@ __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx,
               s_p[u][cp - 1], s_p[a][cp - 1], s_p[a][cp + 1], d.px, d.py, nullptr);
       stencil(s_S[c0][cp], s_S[c0][cp + 1], s_S[c0][cp - 1], s_S[u][cp], s_S[a][cp], s_S[u][cp + 1],
               s_S[u][cp - 1], s_S[a][cp - 1], s_S[a][cp + 1], d.Sx, d.Sy, nullptr);
-      update_node<FIELDS>(P, io, mc, fC, puxC, puyC, d, y * nx + xw);
+      update_node<FIELDS, PT>(P, io, mc, fC, puxC, puyC, d, y * nx + xw);
     }
     __syncthreads();  // rings are overwritten from the next iteration on
     // (5) rotate the pipeline
@@ -718,9 +861,10 @@ __global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx,
 
 // Initial state (no time-stepping yet): u = 0, p = 0, liquid fraction 1,
 // each lattice at its equilibrium; computed in FP64 and rounded once.
+template <class PT>
 __global__ void k_init(KParams P, IParams I, const double* __restrict__ phi0,
-                       const double* __restrict__ T0, float* __restrict__ A,
-                       float* __restrict__ phiu, float* __restrict__ ref, float* __restrict__ fsH,
+                       const double* __restrict__ T0, void* __restrict__ A,
+                       float* __restrict__ phiu, void* __restrict__ ref, float* __restrict__ fsH,
                        float* __restrict__ p, float* __restrict__ S) {
   const long long N = (long long)P.nx * P.ny;
   const long long pl = P.plane;
@@ -737,20 +881,44 @@ __global__ void k_init(KParams P, IParams I, const double* __restrict__ phi0,
     const double Href = I.cp_ref * I.T_melt + I.latent;
     const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     const float fs0 = (float)(1.0 - fl);
-    const float ref0 = (float)ph;
-    ref[k] = ref0;
+    // references of the stored g (and, node-reference storage, h)
+    float ref0, th0;
+    RefIO<PopIO<PT>::kNodeRef>::round((float)ph, (float)dT, ref0, th0);
+    RefIO<PopIO<PT>::kNodeRef>::store(ref, (unsigned)k, ref0, th0);
     for (int i = 0; i < 9; ++i) {
-      A[i * pl + k] = (float)(w[i] * (ph - (double)ref0));
-      A[(9 + i) * pl + k] = 0.0f;
+      pop_st<PT, 0>(A, (unsigned)(i * pl + k), (float)(w[i] * (ph - (double)ref0)), P);
+      pop_st<PT, 1>(A, (unsigned)((9 + i) * pl + k), 0.0f, P);
       const double hs = i == 0 ? (H0 - Href) - I.cp_ref * dT + w[0] * I.cp_ref * dT + I.latent * (double)fs0
                                : w[i] * I.cp_ref * dT;
-      A[(18 + i) * pl + k] = (float)hs;
+      pop_st<PT, 2>(A, (unsigned)((18 + i) * pl + k), (float)(hs - w[i] * I.cp_ref * (double)th0), P);
     }
     phiu[k] = 0.0f;
     phiu[pl + k] = 0.0f;
     fsH[k] = fs0;
     p[k] = 0.0f;
     S[k] = 0.0f;
+  }
+}
+
+// Populations of one lattice as FP32.  FP32 storage: as stored (shifted
+// variables).  Node-reference formats: with the node references added back
+// (w_i phi_ref to g, w_i cp_ref th to h), i.e. in the shifted variables of
+// FP32 storage.
+template <class PT>
+__global__ void k_expand(KParams P, const void* __restrict__ A, const void* __restrict__ ref, int lattice,
+                         float* __restrict__ out) {
+  const unsigned N = (unsigned)P.nx * (unsigned)P.ny;
+  const unsigned pl = P.plane;
+  const float s = PopIO<PT>::kScaled ? P.sc_ld[lattice] : 1.0f;
+  for (unsigned k = blockIdx.x * blockDim.x + threadIdx.x; k < N; k += gridDim.x * blockDim.x) {
+    float r = 0.0f, th = 0.0f;
+    if (PopIO<PT>::kNodeRef) RefIO<PopIO<PT>::kNodeRef>::load(ref, k, r, th);
+    const float add = lattice == 0 ? r : (lattice == 2 ? P.cp_ref * th : 0.0f);
+    for (int i = 0; i < 9; ++i) {
+      float v = PopIO<PT>::get(A, (lattice * 9 + i) * pl + k) * s;
+      if (PopIO<PT>::kNodeRef) v += wt(i) * add;
+      out[i * pl + k] = v;
+    }
   }
 }
 
@@ -809,7 +977,7 @@ __global__ __launch_bounds__(64) void k_reduce2(double* __restrict__ part, int n
   part[RED_BLOCKS * RED_NVAL + j] = r;  // final values after the partials
 }
 
-template <int TX, int TY>
+template <int TX, int TY, class PT>
 int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int xcd, hipStream_t st) {
   const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
   const int ntiles = ntx * nty;
@@ -822,13 +990,13 @@ int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int
   StepIO io{S.pops[cur], S.pops[nxt], S.phiu[cur], S.phiu[nxt], S.ref[cur], S.ref[nxt],
             S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur], S.S[nxt], S.fields};
   if (fields_only)
-    hipLaunchKernelGGL((k_step<TX, TY, true>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx, xcd);
+    hipLaunchKernelGGL((k_step<TX, TY, true, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx, xcd);
   else
-    hipLaunchKernelGGL((k_step<TX, TY, false>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx, xcd);
+    hipLaunchKernelGGL((k_step<TX, TY, false, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx, xcd);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int SY>
+template <int SY, class PT>
 int launch_column(const KParams& P, const State& S, int cur, bool fields_only, int xcd, hipStream_t st) {
   const int nsx = (P.nx + CI - 1) / CI, nsy = (P.ny + SY - 1) / SY;
   const int nstrips = nsx * nsy;
@@ -841,43 +1009,86 @@ int launch_column(const KParams& P, const State& S, int cur, bool fields_only, i
   StepIO io{S.pops[cur], S.pops[nxt], S.phiu[cur], S.phiu[nxt], S.ref[cur], S.ref[nxt],
             S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur], S.S[nxt], S.fields};
   if (fields_only)
-    hipLaunchKernelGGL((k_column<SY, true>), dim3(grid), dim3(CW), 0, st, P, io, nsx, nstrips, tpx, xcd);
+    hipLaunchKernelGGL((k_column<SY, true, PT>), dim3(grid), dim3(CW), 0, st, P, io, nsx, nstrips, tpx, xcd);
   else
-    hipLaunchKernelGGL((k_column<SY, false>), dim3(grid), dim3(CW), 0, st, P, io, nsx, nstrips, tpx, xcd);
+    hipLaunchKernelGGL((k_column<SY, false, PT>), dim3(grid), dim3(CW), 0, st, P, io, nsx, nstrips, tpx, xcd);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace
+
+namespace {
+
+template <class PT>
+int launch_step_t(const KParams& P, const State& S, int cur, bool fields_only, int tile_variant,
+                  int xcd_remap, hipStream_t st) {
+  switch (tile_variant) {
+    case 1:
+      return launch_tile<32, 8, PT>(P, S, cur, fields_only, xcd_remap, st);
+    case 2:
+      return launch_tile<64, 8, PT>(P, S, cur, fields_only, xcd_remap, st);
+    case 3:
+      return launch_tile<64, 16, PT>(P, S, cur, fields_only, xcd_remap, st);
+    case 4:
+      return launch_tile<128, 4, PT>(P, S, cur, fields_only, xcd_remap, st);
+    case 5:
+    case 6:
+    case 7:
+      if constexpr (PopIO<PT>::kNodeRef) {
+        return -1;  // strips exist for FP32 storage only (rejected by the host first)
+      } else {
+        if (tile_variant == 5) return launch_column<32, PT>(P, S, cur, fields_only, xcd_remap, st);
+        if (tile_variant == 6) return launch_column<64, PT>(P, S, cur, fields_only, xcd_remap, st);
+        return launch_column<128, PT>(P, S, cur, fields_only, xcd_remap, st);
+      }
+    default:
+      return launch_tile<64, 4, PT>(P, S, cur, fields_only, xcd_remap, st);
+  }
+}
+
+int grid_of(const KParams& P) {
+  const long long N = (long long)P.nx * P.ny;
+  return (int)std::min<long long>((N + 255) / 256, 4096);
 }
 
 }  // namespace
 
 int launch_init(const KParams& P, const IParams& I, const State& S, int cur, const double* d_phi0,
                 const double* d_T0, hipStream_t st) {
-  const long long N = (long long)P.nx * P.ny;
-  const int grid = (int)std::min<long long>((N + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_init, dim3(grid), dim3(256), 0, st, P, I, d_phi0, d_T0, S.pops[cur], S.phiu[cur],
-                     S.ref[cur], S.fsH[cur], S.p[cur], S.S[cur]);
+  const int grid = grid_of(P);
+  if (P.storage == STORE_FP16)
+    hipLaunchKernelGGL(k_init<_Float16>, dim3(grid), dim3(256), 0, st, P, I, d_phi0, d_T0, S.pops[cur],
+                       S.phiu[cur], S.ref[cur], S.fsH[cur], S.p[cur], S.S[cur]);
+  else if (P.storage == STORE_BF16)
+    hipLaunchKernelGGL(k_init<__bf16>, dim3(grid), dim3(256), 0, st, P, I, d_phi0, d_T0, S.pops[cur],
+                       S.phiu[cur], S.ref[cur], S.fsH[cur], S.p[cur], S.S[cur]);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, st, P, I, d_phi0, d_T0, S.pops[cur],
+                       S.phiu[cur], S.ref[cur], S.fsH[cur], S.p[cur], S.S[cur]);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int tile_variant,
                 int xcd_remap, hipStream_t st) {
-  switch (tile_variant) {
-    case 1:
-      return launch_tile<32, 8>(P, S, cur, fields_only, xcd_remap, st);
-    case 2:
-      return launch_tile<64, 8>(P, S, cur, fields_only, xcd_remap, st);
-    case 3:
-      return launch_tile<64, 16>(P, S, cur, fields_only, xcd_remap, st);
-    case 4:
-      return launch_tile<128, 4>(P, S, cur, fields_only, xcd_remap, st);
-    case 5:
-      return launch_column<32>(P, S, cur, fields_only, xcd_remap, st);
-    case 6:
-      return launch_column<64>(P, S, cur, fields_only, xcd_remap, st);
-    case 7:
-      return launch_column<128>(P, S, cur, fields_only, xcd_remap, st);
-    default:
-      return launch_tile<64, 4>(P, S, cur, fields_only, xcd_remap, st);
-  }
+  if (P.storage == STORE_FP16)
+    return launch_step_t<_Float16>(P, S, cur, fields_only, tile_variant, xcd_remap, st);
+  if (P.storage == STORE_BF16)
+    return launch_step_t<__bf16>(P, S, cur, fields_only, tile_variant, xcd_remap, st);
+  return launch_step_t<float>(P, S, cur, fields_only, tile_variant, xcd_remap, st);
+}
+
+int launch_expand(const KParams& P, const State& S, int cur, int lattice, hipStream_t st) {
+  const int grid = grid_of(P);
+  if (P.storage == STORE_FP16)
+    hipLaunchKernelGGL(k_expand<_Float16>, dim3(grid), dim3(256), 0, st, P, S.pops[cur], S.ref[cur], lattice,
+                       S.fields);
+  else if (P.storage == STORE_BF16)
+    hipLaunchKernelGGL(k_expand<__bf16>, dim3(grid), dim3(256), 0, st, P, S.pops[cur], S.ref[cur], lattice,
+                       S.fields);
+  else
+    hipLaunchKernelGGL(k_expand<float>, dim3(grid), dim3(256), 0, st, P, S.pops[cur], S.ref[cur], lattice,
+                       S.fields);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_reduce(const KParams& P, const State& S, double Href, hipStream_t st) {

@@ -20,6 +20,7 @@ FIELD_BITS = {"phi": 0, "T": 1, "ux": 2, "uy": 3, "p": 4, "fs": 5, "fl": 6, "rho
 TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4,
                  "strip60x32": 5, "strip60x64": 6, "strip60x128": 7}
 TILE_NAMES = {v: k for k, v in TILE_VARIANTS.items()}
+STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}  # LBM_STORE_FP32 / _FP16_SHIFT / _BF16_SHIFT
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 

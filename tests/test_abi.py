@@ -42,6 +42,15 @@ def test_workspace_size_and_validation():
         assert e.value.code == lbm.LBM_EINVAL
 
 
+def test_workspace_shrinks_with_16bit_storage():
+    p = W.default_params(128, 64)
+    plane = (128 * 64 + 63) // 64 * 64
+    n32 = lbm.workspace_bytes(p)
+    for name in ("fp16", "bf16"):
+        n16 = lbm.workspace_bytes(dict(p, storage=lbm.STORAGE[name]))
+        assert n32 - n16 == 2 * 27 * plane * 2  # both population buffers halve
+
+
 def test_strerror_names_every_code():
     L = lbm.load_library()
     for code in (0, -1, -2, -3, -4, -5):

@@ -1,0 +1,214 @@
+"""16-bit population storage (FP16 / BF16 of the shifted populations, FP32
+compute) against the FP64 oracle, through the C ABI.
+
+Storage rounds every stored population once per step, so these runs carry
+a rounding noise of ~2^-12 (FP16) or ~2^-9 (BF16) of the stored, shifted
+values on top of the FP32 path's.  The bounds below are the errors measured
+on these seeded inputs with a margin of about 3x, and BF16's are about 8x
+FP16's (three fewer mantissa bits).
+
+Pointwise phi is held only early in the run.  The frozen bottom rows under
+the droplet and its centre line later develop the order-parameter dips in
+which the method amplifies any perturbation, and the outcome is bistable:
+the FP64 oracle against itself with phi0 perturbed once by 1e-5 (about one
+step of FP16 noise) reaches max|d phi| ~1e-2 after 1000 steps in two of
+three draws and ~7e-4 in the third.  Noise of that size every step crosses
+into that regime in some runs and not in others, so long runs are checked
+on temperature, on the L2 norm of phi and on the integral quantities the
+paper reports (phase and solid volume, enthalpy, solid height).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2403_16122_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("phi", "T", "ux", "uy", "p")
+
+# (max|dphi|, relL2(phi), max|dT|, relL2(u), relL2(p)) after 100 steps of the 128x64 droplet
+EARLY = {"fp16": (5e-3, 5e-4, 1e-4, 1.5e-3, 2e-3), "bf16": (1e-2, 2e-3, 5e-4, 1e-2, 1.5e-2)}
+# (max|dT|, relL2(T), relL2(phi)) after 1000 steps
+LONG = {"fp16": (3e-4, 3e-5, 3e-2), "bf16": (1e-3, 2e-4, 3e-2)}
+
+
+def _lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_16122_amd import lbm
+
+    return lbm
+
+
+def relL2(a, b):
+    return math.sqrt(float(np.sum((a - b) ** 2))) / max(math.sqrt(float(np.sum(b * b))), 1e-300)
+
+
+def errors(g, o):
+    return dict(phi=float(np.abs(g["phi"] - o["phi"]).max()), lphi=relL2(g["phi"], o["phi"]),
+                T=float(np.abs(g["T"] - o["T"]).max()), lT=relL2(g["T"], o["T"]),
+                u=relL2(np.stack([g["ux"], g["uy"]]), np.stack([o["ux"], o["uy"]])), p=relL2(g["p"], o["p"]))
+
+
+def show(tag, e):
+    print(f"[{tag}] " + " ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
+
+
+def solver(lbm, p, phi0, T0, storage, tile="64x4"):
+    s = lbm.Solver(dict(p, storage=lbm.STORAGE[storage]), phi0, T0)
+    s.set_launch(tile, 1)
+    return s
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_early_error_against_oracle(oracle_mod, storage):
+    lbm = _lbm()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    print(f"storage={storage} sessile128 100 steps", flush=True)
+    g = solver(lbm, p, phi0, T0, storage)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    g.step(100)
+    o.step(100)
+    e = errors(g.fields(FIELDS), o.fields(FIELDS))
+    show(f"{storage}/100", e)
+    for name, tol in zip(("phi", "lphi", "T", "u", "p"), EARLY[storage]):
+        assert e[name] <= tol, (storage, name, e[name], tol)
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_long_run_temperature_and_phase(oracle_mod, storage):
+    lbm = _lbm()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    print(f"storage={storage} sessile128 1000 steps", flush=True)
+    g = solver(lbm, p, phi0, T0, storage)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    g.step(1000)
+    o.step(1000)
+    e = errors(g.fields(FIELDS), o.fields(FIELDS))
+    show(f"{storage}/1000", e)
+    for name, tol in zip(("T", "lT", "lphi"), LONG[storage]):
+        assert e[name] <= tol, (storage, name, e[name], tol)
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_integrals_after_1000_steps(oracle_mod, storage):
+    """Phase volume, solid volume, enthalpy and the solid height on the
+    centre column stay close to the oracle's even where pointwise values
+    have entered the sensitive regime."""
+    lbm = _lbm()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    print(f"storage={storage} sessile128 1000 steps (integrals)", flush=True)
+    g = solver(lbm, p, phi0, T0, storage)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    g.step(1000)
+    o.step(1000)
+    dg, do = g.diag(), o.diag()
+    assert dg["rc"] == 0
+    rel = {k: abs(dg[k] - do[k]) / abs(do[k]) for k in ("sum_phi", "sum_H", "sum_solid")}
+    print(f"[{storage}] integrals rel err {rel} h_c {dg['h_c']:.4f} vs {do['h_c']:.4f}", flush=True)
+    scale = 1.0 if storage == "fp16" else 8.0
+    assert rel["sum_phi"] <= 2e-5 * scale
+    assert rel["sum_H"] <= 2e-6 * scale
+    assert rel["sum_solid"] <= 2e-3 * scale
+    assert abs(dg["h_c"] - do["h_c"]) <= 0.05 * scale
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_launch_shapes_bitwise_identical(storage):
+    lbm = _lbm()
+    nx, ny = 100, 37
+    p = W.default_params(nx, ny, rho_s=0.9, theta_bottom_deg=70.0)
+    phi0 = W.sessile_droplet(nx, ny, 14.0, 70.0, 4.0, x0=50.3)
+    T0 = W.temperature_noise(nx, ny, p["T_melt"], 1e-3, 3)
+    ref = None
+    for tile in [t for t in lbm.TILE_VARIANTS if not t.startswith("strip")]:
+        for xcd in (0, 1):
+            print(f"storage={storage} tile={tile} xcd={xcd}", flush=True)
+            s = solver(lbm, p, phi0, T0, storage, tile)
+            s.set_launch(tile, xcd)
+            s.step(40)
+            blob = s.save()
+            if ref is None:
+                ref = blob
+            assert blob == ref, (tile, xcd)
+
+
+def test_fp16_checkpoint_round_trip():
+    lbm = _lbm()
+    p, phi0, T0, _ = W.workload("sessile128", seed=1)
+    a = solver(lbm, p, phi0, T0, "fp16")
+    a.step(30)
+    blob = a.save()
+    assert len(blob) == 32 + 27 * 2 * p["nx"] * p["ny"] + 6 * 4 * p["nx"] * p["ny"]
+    a.step(30)
+    after = a.save()
+    b = solver(lbm, p, phi0, T0, "fp16")
+    b.load(blob)
+    assert b.step_count == 30
+    b.step(30)
+    assert b.save() == after
+    c = solver(lbm, p, phi0, T0, "bf16")
+    with pytest.raises(lbm.LbmError):
+        c.load(blob)  # a checkpoint of another storage format is refused
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_populations_after_one_step(oracle_mod, storage):
+    """Unshifted populations after one step: the oracle's up to one rounding
+    of the stored value (relative 2^-11 FP16, 2^-8 BF16, of values below 10
+    here) plus the FP32 path's own error."""
+    lbm = _lbm()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    g = solver(lbm, p, phi0, T0, storage)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    g.step(1)
+    o.step(1)
+    u = 2.0 ** -11 if storage == "fp16" else 2.0 ** -8
+    for lat, mag in (("g", 0.1), ("f", 1e-2), ("h", 1.0)):
+        d = np.abs(g.pops(lat) - o.pops(lat)).max()
+        print(f"[{storage}] pops {lat}: max|d| {d:.2e}", flush=True)
+        assert d <= 2 * u * mag, (lat, d)
+
+
+def test_strips_and_wide_temperature_spans_are_refused():
+    lbm = _lbm()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    s = solver(lbm, p, phi0, T0, "fp16")
+    with pytest.raises(lbm.LbmError) as e:
+        s.set_launch("strip60x64", 1)
+    assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Solver(dict(p, storage=lbm.STORAGE["fp16"], T_bottom=-1e5), phi0, T0)
+    assert e.value.code == lbm.LBM_EINVAL
+
+
+@pytest.mark.skipif(not __import__("os").environ.get("LBM_STORAGE_REPORT"),
+                    reason="long report run: set LBM_STORAGE_REPORT=<steps> (about 3 min of oracle time per 1e4 steps)")
+def test_storage_report_bubbles1024(oracle_mod):
+    """Error of FP32, FP16 and BF16 storage against the FP64 oracle on the
+    1024x512 droplet with bubbles (R = 160, 1-8 bubbles, chi = 1) over a
+    slice of steps: pointwise and L2 field errors, and the integrals."""
+    import os
+
+    lbm = _lbm()
+    steps = int(os.environ["LBM_STORAGE_REPORT"])
+    p, phi0, T0, meta = W.workload("bubbles1024", seed=0)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    runs = {st: solver(lbm, p, phi0, T0, st) for st in ("fp32", "fp16", "bf16")}
+    done = 0
+    for n in sorted({max(1, steps * j // 5) for j in range(1, 6)}):
+        o.step(n - done)
+        for s in runs.values():
+            s.step(n - done)
+        done = n
+        fo, do = o.fields(FIELDS), o.diag()
+        for st, s in runs.items():
+            e = errors(s.fields(FIELDS), fo)
+            dg = s.diag()
+            assert dg["rc"] == 0
+            ints = {k: abs(dg[k] - do[k]) / abs(do[k]) for k in ("sum_phi", "sum_H", "sum_solid")}
+            show(f"report bubbles1024 step {n} {st}", dict(e, **ints, dh_c=abs(dg["h_c"] - do["h_c"])))
