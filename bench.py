@@ -78,6 +78,84 @@ def pick_launch(solver, args):
     return args.tile, mode
 
 
+def plain_until_frozen(lbm, d, every: int, max_steps: int):
+    """One droplet alone on the plain single-grid solver (FP32 storage):
+    step in intervals, read the liquid volume, stop at 1 % of the initial."""
+    import torch
+
+    s = lbm.Solver(dict(d["params"], storage=lbm.STORAGE["fp32"]), d["phi0"], d["T0"])
+    s.autotune(reps=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, liq = [0], [s.diag()["sum_liquid"]]
+    while steps[-1] < max_steps:
+        s.step(every)
+        steps.append(steps[-1] + every)
+        liq.append(s.diag()["sum_liquid"])
+        if liq[-1] <= 0.01 * liq[0]:
+            break
+    secs = time.perf_counter() - t0
+    thr = 0.01 * liq[0]
+    a, c = liq[-2], liq[-1]
+    tf = steps[-2] + every * min(max((a - thr) / (a - c), 0.0), 1.0) if c <= thr and a > c else float("nan")
+    return tf, steps[-1], secs
+
+
+def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float):
+    """The batched sweep: n droplets (R ~ U(16,64), theta ~ U(60,150),
+    Ste ~ U(0.05,0.3), gamma ~ U(0.85,1.1), 0-8 bubbles, grid 4R x 3R, FP16
+    storage) all run until frozen as one queue, against the plain FP32 solver
+    one droplet at a time on a random subsample of the same droplets."""
+    import numpy as np
+    import torch
+
+    every, max_steps = 200, 2_000_000
+    drops = W.sweep_droplets(n, seed=0, storage=lbm.STORAGE["fp16"])
+    b = lbm.Batch([d["params"] for d in drops], [d["phi0"] for d in drops], [d["T0"] for d in drops],
+                  radii=[d["R"] for d in drops], slots=n)
+    b.configure(sample_every=every, max_steps=max_steps)
+    tile, grp = b.autotune(reps=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        b.step(50000, until_frozen=True)
+        res = b.results()
+        done = sum(r["status"] != "running" and r["status"] != "queued" for r in res)
+        print(f"sweep: {done}/{n} droplets finished after {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+        if done == n or time.perf_counter() - t0 > time_limit:
+            break
+    secs = time.perf_counter() - t0
+    node_steps = sum(d["params"]["nx"] * d["params"]["ny"] * r["steps"] for d, r in zip(drops, res))
+    frozen = [r for r in res if r["status"] == "frozen"]
+    out = {
+        "workload": f"{n} droplets, R~U(16,64), theta~U(60,150), Ste~U(0.05,0.3), gamma~U(0.85,1.1), 0-8 bubbles, "
+                    "grid round(4R) x round(3R), FP16 storage, each run until 1 % of its liquid is left",
+        "droplets": n, "frozen": len(frozen), "seconds": round(secs, 2), "droplets_per_s": round(len(frozen) / secs, 3),
+        "node_steps": int(node_steps), "MLUPS": round(node_steps / secs / 1e6, 1), "tile": tile, "xcd_group": grp,
+        "t_freeze_steps": [round(float(q), 1) for q in np.nanpercentile([r["t_freeze"] for r in res], [0, 50, 100])],
+    }
+    if n_plain > 0:
+        pick = np.random.default_rng(1).choice(n, min(n_plain, n), replace=False)
+        ptime, pwork, errs = 0.0, 0, []
+        for i in pick:
+            tf, st, sec = plain_until_frozen(lbm, drops[i], every, max_steps)
+            ptime += sec
+            pwork += drops[i]["params"]["nx"] * drops[i]["params"]["ny"] * st
+            errs.append(abs(res[i]["t_freeze"] - tf) / tf)
+            print(f"plain: droplet {i} t_freeze {tf:.1f} (batched {res[i]['t_freeze']:.1f}) in {sec:.2f} s",
+                  file=sys.stderr, flush=True)
+        plain_dps = len(pick) / ptime
+        out["plain_fp32"] = {
+            "droplets_per_s": round(plain_dps, 3), "MLUPS": round(pwork / ptime / 1e6, 1),
+            "sample": f"{len(pick)} random droplets of the same sweep, one at a time, FP32 storage, "
+                      f"{ptime:.1f} s",
+        }
+        out["speedup_droplets_per_s"] = round(out["droplets_per_s"] / plain_dps, 2)
+        out["t_freeze_rel_err_max"] = float(f"{max(errs):.2e}")
+    return out
+
+
 def cpu_baseline(params, phi0, T0, budget_s: float):
     import oracle
 
@@ -109,6 +187,9 @@ def main():
                     help="skip the FP16/BF16 storage runs on the 4096x2048 probe")
     ap.add_argument("--probe-steps", type=int, default=100, help="steps on the 4096x2048 grid (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle timing budget (0: skip)")
+    ap.add_argument("--sweep-droplets", type=int, default=256, help="droplets in the batched sweep (0: skip)")
+    ap.add_argument("--sweep-plain", type=int, default=16, help="droplets of the sweep re-run one at a time in FP32")
+    ap.add_argument("--sweep-time-limit", type=float, default=240.0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -215,6 +296,9 @@ def main():
                 }
                 del vs
                 torch.cuda.empty_cache()
+    if args.sweep_droplets > 0:
+        out["sweep"] = sweep_bench(lbm, W, args.sweep_droplets, args.sweep_plain, args.sweep_time_limit)
+        torch.cuda.empty_cache()
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(params, phi0, T0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -145,6 +145,88 @@ int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap);
  * recomputes the next step from the same buffers.  Synchronises. */
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_remap);
 
+/* ---- Batched sweep -----------------------------------------------------
+ * Many droplets (each its own grid and parameters, as in the parametric
+ * study of Sec. 4.2.2) run as one queue: up to `slots` are resident at a
+ * time and every step of all of them is one launch.  A droplet is frozen once its liquid
+ * volume sum clamp(phi) f_l has fallen to freeze_frac (default 0.01) of its
+ * initial value; t_freeze is interpolated linearly between the samples taken
+ * every sample_every steps.  At that sample its shape is measured from the
+ * phi = 1/2 contour: height above the wall (topmost crossing over the
+ * columns + 1/2), base half-width (crossings on row 0) and tip angle (angle
+ * between least-squares lines x(y) through the left and right crossings of
+ * the rows at heights in [0.75, 0.95] of the height).  The freed slot takes
+ * the next queued droplet. */
+
+enum {
+  LBM_DROP_QUEUED = 0,   /* not started */
+  LBM_DROP_RUNNING = 1,  /* resident */
+  LBM_DROP_FROZEN = 2,   /* reached t_freeze and retired */
+  LBM_DROP_LIMIT = 3,    /* retired at max_steps without freezing */
+  LBM_DROP_NONFINITE = 4 /* retired: NaN/Inf in its fields */
+};
+
+typedef struct {
+  int32_t status;       /* LBM_DROP_* */
+  int32_t slot;         /* resident slot, -1 if none */
+  int64_t steps;        /* steps run */
+  double t_freeze;      /* steps (NaN until frozen) */
+  double t_star;        /* Fourier number of t_freeze, k_l t/(rho_l cp_l R^2) (Eq. (42)); NaN without R */
+  double liquid0;       /* liquid volume at the start */
+  double liquid;        /* liquid volume at the last sample */
+  double height;        /* shape at retirement (NaN before) */
+  double base_radius;
+  double tip_angle_deg; /* NaN if fewer than two rows fall in the fit band */
+} lbm_drop_result;
+
+typedef struct lbm_batch lbm_batch;
+
+/* Workspace for n droplets with up to `slots` resident (p: n parameter sets,
+ * all with the same storage; every grid within the single-grid limits). */
+int lbm_batch_workspace_bytes(const lbm_params* p, int32_t n, int32_t slots, size_t* bytes);
+
+/* Set up the queue.  phi0[i], T0[i]: host arrays of p[i].nx*p[i].ny doubles,
+ * read when droplet i enters a slot (the first `slots` here, the rest during
+ * lbm_batch_step): they must stay valid until then.  radius: n initial radii
+ * for t_star, or NULL.  Workspace and stream as for lbm_init. */
+int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, const double* const* T0,
+                   const double* radius, int32_t slots, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                   lbm_batch** out);
+
+/* Sampling interval (even, >= 2; default 100), per-droplet step limit
+ * (0 = none), freezing threshold (default 0.01), and whether each interval
+ * runs as a replayed hipGraph (default 1) or as individual launches. */
+int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, double freeze_frac,
+                        int32_t use_graph);
+
+/* Tile shape (tile_variant 0..4 of lbm_set_launch) and whether each
+ * droplet's tiles are kept on one XCD (xcd_group 1, default) or laid out
+ * droplet after droplet (0); results are bitwise identical either way. */
+int lbm_batch_set_launch(lbm_batch* b, int32_t tile_variant, int32_t xcd_group);
+int lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* tile_variant, int32_t* xcd_group);
+
+/* Advance the resident droplets by nsteps (whole sampling intervals).  With
+ * until_frozen, finished droplets retire and queued ones take their slots,
+ * and the call returns early once the queue is empty.  Synchronises. */
+int lbm_batch_step(lbm_batch* b, int64_t nsteps, int32_t until_frozen);
+
+/* Per-droplet results, n entries. */
+int lbm_batch_results(lbm_batch* b, lbm_drop_result* out);
+
+/* Current fields of a resident droplet (as lbm_fields; LBM_ESTATE if it is
+ * not resident).  Synchronises. */
+int lbm_batch_fields(lbm_batch* b, int32_t drop, uint32_t field_mask, double* const* host_out);
+
+const char* lbm_batch_last_error(void);
+void lbm_batch_destroy(lbm_batch* b);
+
+/* The batch's shape measurement on any phi field (host, ny rows of nx
+ * doubles, row 0 half a spacing above the wall), rounded to FP32 as the
+ * fields are: out[0..3] = height, base radius, tip angle in degrees, number
+ * of rows in the tip fit.  Allocates and synchronises (a utility, not for
+ * hot loops). */
+int lbm_shape_of(const double* phi, int32_t nx, int32_t ny, double* out);
+
 #ifdef __cplusplus
 }
 #endif

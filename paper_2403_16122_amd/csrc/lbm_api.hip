@@ -32,6 +32,10 @@ constexpr int kAuxPlanes = 4 + 8;  // (phi u) x/y, node references, f_s^H, p, S,
 constexpr int kStatePlanes = kPops + 6;  // checkpointed planes
 constexpr int64_t kMagic = 0x4c424d4750555331LL;
 
+}  // namespace
+
+namespace lbmk {
+
 bool all_finite(const lbm_params* p) {
   const double v[] = {p->W,       p->M,      p->sigma,  p->rho_l,  p->rho_g,  p->rho_s,
                       p->mu_l,    p->mu_g,   p->mu_s,   p->cp_l,   p->cp_g,   p->cp_s,
@@ -46,7 +50,7 @@ bool all_finite(const lbm_params* p) {
 // Every relaxation time must exceed 1/2: tau_g = M/cs^2 + 1/2 needs M > 0,
 // tau_f = mu/(rho cs^2) + 1/2 needs mu, rho > 0 in every phase (mixtures
 // stay positive), tau_h = k/(cp_ref cs^2) + 1/2 needs k, cp_ref > 0.
-int validate(const lbm_params* p) {
+int validate_params(const lbm_params* p) {
   if (!p) return LBM_EINVAL;
   if (p->nx < 3 || p->ny < 3) return LBM_EINVAL;
   if ((long long)p->nx * p->ny > (1LL << 32) / 80) return LBM_EINVAL;  // 32-bit element indices over the workspace
@@ -65,20 +69,30 @@ int validate(const lbm_params* p) {
   return LBM_OK;
 }
 
-size_t pop_bytes(const lbm_params* p) { return p->storage == LBM_STORE_FP32 ? 4 : 2; }
-bool is_strip(int tile_variant) { return tile_variant >= 5; }
+size_t pop_bytes(int storage) { return storage == LBM_STORE_FP32 ? 4 : 2; }
 
-long long plane_floats(const lbm_params* p) {
-  const long long n = (long long)p->nx * p->ny;
-  return (n + 63) / 64 * 64;  // 256-byte aligned planes
+long long plane_floats(long long nodes) { return (nodes + 63) / 64 * 64; }  // 256-byte aligned planes
+
+size_t state_bytes(long long plane, int storage) {
+  return (size_t)2 * kPops * plane * pop_bytes(storage) + (size_t)(kAuxPlanes + NFIELD) * plane * sizeof(float);
 }
 
-size_t part_bytes() { return (size_t)(lbmk::RED_BLOCKS + 1) * lbmk::RED_NVAL * sizeof(double); }
-
-size_t ws_size(const lbm_params* p) {
-  const long long pl = plane_floats(p);
-  return (size_t)2 * kPops * pl * pop_bytes(p) + (size_t)(kAuxPlanes + lbmk::NFIELD) * pl * sizeof(float) +
-         part_bytes();
+void carve_state(State& S, char* base, long long pl, int storage) {
+  const size_t popbuf = (size_t)kPops * pl * pop_bytes(storage);  // multiple of 256 bytes
+  S.pops[0] = base;
+  S.pops[1] = base + popbuf;
+  float* aux = (float*)(base + 2 * popbuf);
+  S.phiu[0] = aux;
+  S.phiu[1] = aux + 2 * pl;
+  S.fsH[0] = aux + 4 * pl;
+  S.fsH[1] = aux + 5 * pl;
+  S.p[0] = aux + 6 * pl;
+  S.p[1] = aux + 7 * pl;
+  S.S[0] = aux + 8 * pl;
+  S.S[1] = aux + 9 * pl;
+  S.ref[0] = aux + 10 * pl;
+  S.ref[1] = aux + 11 * pl;
+  S.fields = aux + kAuxPlanes * pl;
 }
 
 // FP16 scales (powers of two).  g and the shifted h stay O(1) and f is
@@ -86,7 +100,7 @@ size_t ws_size(const lbm_params* p) {
 // subnormals while leaving a wide margin below its maximum 65504: |g| < 256,
 // |f| < 64, and h within 16x of the largest enthalpy excess the parameters
 // and the initial temperature imply.
-void fp16_scales(const lbm_params& p, double tspan, lbmk::KParams& K) {
+void fp16_scales(const lbm_params& p, double tspan, KParams& K) {
   const double cpmax = std::max(std::max(p.cp_l, p.cp_g), std::max(p.cp_s, p.cp_ref));
   const double hmax = cpmax * std::max(tspan, 1.0) + p.latent;
   double sh = 16.0;
@@ -98,33 +112,11 @@ void fp16_scales(const lbm_params& p, double tspan, lbmk::KParams& K) {
   }
 }
 
-}  // namespace
 
-struct lbm_ctx {
-  lbm_params P;
-  lbmk::KParams K;
-  lbmk::IParams I;
-  lbmk::State S;
-  hipStream_t stream;
-  int device;
-  void* ws;
-  bool own_ws;
-  int cur;
-  int64_t step;
-  int tile_variant;
-  int xcd;
-  double Href;
-  std::vector<float> stage;
-};
-
-namespace {
-
-void fill_kparams(lbm_ctx* c) {
-  const lbm_params& p = c->P;
-  lbmk::KParams& K = c->K;
+void fill_constants(const lbm_params& p, KParams& K, IParams& I, double& Href) {
   K.nx = p.nx;
   K.ny = p.ny;
-  K.plane = (unsigned)plane_floats(&p);
+  K.plane = (unsigned)plane_floats((long long)p.nx * p.ny);
   const double tau_g = 3.0 * p.M + 0.5;
   K.inv_tau_g = (float)(1.0 / tau_g);
   K.src_g = (float)(1.0 - 0.5 / tau_g);
@@ -150,34 +142,61 @@ void fill_kparams(lbm_ctx* c) {
   K.bq_coef = (float)(p.bq_rho0 * p.bq_beta);
   K.bq_Tref = (float)p.bq_Tref;
   K.chi = (float)p.st_solid_mask;
+  K.seed = 0;
   K.storage = p.storage;
   for (int j = 0; j < 3; ++j) K.sc_st[j] = K.sc_ld[j] = 1.0f;
-  c->I.cp_l = p.cp_l;
-  c->I.cp_g = p.cp_g;
-  c->I.cp_ref = p.cp_ref;
-  c->I.T_melt = p.T_melt;
-  c->I.latent = p.latent;
-  c->Href = p.cp_ref * p.T_melt + p.latent;
+  I.cp_l = p.cp_l;
+  I.cp_g = p.cp_g;
+  I.cp_ref = p.cp_ref;
+  I.T_melt = p.T_melt;
+  I.latent = p.latent;
+  Href = p.cp_ref * p.T_melt + p.latent;
 }
+
+// Temperatures stay within the initial and wall values (maximum
+// principle); 16-bit storage keeps T - T_m of every node as an FP16
+// reference, which needs that span well inside FP16's range.
+int storage_setup(const lbm_params& p, const double* T0, long long N, KParams& K) {
+  double tspan = std::fabs(p.T_bottom - p.T_melt);
+  for (long long k = 0; k < N; ++k) tspan = std::max(tspan, std::fabs(T0[k] - p.T_melt));
+  if (p.storage != LBM_STORE_FP32 && !(tspan < 3.0e4)) return LBM_EINVAL;
+  if (p.storage == LBM_STORE_FP16_SHIFT) fp16_scales(p, tspan, K);
+  return LBM_OK;
+}
+
+
+}  // namespace lbmk
+
+struct lbm_ctx {
+  lbm_params P;
+  lbmk::KParams K;
+  lbmk::IParams I;
+  lbmk::State S;
+  hipStream_t stream;
+  int device;
+  void* ws;
+  bool own_ws;
+  int cur;
+  int64_t step;
+  int tile_variant;
+  int xcd;
+  double Href;
+  std::vector<float> stage;
+};
+
+namespace {
+
+size_t part_bytes() { return (size_t)(lbmk::RED_BLOCKS + 1) * lbmk::RED_NVAL * sizeof(double); }
+
+size_t ws_size(const lbm_params* p) {
+  return lbmk::state_bytes(lbmk::plane_floats((long long)p->nx * p->ny), p->storage) + part_bytes();
+}
+
+bool is_strip(int tile_variant) { return tile_variant >= 5; }
 
 void carve(lbm_ctx* c) {
   const long long pl = c->K.plane;
-  const size_t popbuf = (size_t)kPops * pl * pop_bytes(&c->P);  // multiple of 256 bytes
-  char* base = (char*)c->ws;
-  c->S.pops[0] = base;
-  c->S.pops[1] = base + popbuf;
-  float* aux = (float*)(base + 2 * popbuf);
-  c->S.phiu[0] = aux;
-  c->S.phiu[1] = aux + 2 * pl;
-  c->S.fsH[0] = aux + 4 * pl;
-  c->S.fsH[1] = aux + 5 * pl;
-  c->S.p[0] = aux + 6 * pl;
-  c->S.p[1] = aux + 7 * pl;
-  c->S.S[0] = aux + 8 * pl;
-  c->S.S[1] = aux + 9 * pl;
-  c->S.ref[0] = aux + 10 * pl;
-  c->S.ref[1] = aux + 11 * pl;
-  c->S.fields = aux + kAuxPlanes * pl;
+  lbmk::carve_state(c->S, (char*)c->ws, pl, c->P.storage);
   c->S.part = (double*)(c->S.fields + lbmk::NFIELD * pl);
 }
 
@@ -191,7 +210,7 @@ int run_fields(lbm_ctx* c) {
 // the populations in their storage format, then the FP32 history planes.
 int copy_state(lbm_ctx* c, char* host, bool save) {
   const size_t N = (size_t)c->P.nx * c->P.ny;
-  const size_t pb = pop_bytes(&c->P);
+  const size_t pb = lbmk::pop_bytes(c->P.storage);
   void* dev[kStatePlanes];
   for (int i = 0; i < kPops; ++i) dev[i] = (char*)c->S.pops[c->cur] + (size_t)i * c->K.plane * pb;
   dev[kPops + 0] = c->S.phiu[c->cur];
@@ -218,7 +237,7 @@ extern "C" {
 
 int lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
   if (!bytes) return LBM_EINVAL;
-  int rc = validate(p);
+  int rc = lbmk::validate_params(p);
   if (rc) return rc;
   *bytes = ws_size(p);
   return LBM_OK;
@@ -228,7 +247,7 @@ int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_
              size_t ws_bytes, void* hip_stream, lbm_ctx** out) {
   if (!out) return LBM_EINVAL;
   *out = nullptr;
-  int rc = validate(p);
+  int rc = lbmk::validate_params(p);
   if (rc) {
     g_last_error = "invalid parameters";
     return rc;
@@ -245,12 +264,11 @@ int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_
       g_last_error = "non-finite initial field";
       return LBM_EINVAL;
     }
-  // Temperatures stay within the initial and wall values (maximum
-  // principle); 16-bit storage keeps T - T_m of every node as an FP16
-  // reference, which needs that span well inside FP16's range.
-  double tspan = std::fabs(p->T_bottom - p->T_melt);
-  for (long long k = 0; k < N; ++k) tspan = std::max(tspan, std::fabs(T0[k] - p->T_melt));
-  if (p->storage != LBM_STORE_FP32 && !(tspan < 3.0e4)) {
+  lbmk::KParams K;
+  lbmk::IParams I;
+  double Href;
+  lbmk::fill_constants(*p, K, I, Href);
+  if (lbmk::storage_setup(*p, T0, N, K)) {
     g_last_error = "temperature span too wide for the FP16 node references of 16-bit storage";
     return LBM_EINVAL;
   }
@@ -267,8 +285,9 @@ int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_
     delete c;
     return dev_error(e, "hipGetDevice");
   }
-  fill_kparams(c);
-  if (p->storage == LBM_STORE_FP16_SHIFT) fp16_scales(*p, tspan, c->K);
+  c->K = K;
+  c->I = I;
+  c->Href = Href;
   if (d_workspace) {
     c->ws = d_workspace;
     c->own_ws = false;
@@ -303,6 +322,7 @@ int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_
 int lbm_step(lbm_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
   for (int32_t s = 0; s < nsteps; ++s) {
+    c->K.seed = (unsigned)c->step;  // the step number seeds 16-bit stochastic rounding
     if (lbmk::launch_step(c->K, c->S, c->cur, false, c->tile_variant, c->xcd, c->stream))
       return dev_error(hipGetLastError(), "step kernel launch");
     c->cur ^= 1;
@@ -410,7 +430,7 @@ int lbm_pops(lbm_ctx* c, int32_t lattice, double* host_out) {
 size_t lbm_state_bytes(const lbm_ctx* c) {
   if (!c) return 0;
   const size_t N = (size_t)c->P.nx * c->P.ny;
-  return 4 * sizeof(int64_t) + (size_t)kPops * N * pop_bytes(&c->P) +
+  return 4 * sizeof(int64_t) + (size_t)kPops * N * lbmk::pop_bytes(c->P.storage) +
          (size_t)(kStatePlanes - kPops) * N * sizeof(float);
 }
 

@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "lbm.h"
+
 namespace lbmk {
 
 // Precomputed lattice-unit constants handed to every kernel by value.
@@ -27,6 +29,7 @@ struct KParams {
   float chi;                       // surface-tension solid mask
   int storage;                     // STORE_FP32 / STORE_FP16 / STORE_BF16
   float sc_st[3], sc_ld[3];        // FP16 only: per-lattice power-of-two scale on store / load
+  unsigned seed;                   // 16-bit storage: step number, seeds the stochastic rounding
 };
 
 enum { STORE_FP32 = 0, STORE_FP16 = 1, STORE_BF16 = 2 };
@@ -41,6 +44,38 @@ struct State {
   float* S[2];     // mass-source term S of the previous step
   float* fields;   // 10 planes of output fields
   double* part;    // reduction scratch
+};
+
+// Buffers one step reads (time n) and writes (time n+1).  The step is a
+// pure function of the *_in buffers, so it can be replayed for timing.
+struct StepIO {
+  const void* A;  // populations of time n (storage type of the instantiation)
+  void* B;        // populations of time n+1
+  const float* phiu_in;
+  float* phiu_out;
+  const void* ref_in;  // node references (FP32 phi_ref, or FP16 pairs (phi_ref, th))
+  void* ref_out;
+  const float* fsH_in;
+  float* fsH_out;
+  const float* p_in;
+  float* p_out;
+  const float* S_in;
+  float* S_out;
+  float* fields;
+};
+
+
+inline StepIO make_io(const State& S, int cur) {
+  const int nxt = cur ^ 1;
+  return StepIO{S.pops[cur], S.pops[nxt], S.phiu[cur], S.phiu[nxt], S.ref[cur], S.ref[nxt],
+                S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur], S.S[nxt], S.fields};
+}
+
+// The buffer set of one grid of a batch as byte offsets from the batch's
+// workspace base.  The kernels rebuild the pointers from the base they get
+// as an argument, so the compiler knows every access is to global memory.
+struct StepOff {
+  unsigned long long A, B, phiu_in, phiu_out, ref_in, ref_out, fsH_in, fsH_out, p_in, p_out, S_in, S_out, fields;
 };
 
 enum { NFIELD = 10 };
@@ -62,5 +97,42 @@ int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int
 int launch_expand(const KParams& P, const State& S, int cur, int lattice, hipStream_t st);
 // Reduces the field planes into RED_NVAL doubles at part[RED_BLOCKS * RED_NVAL].
 int launch_reduce(const KParams& P, const State& S, double Href, hipStream_t st);
+
+// ---- host-side set-up shared by the single-grid and batch contexts --------
+int validate_params(const lbm_params* p);
+size_t pop_bytes(int storage);
+long long plane_floats(long long nodes);
+// Bytes of one grid's state (both population buffers, history planes and
+// the NFIELD output planes) at the given plane stride; carve_state lays it
+// out from `base` (S.part is left alone).
+size_t state_bytes(long long plane, int storage);
+void carve_state(State& S, char* base, long long plane, int storage);
+// Kernel constants of p (K.plane = nx*ny rounded up to 64).
+void fill_constants(const lbm_params& p, KParams& K, IParams& I, double& Href);
+// Storage-dependent constants from the initial temperature; LBM_EINVAL if
+// the temperature span does not fit the FP16 references of 16-bit storage.
+int storage_setup(const lbm_params& p, const double* T0, long long N, KParams& K);
+
+// ---- batches of grids ------------------------------------------------------
+enum { NBATCH_VARIANTS = 5 };  // the tile shapes of variants 0..4
+void tile_shape(int tile_variant, int* tx, int* ty);
+// Step s (0-based, even at a sample) of a sampling interval, or the fields
+// pass (s = 0), for every tile listed in d_tmap (nblocks entries:
+// slot << 16 | tile, ~0u = none), with the per-slot constants d_ptab[slot],
+// buffer sets d_otab[2 slot + (s & 1)] (offsets from d_base) and step
+// numbers d_steps[slot] + s (seeds of the stochastic rounding).
+int launch_batch(int storage, int tile_variant, bool fields_only, char* d_base, const KParams* d_ptab,
+                 const StepOff* d_otab, const unsigned* d_tmap, const unsigned* d_steps, int nblocks, int s,
+                 hipStream_t st);
+// Per listed slot (d_slots, nslots entries), from its field planes:
+// out[2 slot] = sum clamp(phi) f_l (liquid volume), out[2 slot + 1] = number
+// of non-finite phi, T, u values.
+int launch_batch_liquid(const char* d_base, const KParams* d_ptab, const StepOff* d_otab, const int* d_slots,
+                        int nslots, double* d_out, hipStream_t st);
+// Per listed slot, shape of the phi = 1/2 contour from its field planes:
+// out[4 slot + 0..3] = height above the wall, base half-width on row 0,
+// tip angle in degrees, number of contour points in the tip fit.
+int launch_batch_shape(const char* d_base, const KParams* d_ptab, const StepOff* d_otab, const int* d_slots,
+                       int nslots, double* d_out, hipStream_t st);
 
 }  // namespace lbmk

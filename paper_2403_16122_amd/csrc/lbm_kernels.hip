@@ -58,10 +58,33 @@ __device__ __forceinline__ void st(float* __restrict__ base, unsigned idx, float
 __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
 
 // Population storage.  FP32 keeps the shifted populations as computed.  The
-// 16-bit formats round them to nearest-even; FP16 first multiplies by a
-// per-lattice power of two (exact in FP32, undone on load) so that the
-// small shifted values stay in its normal range.  BF16 has FP32's exponent
-// range and is not scaled.  Compute is FP32 throughout.
+// 16-bit formats round them stochastically (the hardware's v_cvt_sr_*: the
+// random word is added below the kept mantissa bits before truncation), so
+// the rounding error has zero mean even where a node stores the same value
+// step after step; round-to-nearest there loses phase-field mass steadily
+// and shifts freezing times by percents.  The random word of a store is a
+// hash of the node index and the step number, xor-ed with a constant per
+// population, so results do not depend on the launch shape.  FP16 first multiplies by a per-lattice power of two (exact
+// in FP32, undone on load) so that the small shifted values stay in its
+// normal range; BF16 has FP32's exponent range and is not scaled.  Compute
+// is FP32 throughout.
+typedef __bf16 bf162v __attribute__((ext_vector_type(2)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+// 32-bit finalizer of MurmurHash3 (a bijective avalanche mix).
+__device__ __forceinline__ unsigned fmix32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ unsigned sr_node(unsigned k, unsigned seed) {
+  return fmix32(k * 0x9e3779b1u ^ seed * 0x85ebca77u);
+}
+// word of population j (0..26) of a node from its hash
+__device__ __forceinline__ constexpr unsigned sr_pop(int j) { return 0x9e3779b9u * (unsigned)(j + 1); }
 template <class PT>
 struct PopIO;
 // kNodeRef: the 16-bit formats keep h relative to the writing node's own
@@ -74,7 +97,7 @@ struct PopIO<float> {
   static constexpr bool kNodeRef = false;
   static constexpr bool kScaled = false;
   static __device__ __forceinline__ float get(const void* b, unsigned idx) { return ld((const float*)b, idx); }
-  static __device__ __forceinline__ void put(void* b, unsigned idx, float v) { st((float*)b, idx, v); }
+  static __device__ __forceinline__ void put(void* b, unsigned idx, float v, unsigned) { st((float*)b, idx, v); }
 };
 template <>
 struct PopIO<_Float16> {
@@ -83,8 +106,10 @@ struct PopIO<_Float16> {
   static __device__ __forceinline__ float get(const void* b, unsigned idx) {
     return (float)*(const _Float16*)((const char*)b + (idx << 1));
   }
-  static __device__ __forceinline__ void put(void* b, unsigned idx, float v) {
-    *(_Float16*)((char*)b + (idx << 1)) = (_Float16)v;
+  static __device__ __forceinline__ void put(void* b, unsigned idx, float v, unsigned rnd) {
+    half2v h = {0, 0};
+    h = __builtin_amdgcn_cvt_sr_f16_f32(h, v, rnd, false);
+    *(_Float16*)((char*)b + (idx << 1)) = h.x;
   }
 };
 template <>
@@ -94,8 +119,10 @@ struct PopIO<__bf16> {
   static __device__ __forceinline__ float get(const void* b, unsigned idx) {
     return (float)*(const __bf16*)((const char*)b + (idx << 1));
   }
-  static __device__ __forceinline__ void put(void* b, unsigned idx, float v) {
-    *(__bf16*)((char*)b + (idx << 1)) = (__bf16)v;
+  static __device__ __forceinline__ void put(void* b, unsigned idx, float v, unsigned rnd) {
+    bf162v h = {0, 0};
+    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, rnd, false);
+    *(__bf16*)((char*)b + (idx << 1)) = h.x;
   }
 };
 // Node references.  FP32 storage keeps phi_ref, the reference of the stored
@@ -103,7 +130,6 @@ struct PopIO<__bf16> {
 // (phi_ref, th) as two FP16 values in one 32-bit word per node: the writer
 // first rounds its phi and T - T_m to FP16 and shifts by the rounded
 // values, so writer and readers use identical references.
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 template <bool NR>
 struct RefIO;
 template <>
@@ -143,10 +169,11 @@ __device__ __forceinline__ float pop_ld(const void* A, unsigned idx, const KPara
   if constexpr (PopIO<PT>::kScaled) v *= P.sc_ld[LAT];
   return v;
 }
+// rnd: the node's hash (sr_node) xor sr_pop(population); unused for FP32
 template <class PT, int LAT>
-__device__ __forceinline__ void pop_st(void* B, unsigned idx, float v, const KParams& P) {
+__device__ __forceinline__ void pop_st(void* B, unsigned idx, float v, const KParams& P, unsigned rnd) {
   if constexpr (PopIO<PT>::kScaled) v *= P.sc_st[LAT];
-  PopIO<PT>::put(B, idx, v);
+  PopIO<PT>::put(B, idx, v, rnd);
 }
 // Plane `j` of a population buffer.
 template <class PT>
@@ -311,24 +338,6 @@ __device__ __forceinline__ void finish_macro(const KParams& P, float rs, Macro& 
   m.mu = mix3(fsol, pc, P.mu_s, P.mu_l, P.mu_g);
 }
 
-// Buffers one step reads (time n) and writes (time n+1).  The step is a
-// pure function of the *_in buffers, so it can be replayed for timing.
-struct StepIO {
-  const void* A;  // populations of time n (storage type of the instantiation)
-  void* B;        // populations of time n+1
-  const float* phiu_in;
-  float* phiu_out;
-  const void* ref_in;  // node references (FP32 phi_ref, or FP16 pairs (phi_ref, th))
-  void* ref_out;
-  const float* fsH_in;
-  float* fsH_out;
-  const float* p_in;
-  float* p_out;
-  const float* S_in;
-  float* S_out;
-  float* fields;
-};
-
 // Gradients and Laplacian of Eq. (38) at one node: phi (with its
 // Laplacian) and rho at time t, lagged p and S.
 struct Grads {
@@ -420,6 +429,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
   const unsigned pl = P.plane;
   void* __restrict__ B = io.B;
   float r_new, th_new;  // references the stored g and h take this step
+  const unsigned rb = PopIO<PT>::kNodeRef ? sr_node(k, P.seed) : 0u;  // stochastic-rounding hash
   // flow collision (Eq. (30)-(33))
   {
     const float itau = rcp(tauf), sf = 1.0f - 0.5f * itau;
@@ -433,7 +443,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float feq = 3.0f * p * (wt(i) - (i == 0 ? 1.0f : 0.0f)) + rho * si;
       const float cF = cx * Ftx + cy * Fty;
       const float Fi = wt(i) * (Ssrc + 3.0f * (cx * Gx + cy * Gy) + 9.0f * cu * cF - 3.0f * uFt);
-      pop_st<PT, 1>(Bf, i * pl + k, f[i] - (f[i] - feq) * itau + sf * Fi, P);
+      pop_st<PT, 1>(Bf, i * pl + k, f[i] - (f[i] - feq) * itau + sf * Fi, P, rb ^ sr_pop(9 + i));
     }
   }
   // phase-field collision (Eq. (21), (24), (25), (37))
@@ -454,7 +464,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float gi = m.g[i] + wt(i) * dr;                 // g_i - w_i phi_ref
       const float geq = wt(i) * (dln + 3.0f * phi * cu);  // g_i^eq - w_i phi_ref
       const float Gi = wt(i) * (cx * ax + cy * ay + pm);
-      pop_st<PT, 0>(B, i * pl + k, gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi, P);
+      pop_st<PT, 0>(B, i * pl + k, gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi, P, rb ^ sr_pop(i));
     }
     RefIO<PopIO<PT>::kNodeRef>::store(io.ref_out, k, r_new, th_new);
     st(io.phiu_out, k, pux);
@@ -477,7 +487,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float heq = wt(i) * (crd + cpT * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
       float hn = m.h[i] - (m.h[i] - heq) * itau;
       if (NR) hn += wt(i) * cmove;
-      pop_st<PT, 2>(Bh, i * pl + k, hn, P);
+      pop_st<PT, 2>(Bh, i * pl + k, hn, P, rb ^ sr_pop(18 + i));
       hs += m.h[i];
     }
     // rest population: h0eq - h0 = sum_{i>0} h_i - cp_ref dT + w0 (cp_ref dT - 1.5 cp T u.u);
@@ -485,7 +495,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
     const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
     float h0 = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
     if (NR) h0 += W0 * cmove;
-    pop_st<PT, 2>(Bh, k, h0, P);
+    pop_st<PT, 2>(Bh, k, h0, P, rb ^ sr_pop(18));
   }
   st(io.fsH_out, k, m.fsH);
   st(io.p_out, k, p);
@@ -500,9 +510,10 @@ __device__ __forceinline__ int map_tile(int b, int mode, int tiles_per_xcd) {
   return mode == 1 ? (b & 7) * tiles_per_xcd + (b >> 3) : b;
 }
 
+// One TX x TY tile (origin x0, y0) of the fused step; shared by the
+// single-grid kernel and the batched one.
 template <int TX, int TY, bool FIELDS, class PT>
-__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) void k_step(KParams P, StepIO io, int ntx, int ntiles,
-                                                 int tiles_per_xcd, int mode) {
+__device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, int x0, int y0) {
   constexpr int NT = TX * TY;
   constexpr int LX = TX + 4, LY = TY + 2;  // LDS column c <-> x0 + c - 2, row r <-> y0 + r - 1
   constexpr int RX = LX + 2, RY = LY + 2;  // reference tile: one more cell on every side
@@ -516,10 +527,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
   __shared__ float s_th[NR ? RY : 1][NR ? RX : 1];  // reference T - T_m of the stored h
 
   const void* __restrict__ A = io.A;
-  const int tile = map_tile(blockIdx.x, mode, tiles_per_xcd);
-  if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
   const int nx = P.nx, ny = P.ny;
-  const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
   const int t = threadIdx.x;
   const int lx = t % TX, ly = t / TX;
   const int x = x0 + lx, y = y0 + ly;
@@ -646,6 +654,39 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
   LBM_TILE_STENCIL(s_S, d.Sx, d.Sy, nullptr);
 #undef LBM_TILE_STENCIL
   update_node<FIELDS, PT>(P, io, m, f, phiux, phiuy, d, k);
+}
+
+template <int TX, int TY, bool FIELDS, class PT>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) void k_step(
+    KParams P, StepIO io, int ntx, int ntiles, int tiles_per_xcd, int mode) {
+  const int tile = map_tile(blockIdx.x, mode, tiles_per_xcd);
+  if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
+  step_tile<TX, TY, FIELDS, PT>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
+}
+
+__device__ __forceinline__ StepIO io_of(char* base, const StepOff& o) {
+  return StepIO{base + o.A, base + o.B, (const float*)(base + o.phiu_in), (float*)(base + o.phiu_out),
+                base + o.ref_in, base + o.ref_out, (const float*)(base + o.fsH_in), (float*)(base + o.fsH_out),
+                (const float*)(base + o.p_in), (float*)(base + o.p_out), (const float*)(base + o.S_in),
+                (float*)(base + o.S_out), (float*)(base + o.fields)};
+}
+
+// Many grids in one launch: workgroup b updates tile tmap[b] & 0xffff of the
+// grid in slot tmap[b] >> 16 (entries of ~0u are padding), with that slot's
+// constants and its buffer set for parity `par`.
+template <int TX, int TY, bool FIELDS, class PT>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) void k_batch(
+    char* __restrict__ base, const KParams* __restrict__ ptab, const StepOff* __restrict__ otab,
+    const unsigned* __restrict__ tmap, const unsigned* __restrict__ steps, int s) {
+  const unsigned e = tmap[blockIdx.x];
+  if (e == ~0u) return;
+  const int slot = (int)(e >> 16), tile = (int)(e & 0xffffu);
+  const int par = s & 1;
+  KParams P = ptab[slot];
+  P.seed = steps[slot] + (unsigned)s;  // the grid's own step number
+  const StepIO io = io_of(base, otab[2 * slot + par]);
+  const int ntx = (P.nx + TX - 1) / TX;
+  step_tile<TX, TY, FIELDS, PT>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
 }
 
 // Sliding-window variant for large grids.  A workgroup is one wavefront
@@ -886,11 +927,13 @@ __global__ void k_init(KParams P, IParams I, const double* __restrict__ phi0,
     RefIO<PopIO<PT>::kNodeRef>::round((float)ph, (float)dT, ref0, th0);
     RefIO<PopIO<PT>::kNodeRef>::store(ref, (unsigned)k, ref0, th0);
     for (int i = 0; i < 9; ++i) {
-      pop_st<PT, 0>(A, (unsigned)(i * pl + k), (float)(w[i] * (ph - (double)ref0)), P);
-      pop_st<PT, 1>(A, (unsigned)((9 + i) * pl + k), 0.0f, P);
+      const unsigned rb = sr_node((unsigned)k, P.seed);
+      pop_st<PT, 0>(A, (unsigned)(i * pl + k), (float)(w[i] * (ph - (double)ref0)), P, rb ^ sr_pop(i));
+      pop_st<PT, 1>(A, (unsigned)((9 + i) * pl + k), 0.0f, P, rb ^ sr_pop(9 + i));
       const double hs = i == 0 ? (H0 - Href) - I.cp_ref * dT + w[0] * I.cp_ref * dT + I.latent * (double)fs0
                                : w[i] * I.cp_ref * dT;
-      pop_st<PT, 2>(A, (unsigned)((18 + i) * pl + k), (float)(hs - w[i] * I.cp_ref * (double)th0), P);
+      pop_st<PT, 2>(A, (unsigned)((18 + i) * pl + k), (float)(hs - w[i] * I.cp_ref * (double)th0), P,
+                    rb ^ sr_pop(18 + i));
     }
     phiu[k] = 0.0f;
     phiu[pl + k] = 0.0f;
@@ -977,6 +1020,118 @@ __global__ __launch_bounds__(64) void k_reduce2(double* __restrict__ part, int n
   part[RED_BLOCKS * RED_NVAL + j] = r;  // final values after the partials
 }
 
+// ---- per-grid reductions of a batch (one workgroup per grid) -------------
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+__device__ __forceinline__ double block_max256(double v, double* sh) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__global__ __launch_bounds__(256) void k_batch_liquid(const char* __restrict__ base,
+                                                      const KParams* __restrict__ ptab,
+                                                      const StepOff* __restrict__ otab,
+                                                      const int* __restrict__ slots, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int slot = slots[blockIdx.x];
+  const int nx = ptab[slot].nx, ny = ptab[slot].ny;
+  const unsigned pl = ptab[slot].plane;
+  const float* __restrict__ F = (const float*)(base + otab[2 * slot].fields);
+  const unsigned N = (unsigned)nx * (unsigned)ny;
+  double s = 0.0, bad = 0.0;
+  for (unsigned k = threadIdx.x; k < N; k += 256) {
+    const float ph = F[k], T = F[pl + k], ux = F[2 * pl + k], uy = F[3 * pl + k], fl = F[6 * pl + k];
+    s += (double)clamp01(ph) * (double)fl;
+    if (!isfinite(ph) || !isfinite(T) || !isfinite(ux) || !isfinite(uy)) bad += 1.0;
+  }
+  s = block_sum256(s, sh);
+  bad = block_sum256(bad, sh);
+  if (threadIdx.x == 0) {
+    out[2 * slot] = s;
+    out[2 * slot + 1] = bad;
+  }
+}
+
+// Outermost phi = 1/2 crossings of one row of phi (linear interpolation);
+// false if no value reaches 1/2.
+__device__ bool row_crossings(const float* __restrict__ row, int nx, double& xl, double& xr) {
+  int a = -1, b = -1;
+  for (int x = 0; x < nx; ++x)
+    if (row[x] >= 0.5f) {
+      if (a < 0) a = x;
+      b = x;
+    }
+  if (a < 0) return false;
+  xl = a == 0 ? 0.0 : (a - 1) + (0.5 - (double)row[a - 1]) / ((double)row[a] - (double)row[a - 1]);
+  xr = b == nx - 1 ? (double)(nx - 1) : b + ((double)row[b] - 0.5) / ((double)row[b] - (double)row[b + 1]);
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_batch_shape(const char* __restrict__ base,
+                                                     const KParams* __restrict__ ptab,
+                                                     const StepOff* __restrict__ otab,
+                                                     const int* __restrict__ slots, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int slot = slots[blockIdx.x];
+  const int nx = ptab[slot].nx, ny = ptab[slot].ny;
+  const float* __restrict__ phi = (const float*)(base + otab[2 * slot].fields);  // field plane 0
+  // height: highest phi = 1/2 crossing over the columns, from the wall at y = -1/2
+  double top = -1e300;
+  for (int x = threadIdx.x; x < nx; x += 256) {
+    for (int y = ny - 1; y >= 0; --y) {
+      const float v = phi[y * nx + x];
+      if (v >= 0.5f) {
+        const double yc = y == ny - 1 ? (double)y
+                                      : y + ((double)v - 0.5) / ((double)v - (double)phi[(y + 1) * nx + x]);
+        top = fmax(top, yc);
+        break;
+      }
+    }
+  }
+  top = block_max256(top, sh);
+  const bool any = top > -1e299;
+  const double H = any ? top + 0.5 : nan("");
+  // base half-width from the crossings on row 0
+  double xl0 = 0.0, xr0 = 0.0;
+  const bool has_base = row_crossings(phi, nx, xl0, xr0);
+  // tip: least-squares lines x(y) through the left and right crossings of
+  // the rows whose height y + 1/2 lies in [0.75 H, 0.95 H]
+  double s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};  // left n, y, x, yy, xy; right n, y, x, yy, xy
+  if (any) {
+    for (int y = threadIdx.x; y < ny; y += 256) {
+      const double hy = y + 0.5;
+      if (hy < 0.75 * H || hy > 0.95 * H) continue;
+      double xl, xr;
+      if (!row_crossings(phi + y * nx, nx, xl, xr)) continue;
+      s[0] += 1.0; s[1] += y; s[2] += xl; s[3] += (double)y * y; s[4] += y * xl;
+      s[5] += 1.0; s[6] += y; s[7] += xr; s[8] += (double)y * y; s[9] += y * xr;
+    }
+  }
+  for (int j = 0; j < 10; ++j) s[j] = block_sum256(s[j], sh);
+  if (threadIdx.x == 0) {
+    double ang = nan("");
+    if (s[0] >= 2.0) {
+      const double bl = (s[0] * s[4] - s[2] * s[1]) / (s[0] * s[3] - s[1] * s[1]);
+      const double br = (s[5] * s[9] - s[7] * s[6]) / (s[5] * s[8] - s[6] * s[6]);
+      ang = (atan(bl) - atan(br)) * (180.0 / M_PI);
+    }
+    out[4 * slot + 0] = H;
+    out[4 * slot + 1] = has_base ? 0.5 * (xr0 - xl0) : nan("");
+    out[4 * slot + 2] = ang;
+    out[4 * slot + 3] = s[0];
+  }
+}
+
 template <int TX, int TY, class PT>
 int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int xcd, hipStream_t st) {
   const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
@@ -986,9 +1141,7 @@ int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int
     tpx = (ntiles + 7) / 8;
     grid = 8 * tpx;
   }
-  const int nxt = cur ^ 1;
-  StepIO io{S.pops[cur], S.pops[nxt], S.phiu[cur], S.phiu[nxt], S.ref[cur], S.ref[nxt],
-            S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur], S.S[nxt], S.fields};
+  const StepIO io = make_io(S, cur);
   if (fields_only)
     hipLaunchKernelGGL((k_step<TX, TY, true, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx, xcd);
   else
@@ -1005,9 +1158,7 @@ int launch_column(const KParams& P, const State& S, int cur, bool fields_only, i
     tpx = (nstrips + 7) / 8;
     grid = 8 * tpx;
   }
-  const int nxt = cur ^ 1;
-  StepIO io{S.pops[cur], S.pops[nxt], S.phiu[cur], S.phiu[nxt], S.ref[cur], S.ref[nxt],
-            S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur], S.S[nxt], S.fields};
+  const StepIO io = make_io(S, cur);
   if (fields_only)
     hipLaunchKernelGGL((k_column<SY, true, PT>), dim3(grid), dim3(CW), 0, st, P, io, nsx, nstrips, tpx, xcd);
   else
@@ -1088,6 +1239,72 @@ int launch_expand(const KParams& P, const State& S, int cur, int lattice, hipStr
   else
     hipLaunchKernelGGL(k_expand<float>, dim3(grid), dim3(256), 0, st, P, S.pops[cur], S.ref[cur], lattice,
                        S.fields);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+void tile_shape(int tile_variant, int* tx, int* ty) {
+  static const int T[NBATCH_VARIANTS][2] = {{64, 4}, {32, 8}, {64, 8}, {64, 16}, {128, 4}};
+  const int v = tile_variant >= 0 && tile_variant < NBATCH_VARIANTS ? tile_variant : 0;
+  *tx = T[v][0];
+  *ty = T[v][1];
+}
+
+namespace {
+template <int TX, int TY, class PT>
+int launch_batch_t(bool fields_only, char* base, const KParams* ptab, const StepOff* otab, const unsigned* tmap,
+                   const unsigned* steps, int nblocks, int s, hipStream_t st) {
+  if (fields_only)
+    hipLaunchKernelGGL((k_batch<TX, TY, true, PT>), dim3(nblocks), dim3(TX * TY), 0, st, base, ptab, otab, tmap,
+                       steps, s);
+  else
+    hipLaunchKernelGGL((k_batch<TX, TY, false, PT>), dim3(nblocks), dim3(TX * TY), 0, st, base, ptab, otab, tmap,
+                       steps, s);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+template <class PT>
+int launch_batch_v(int variant, bool fields_only, char* base, const KParams* ptab, const StepOff* otab,
+                   const unsigned* tmap, const unsigned* steps, int nblocks, int s, hipStream_t st) {
+  switch (variant) {
+    case 0:
+      return launch_batch_t<64, 4, PT>(fields_only, base, ptab, otab, tmap, steps, nblocks, s, st);
+    case 1:
+      return launch_batch_t<32, 8, PT>(fields_only, base, ptab, otab, tmap, steps, nblocks, s, st);
+    case 2:
+      return launch_batch_t<64, 8, PT>(fields_only, base, ptab, otab, tmap, steps, nblocks, s, st);
+    case 3:
+      return launch_batch_t<64, 16, PT>(fields_only, base, ptab, otab, tmap, steps, nblocks, s, st);
+    case 4:
+      return launch_batch_t<128, 4, PT>(fields_only, base, ptab, otab, tmap, steps, nblocks, s, st);
+    default:
+      return -1;
+  }
+}
+}  // namespace
+
+int launch_batch(int storage, int tile_variant, bool fields_only, char* d_base, const KParams* d_ptab,
+                 const StepOff* d_otab, const unsigned* d_tmap, const unsigned* d_steps, int nblocks, int s,
+                 hipStream_t st) {
+  if (nblocks <= 0) return 0;
+  if (storage == STORE_FP16)
+    return launch_batch_v<_Float16>(tile_variant, fields_only, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s,
+                                    st);
+  if (storage == STORE_BF16)
+    return launch_batch_v<__bf16>(tile_variant, fields_only, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s,
+                                  st);
+  return launch_batch_v<float>(tile_variant, fields_only, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s, st);
+}
+
+int launch_batch_liquid(const char* d_base, const KParams* d_ptab, const StepOff* d_otab, const int* d_slots,
+                        int nslots, double* d_out, hipStream_t st) {
+  if (nslots <= 0) return 0;
+  hipLaunchKernelGGL(k_batch_liquid, dim3(nslots), dim3(256), 0, st, d_base, d_ptab, d_otab, d_slots, d_out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_batch_shape(const char* d_base, const KParams* d_ptab, const StepOff* d_otab, const int* d_slots,
+                       int nslots, double* d_out, hipStream_t st) {
+  if (nslots <= 0) return 0;
+  hipLaunchKernelGGL(k_batch_shape, dim3(nslots), dim3(256), 0, st, d_base, d_ptab, d_otab, d_slots, d_out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

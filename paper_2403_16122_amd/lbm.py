@@ -28,7 +28,11 @@ EXPORTED = [
     "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_diag",
     "lbm_pops", "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_step_count", "lbm_sync",
     "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_set_launch", "lbm_autotune",
+    "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_configure", "lbm_batch_set_launch",
+    "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_results", "lbm_batch_fields",
+    "lbm_batch_last_error", "lbm_batch_destroy", "lbm_shape_of",
 ]
+DROP_STATUS = {0: "queued", 1: "running", 2: "frozen", 3: "limit", 4: "nonfinite"}
 
 
 class LbmError(RuntimeError):
@@ -58,6 +62,14 @@ class Diag(C.Structure):
         ("step", C.c_int64), ("sum_phi", C.c_double), ("sum_phic", C.c_double),
         ("sum_solid", C.c_double), ("sum_liquid", C.c_double), ("sum_H", C.c_double),
         ("max_u", C.c_double), ("h_c", C.c_double), ("nonfinite", C.c_int32),
+    ]
+
+
+class DropResult(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("slot", C.c_int32), ("steps", C.c_int64), ("t_freeze", C.c_double),
+        ("t_star", C.c_double), ("liquid0", C.c_double), ("liquid", C.c_double), ("height", C.c_double),
+        ("base_radius", C.c_double), ("tip_angle_deg", C.c_double),
     ]
 
 
@@ -95,6 +107,20 @@ def load_library():
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
     L.lbm_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.lbm_batch_workspace_bytes.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+    L.lbm_batch_init.argtypes = [C.POINTER(Params), C.c_int32, C.POINTER(dp), C.POINTER(dp), dp, C.c_int32, vp,
+                                 C.c_size_t, vp, C.POINTER(vp)]
+    L.lbm_batch_configure.argtypes = [vp, C.c_int32, C.c_int64, C.c_double, C.c_int32]
+    L.lbm_batch_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
+    L.lbm_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.lbm_batch_step.argtypes = [vp, C.c_int64, C.c_int32]
+    L.lbm_batch_results.argtypes = [vp, C.POINTER(DropResult)]
+    L.lbm_batch_fields.argtypes = [vp, C.c_int32, C.c_uint32, C.POINTER(dp)]
+    L.lbm_batch_last_error.argtypes = []
+    L.lbm_batch_last_error.restype = C.c_char_p
+    L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_batch_destroy.restype = None
+    L.lbm_shape_of.argtypes = [dp, C.c_int32, C.c_int32, dp]
     _lib = L
     return L
 
@@ -225,3 +251,116 @@ class Solver:
     def load(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
         self._check(self.L.lbm_load(self._h, buf, len(blob)), "lbm_load")
+
+
+def shape_of(phi: np.ndarray) -> Dict[str, float]:
+    """Height, base radius and tip angle of the phi = 1/2 contour of a
+    (ny, nx) field, measured by the library's device kernel."""
+    L = load_library()
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    ny, nx = phi.shape
+    out = np.empty(4, dtype=np.float64)
+    rc = L.lbm_shape_of(_dptr(phi), nx, ny, _dptr(out))
+    if rc != LBM_OK:
+        raise LbmError(rc, "lbm_shape_of", L.lbm_batch_last_error().decode())
+    return dict(height=out[0], base_radius=out[1], tip_angle_deg=out[2], npts=int(out[3]))
+
+
+def batch_workspace_bytes(params_list, slots: int) -> int:
+    L = load_library()
+    arr = (Params * len(params_list))(*[make_params(p) for p in params_list])
+    n = C.c_size_t()
+    rc = L.lbm_batch_workspace_bytes(arr, len(params_list), int(slots), C.byref(n))
+    if rc != LBM_OK:
+        raise LbmError(rc, "lbm_batch_workspace_bytes", L.lbm_strerror(rc).decode())
+    return int(n.value)
+
+
+class Batch:
+    """A queue of droplets run together on one GPU (the batched sweep).
+
+    ``params_list[i]``, ``phi0_list[i]``, ``T0_list[i]`` describe droplet i
+    (its own grid); ``radii`` gives R for the Fourier number of t_freeze.
+    Up to ``slots`` droplets are resident at a time."""
+
+    def __init__(self, params_list, phi0_list, T0_list, radii=None, slots: Optional[int] = None, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the batch needs a ROCm GPU (no CPU fallback)")
+        self.L = load_library()
+        self.torch = torch
+        n = len(params_list)
+        if not (len(phi0_list) == len(T0_list) == n) or n < 1:
+            raise ValueError("one phi0 and one T0 per parameter set")
+        self.n = n
+        self.slots = int(slots or n)
+        self.shapes = [(int(p["ny"]), int(p["nx"])) for p in params_list]
+        # the library reads droplet i's arrays when it enters a slot: keep them alive
+        self._phi0 = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in phi0_list]
+        self._T0 = [np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in T0_list]
+        for i, (ny, nx) in enumerate(self.shapes):
+            if self._phi0[i].size != nx * ny or self._T0[i].size != nx * ny:
+                raise ValueError(f"droplet {i}: phi0/T0 must have nx*ny entries")
+        self._params = (Params * n)(*[make_params(p) for p in params_list])
+        self._radii = None if radii is None else np.ascontiguousarray(radii, dtype=np.float64)
+        nbytes = batch_workspace_bytes(params_list, self.slots)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        pa = (C.POINTER(C.c_double) * n)(*[_dptr(a) for a in self._phi0])
+        ta = (C.POINTER(C.c_double) * n)(*[_dptr(a) for a in self._T0])
+        h = C.c_void_p()
+        rc = self.L.lbm_batch_init(self._params, n, pa, ta, None if self._radii is None else _dptr(self._radii),
+                                   self.slots, C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self._check(rc, "lbm_batch_init")
+        self._h = h
+
+    def _check(self, rc: int, what: str):
+        if rc != LBM_OK:
+            raise LbmError(rc, what, self.L.lbm_batch_last_error().decode())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.L.lbm_batch_destroy(h)
+            self._h = None
+
+    def configure(self, sample_every: int = 100, max_steps: int = 0, freeze_frac: float = 0.01,
+                  use_graph: bool = True):
+        self._check(self.L.lbm_batch_configure(self._h, int(sample_every), int(max_steps), float(freeze_frac),
+                                               int(bool(use_graph))), "lbm_batch_configure")
+
+    def set_launch(self, tile: str = "64x4", xcd_group: int = 1):
+        self._check(self.L.lbm_batch_set_launch(self._h, TILE_VARIANTS[tile], int(xcd_group)), "lbm_batch_set_launch")
+
+    def autotune(self, reps: int = 10):
+        v, x = C.c_int32(), C.c_int32()
+        self._check(self.L.lbm_batch_autotune(self._h, int(reps), C.byref(v), C.byref(x)), "lbm_batch_autotune")
+        return TILE_NAMES[v.value], int(x.value)
+
+    def step(self, nsteps: int, until_frozen: bool = False):
+        self._check(self.L.lbm_batch_step(self._h, int(nsteps), int(bool(until_frozen))), "lbm_batch_step")
+
+    def results(self):
+        out = (DropResult * self.n)()
+        self._check(self.L.lbm_batch_results(self._h, out), "lbm_batch_results")
+        res = []
+        for r in out:
+            d = {name: getattr(r, name) for name, _ in DropResult._fields_}
+            d["status"] = DROP_STATUS.get(d["status"], str(d["status"]))
+            res.append(d)
+        return res
+
+    def fields(self, drop: int, names: Iterable[str] = ("phi", "T", "ux", "uy", "p")) -> Dict[str, np.ndarray]:
+        names = list(names)
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELD_BITS[nm]
+        order = sorted(names, key=lambda nm: FIELD_BITS[nm])
+        ny, nx = self.shapes[drop]
+        outs = [np.empty(nx * ny, dtype=np.float64) for _ in order]
+        arr = (C.POINTER(C.c_double) * len(outs))(*[_dptr(o) for o in outs])
+        self._check(self.L.lbm_batch_fields(self._h, int(drop), mask, arr), "lbm_batch_fields")
+        return {nm: o.reshape(ny, nx) for nm, o in zip(order, outs)}

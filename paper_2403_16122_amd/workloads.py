@@ -234,3 +234,29 @@ def workload(name: str, seed: int = 0):
         T0 = temperature_noise(nx, ny, p["T_melt"], 1e-3, seed)
         return p, phi0, T0, dict(R=R, theta=th, bubbles=bubbles)
     raise KeyError(name)
+
+
+def sweep_droplets(n: int, seed: int = 0, R_range=(16.0, 64.0), theta_range=(60.0, 150.0),
+                   ste_range=(0.05, 0.3), gamma_range=(0.85, 1.1), max_bubbles: int = 8, storage: int = 0):
+    """Droplets of a parametric sweep (the study of Sec. 4.2.2 widened):
+    radius R, contact angle theta, Stefan number and density ratio
+    gamma = rho_s/rho_l drawn uniformly, 0..max_bubbles gas bubbles placed
+    inside, grid round(4R) x round(3R), liquid at T_m (+1e-3 noise) on a wall
+    at T = 0.  Returns a list of dicts with params, phi0, T0 and the draws."""
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng([seed, i])
+        R = float(rng.uniform(*R_range))
+        th = float(rng.uniform(*theta_range))
+        ste = float(rng.uniform(*ste_range))
+        gamma = float(rng.uniform(*gamma_range))
+        nb = int(rng.integers(0, max_bubbles + 1))
+        nx, ny = int(round(4 * R)), int(round(3 * R))
+        p = default_params(nx, ny, rho_s=gamma, latent=stefan_latent(ste), theta_bottom_deg=th, storage=storage)
+        Rc = cap_radius(R, th)
+        yc = -0.5 - Rc * math.cos(math.radians(th))
+        bubbles = place_bubbles(int(rng.integers(1 << 31)), nb, (nx / 2.0, yc), Rc, p["W"], max_tries=2000)
+        phi0 = droplet_with_bubbles(nx, ny, R, th, p["W"], bubbles)
+        T0 = temperature_noise(nx, ny, p["T_melt"], 1e-3, int(rng.integers(1 << 31)))
+        out.append(dict(params=p, phi0=phi0, T0=T0, R=R, theta=th, ste=ste, gamma=gamma, bubbles=bubbles))
+    return out

@@ -1,0 +1,161 @@
+"""Batched sweep on the GPU through the C ABI.
+
+* One launch over many grids computes exactly what the single-grid solver
+  computes for each (same tile shape and storage: bitwise equal fields),
+  whatever the tile layout, and the captured graph replays equal the same
+  steps launched one by one.
+* Run until frozen, the queue (more droplets than slots, so slots are
+  refilled) gives each droplet the freezing time, height, base radius and
+  tip angle that the FP64 oracle and the shape checker give for it.
+* The device shape measurement equals the checker on the same field.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import shape as SH
+from paper_2403_16122_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_16122_amd import lbm
+
+    return lbm
+
+
+def small_sweep(n, seed, storage=0, R_range=(7.0, 12.0), ste_range=(0.2, 0.3)):
+    return W.sweep_droplets(n, seed=seed, R_range=R_range, ste_range=ste_range, max_bubbles=1, storage=storage)
+
+
+def make_batch(lbm, drops, slots=None):
+    return lbm.Batch([d["params"] for d in drops], [d["phi0"] for d in drops], [d["T0"] for d in drops],
+                     radii=[d["R"] for d in drops], slots=slots)
+
+
+@pytest.mark.parametrize("storage,tile,xcd", [(0, "64x4", 1), (1, "64x8", 0), (2, "128x4", 1)])
+def test_batch_equals_single_solver_bitwise(storage, tile, xcd):
+    lbm = _lbm()
+    drops = small_sweep(5, seed=3, storage=storage)
+    print(f"batch of {len(drops)} storage={storage} tile={tile} xcd={xcd}", flush=True)
+    b = make_batch(lbm, drops)
+    b.configure(sample_every=50, use_graph=True)
+    b.set_launch(tile, xcd)
+    b.step(200)
+    names = ("phi", "T", "ux", "uy", "p", "fl")
+    for i, d in enumerate(drops):
+        s = lbm.Solver(d["params"], d["phi0"], d["T0"])
+        s.set_launch(tile, 1)
+        s.step(200)
+        fs, fb = s.fields(names), b.fields(i, names)
+        for k in names:
+            assert np.array_equal(fs[k], fb[k]), (i, k, np.abs(fs[k] - fb[k]).max())
+    assert all(r["steps"] == 200 for r in b.results())
+
+
+def test_graph_replays_equal_individual_launches():
+    lbm = _lbm()
+    drops = small_sweep(4, seed=5, storage=1)
+    g = make_batch(lbm, drops)
+    e = make_batch(lbm, drops)
+    g.configure(sample_every=40, use_graph=True)
+    e.configure(sample_every=40, use_graph=False)
+    for rep in range(4):  # every replay, with eager work and synchronisation in between
+        print(f"replay {rep}", flush=True)
+        g.step(40)
+        e.step(40)
+        for i in range(len(drops)):
+            a, c = g.fields(i, ("phi", "T", "ux")), e.fields(i, ("phi", "T", "ux"))
+            for k in a:
+                assert np.array_equal(a[k], c[k]), (rep, i, k)
+
+
+def test_autotune_does_not_advance_the_state():
+    lbm = _lbm()
+    drops = small_sweep(6, seed=7, storage=1)
+    a = make_batch(lbm, drops)
+    c = make_batch(lbm, drops)
+    a.step(100)
+    c.step(100)
+    tile, grp = a.autotune(reps=3)
+    print(f"autotune picked {tile} xcd_group={grp}", flush=True)
+    c.set_launch(tile, grp)
+    a.step(100)
+    c.step(100)
+    for i in range(len(drops)):
+        fa, fc = a.fields(i, ("phi", "T")), c.fields(i, ("phi", "T"))
+        assert np.array_equal(fa["phi"], fc["phi"]) and np.array_equal(fa["T"], fc["T"])
+
+
+def oracle_freeze(oracle_mod, d, every, max_steps):
+    o = oracle_mod.OracleSolver(d["params"], d["phi0"], d["T0"])
+    steps, liq = [0], [o.diag()["sum_liquid"]]
+    while steps[-1] < max_steps:
+        o.step(every)
+        steps.append(steps[-1] + every)
+        liq.append(o.diag()["sum_liquid"])
+        if liq[-1] <= 0.01 * liq[0]:
+            break
+    return SH.freeze_time(steps, liq), steps[-1], o
+
+
+def test_queue_until_frozen_against_oracle(oracle_mod):
+    lbm = _lbm()
+    drops = small_sweep(3, seed=11, R_range=(6.0, 8.0), ste_range=(0.25, 0.3))
+    every, limit = 20, 40000
+    b = make_batch(lbm, drops, slots=2)
+    b.configure(sample_every=every, max_steps=limit)
+    b.step(10 * limit, until_frozen=True)
+    res = b.results()
+    for i, (d, r) in enumerate(zip(drops, res)):
+        print(f"drop {i}: R={d['R']:.2f} theta={d['theta']:.1f} Ste={d['ste']:.3f} -> {r}", flush=True)
+        assert r["status"] == "frozen", r
+        tf, stop, o = oracle_freeze(oracle_mod, d, every, limit)
+        print(f"  oracle t_freeze {tf:.1f} (stopped at {stop})", flush=True)
+        assert r["t_freeze"] == pytest.approx(tf, rel=5e-3)
+        assert abs(r["steps"] - stop) <= every
+        p = d["params"]
+        assert r["t_star"] == pytest.approx(SH.fourier_number(r["t_freeze"], p["k_l"], p["rho_l"], p["cp_l"], d["R"]))
+        m = SH.shape_metrics(o.fields(("phi",))["phi"])
+        print(f"  oracle shape {m}", flush=True)
+        assert r["height"] == pytest.approx(m["height"], abs=0.05)
+        assert r["base_radius"] == pytest.approx(m["base_radius"], abs=0.1)
+        if m["npts"] >= 3:
+            assert r["tip_angle_deg"] == pytest.approx(m["tip_angle_deg"], abs=3.0)
+
+
+def test_step_limit_retires_unfrozen_droplets():
+    lbm = _lbm()
+    drops = small_sweep(3, seed=13)
+    b = make_batch(lbm, drops, slots=2)
+    b.configure(sample_every=20, max_steps=60)
+    b.step(1000, until_frozen=True)
+    for r in b.results():
+        assert r["status"] == "limit" and r["steps"] == 60 and math.isnan(r["t_freeze"])
+
+
+@pytest.mark.parametrize("kind", ["cap", "wedge", "sweep"])
+def test_device_shape_equals_checker(kind):
+    lbm = _lbm()
+    if kind == "cap":
+        y, x = np.mgrid[0:70, 0:100].astype(float)
+        phi = 0.5 * (1 + np.tanh(0.5 * (25.0 - np.hypot(x - 50.3, y + 8.0))))
+    elif kind == "wedge":
+        y, x = np.mgrid[0:90, 0:120].astype(float)
+        h = math.radians(40.0)
+        d = np.maximum((x - 60) * math.cos(h) + (y - 60) * math.sin(h), -(x - 60) * math.cos(h) + (y - 60) * math.sin(h))
+        phi = 0.5 * (1 + np.tanh(-0.5 * d))
+    else:
+        phi = small_sweep(1, seed=17, R_range=(20.0, 20.0), ste_range=(0.1, 0.1))[0]["phi0"].reshape(60, 80)
+    phi32 = phi.astype(np.float32).astype(np.float64)  # the device measures FP32 fields
+    g, c = lbm.shape_of(phi), SH.shape_metrics(phi32)
+    print(kind, g, c, flush=True)
+    for k in ("height", "base_radius", "tip_angle_deg"):
+        assert g[k] == pytest.approx(c[k], rel=1e-7, abs=1e-9)
+    assert g["npts"] == c["npts"]
