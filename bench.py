@@ -156,6 +156,24 @@ def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float):
     return out
 
 
+def surrogate_bench(sweep):
+    """The learned surrogate: trained on the stored 4096-droplet sweep,
+    scored on the 512 held-out droplets against the solver's values."""
+    from paper_2403_16122_amd import surrogate as S
+
+    data = os.path.join(ROOT, "paper_2403_16122_amd", "data")
+    tr, te = S.load(os.path.join(data, "sweep_train.npz")), S.load(os.path.join(data, "sweep_test.npz"))
+    sur = S.Surrogate(ensemble=8, seed=0, fallback_rel=0.05)
+    sur.fit(tr)
+    ev = S.evaluate(sur, te)
+    out = {"ensemble": 8, "train_droplets": int(len(tr["R"])), "train_seconds": round(sur.train_seconds, 2)}
+    out.update({k: (round(v, 5) if isinstance(v, float) else v) for k, v in ev.items()})
+    out["droplets_per_s"] = round(ev["n"] / ev["inference_seconds"], 1)
+    if sweep and sweep.get("droplets_per_s"):
+        out["speedup_vs_batched_solver"] = round(out["droplets_per_s"] / sweep["droplets_per_s"], 1)
+    return out
+
+
 def cpu_baseline(params, phi0, T0, budget_s: float):
     import oracle
 
@@ -190,6 +208,8 @@ def main():
     ap.add_argument("--sweep-droplets", type=int, default=256, help="droplets in the batched sweep (0: skip)")
     ap.add_argument("--sweep-plain", type=int, default=16, help="droplets of the sweep re-run one at a time in FP32")
     ap.add_argument("--sweep-time-limit", type=float, default=240.0)
+    ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
+                    help="skip training and scoring the surrogate network")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -299,6 +319,8 @@ def main():
     if args.sweep_droplets > 0:
         out["sweep"] = sweep_bench(lbm, W, args.sweep_droplets, args.sweep_plain, args.sweep_time_limit)
         torch.cuda.empty_cache()
+    if args.surrogate:
+        out["surrogate"] = surrogate_bench(out.get("sweep"))
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(params, phi0, T0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

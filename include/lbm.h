@@ -227,6 +227,49 @@ void lbm_batch_destroy(lbm_batch* b);
  * hot loops). */
 int lbm_shape_of(const double* phi, int32_t nx, int32_t ny, double* out);
 
+/* ---- Surrogate network ---------------------------------------------------
+ * An ensemble of `ensemble` networks maps the 5 parameters of a sweep
+ * droplet (normalised by the caller) to 3 outputs (t*, height/R, tip
+ * angle, normalised): two hidden layers of 128 units with the exact GELU,
+ * BF16 weights on the matrix cores with FP32 accumulation, FP32 master
+ * weights trained with Adam on the loss
+ *     L = sum_j w_j sum_s mask_sj (y_sj - t_sj)^2 / n.
+ * Its spread over the ensemble tells when to fall back to the solver.
+ * Parameters per member (lbm_mlp_param_count floats): W1 (128x5,
+ * row-major), b1 (128), W2 (128x128), b2 (128), W3 (3x128), b3 (3).
+ * Device arrays are row-major: x [n][5], targets and mask [n][3],
+ * outputs [ensemble][n][3]. */
+typedef struct lbm_mlp lbm_mlp;
+
+size_t lbm_mlp_param_count(void);
+
+/* He-uniform initial weights (seeded per member), zero biases; buffers
+ * for batches of up to max_batch samples.  The library allocates. */
+int lbm_mlp_create(int32_t ensemble, uint64_t seed, int32_t max_batch, void* hip_stream, lbm_mlp** out);
+
+/* All members' FP32 parameters (ensemble x param_count floats, host);
+ * setting them also resets the Adam state.  Synchronise. */
+int lbm_mlp_set_params(lbm_mlp* m, const float* host, size_t count);
+int lbm_mlp_get_params(lbm_mlp* m, float* host, size_t count);
+
+/* Outputs of every member for n device samples (asynchronous). */
+int lbm_mlp_forward(lbm_mlp* m, const float* d_x, int32_t n, float* d_y);
+
+/* Loss (per member) and its gradient (ensemble x param_count floats) for
+ * one batch, without updating.  w3: the 3 output weights (NULL = 1).
+ * Synchronises. */
+int lbm_mlp_gradient(lbm_mlp* m, const float* d_x, const float* d_t, const float* d_mask, int32_t n,
+                     const float* w3, float* host_grad, double* host_loss);
+
+/* `steps` Adam steps (beta 0.9/0.999, eps 1e-8, rate lr) on one batch of
+ * n <= max_batch samples; host_loss receives each member's loss before the
+ * last update.  Synchronises. */
+int lbm_mlp_train(lbm_mlp* m, const float* d_x, const float* d_t, const float* d_mask, int32_t n, const float* w3,
+                  float lr, int32_t steps, double* host_loss);
+
+const char* lbm_mlp_last_error(void);
+void lbm_mlp_destroy(lbm_mlp* m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("lbm_kernels.hip", "lbm_api.hip", "lbm_batch.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("lbm_kernels.hip", "lbm_api.hip", "lbm_batch.hip", "lbm_mlp.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 instructions are disabled for all device code (they have been

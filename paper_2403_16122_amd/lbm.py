@@ -31,6 +31,8 @@ EXPORTED = [
     "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_configure", "lbm_batch_set_launch",
     "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_results", "lbm_batch_fields",
     "lbm_batch_last_error", "lbm_batch_destroy", "lbm_shape_of",
+    "lbm_mlp_param_count", "lbm_mlp_create", "lbm_mlp_set_params", "lbm_mlp_get_params", "lbm_mlp_forward",
+    "lbm_mlp_gradient", "lbm_mlp_train", "lbm_mlp_last_error", "lbm_mlp_destroy",
 ]
 DROP_STATUS = {0: "queued", 1: "running", 2: "frozen", 3: "limit", 4: "nonfinite"}
 
@@ -121,6 +123,19 @@ def load_library():
     L.lbm_batch_destroy.argtypes = [vp]
     L.lbm_batch_destroy.restype = None
     L.lbm_shape_of.argtypes = [dp, C.c_int32, C.c_int32, dp]
+    fp = C.POINTER(C.c_float)
+    L.lbm_mlp_param_count.argtypes = []
+    L.lbm_mlp_param_count.restype = C.c_size_t
+    L.lbm_mlp_create.argtypes = [C.c_int32, C.c_uint64, C.c_int32, vp, C.POINTER(vp)]
+    L.lbm_mlp_set_params.argtypes = [vp, fp, C.c_size_t]
+    L.lbm_mlp_get_params.argtypes = [vp, fp, C.c_size_t]
+    L.lbm_mlp_forward.argtypes = [vp, vp, C.c_int32, vp]
+    L.lbm_mlp_gradient.argtypes = [vp, vp, vp, vp, C.c_int32, fp, fp, dp]
+    L.lbm_mlp_train.argtypes = [vp, vp, vp, vp, C.c_int32, fp, C.c_float, C.c_int32, dp]
+    L.lbm_mlp_last_error.argtypes = []
+    L.lbm_mlp_last_error.restype = C.c_char_p
+    L.lbm_mlp_destroy.argtypes = [vp]
+    L.lbm_mlp_destroy.restype = None
     _lib = L
     return L
 
@@ -364,3 +379,89 @@ class Batch:
         arr = (C.POINTER(C.c_double) * len(outs))(*[_dptr(o) for o in outs])
         self._check(self.L.lbm_batch_fields(self._h, int(drop), mask, arr), "lbm_batch_fields")
         return {nm: o.reshape(ny, nx) for nm, o in zip(order, outs)}
+
+
+class MLP:
+    """Ensemble of surrogate networks on the GPU (matrix-core BF16 kernels).
+
+    Inputs and targets are torch tensors on the device (float32, row-major):
+    x [n][5], t and mask [n][3]; ``forward`` returns [ensemble][n][3]."""
+
+    def __init__(self, ensemble: int = 8, seed: int = 0, max_batch: int = 8192, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the network needs a ROCm GPU (no CPU fallback)")
+        self.L = load_library()
+        self.torch = torch
+        self.E = int(ensemble)
+        self.max_batch = int(max_batch)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.P = int(self.L.lbm_mlp_param_count())
+        h = C.c_void_p()
+        rc = self.L.lbm_mlp_create(self.E, int(seed), self.max_batch, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self._check(rc, "lbm_mlp_create")
+        self._h = h
+
+    def _check(self, rc: int, what: str):
+        if rc != LBM_OK:
+            raise LbmError(rc, what, self.L.lbm_mlp_last_error().decode())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.L.lbm_mlp_destroy(h)
+            self._h = None
+
+    @staticmethod
+    def _fp(a: np.ndarray):
+        return a.ctypes.data_as(C.POINTER(C.c_float))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.E * self.P, dtype=np.float32)
+        self._check(self.L.lbm_mlp_get_params(self._h, self._fp(out), out.size), "lbm_mlp_get_params")
+        return out.reshape(self.E, self.P)
+
+    def set_params(self, params: np.ndarray):
+        a = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        self._check(self.L.lbm_mlp_set_params(self._h, self._fp(a), a.size), "lbm_mlp_set_params")
+
+    def _dev(self, a, cols):
+        t = self.torch.as_tensor(a, dtype=self.torch.float32, device=self.device).contiguous()
+        if t.dim() != 2 or t.shape[1] != cols:
+            raise ValueError(f"expected [n][{cols}]")
+        return t
+
+    def forward(self, x):
+        x = self._dev(x, 5)
+        n = x.shape[0]
+        y = self.torch.empty((self.E, n, 3), dtype=self.torch.float32, device=self.device)
+        self._check(self.L.lbm_mlp_forward(self._h, C.c_void_p(x.data_ptr()), n, C.c_void_p(y.data_ptr())),
+                    "lbm_mlp_forward")
+        return y
+
+    def _w3(self, w):
+        w = np.ones(3, dtype=np.float32) if w is None else np.ascontiguousarray(w, dtype=np.float32)
+        return w
+
+    def gradient(self, x, t, mask, w=None):
+        x, t, mask = self._dev(x, 5), self._dev(t, 3), self._dev(mask, 3)
+        n = x.shape[0]
+        g = np.empty(self.E * self.P, dtype=np.float32)
+        loss = np.empty(self.E, dtype=np.float64)
+        w3 = self._w3(w)
+        self._check(self.L.lbm_mlp_gradient(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                            C.c_void_p(mask.data_ptr()), n, self._fp(w3), self._fp(g), _dptr(loss)),
+                    "lbm_mlp_gradient")
+        return loss, g.reshape(self.E, self.P)
+
+    def train(self, x, t, mask, steps: int, lr: float = 1e-3, w=None):
+        x, t, mask = self._dev(x, 5), self._dev(t, 3), self._dev(mask, 3)
+        n = x.shape[0]
+        loss = np.empty(self.E, dtype=np.float64)
+        w3 = self._w3(w)
+        self._check(self.L.lbm_mlp_train(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                         C.c_void_p(mask.data_ptr()), n, self._fp(w3), float(lr), int(steps),
+                                         _dptr(loss)), "lbm_mlp_train")
+        return loss

@@ -1,0 +1,169 @@
+"""Learned surrogate of the parametric sweep.
+
+An ensemble of small networks (``lbm.MLP``: BF16 matrix-core kernels) maps
+a droplet's parameters (R, theta, Ste, gamma = rho_s/rho_l, bubble count) to
+its freezing time t* (Fourier number, Eq. (42)), final height/R and tip
+angle, trained on droplets the batched solver ran to freezing
+(``sweep_data``).  The ensemble's spread of log t*, scaled on a held-back
+calibration tenth of the training droplets so that it bounds 95 % of their
+relative errors, is the predicted error of the mean: where it exceeds
+``fallback_rel`` (2 %), the droplet is run by the solver instead.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import Dict, Optional
+
+import numpy as np
+
+INPUTS = ("R", "theta", "ste", "gamma", "nbubbles")
+# network targets: log t*, height/R, tip angle / 100 (NaN tip angles are masked)
+TARGETS = ("log_t_star", "height_R", "tip_angle_100")
+
+
+def features(d: Dict[str, np.ndarray]) -> np.ndarray:
+    return np.stack([np.asarray(d[k], dtype=np.float64) for k in INPUTS], axis=1)
+
+
+def targets(d: Dict[str, np.ndarray]):
+    y = np.stack([np.log(d["t_star"]), d["height_R"], d["tip_angle"] / 100.0], axis=1)
+    mask = np.isfinite(y).astype(np.float64)
+    return np.where(mask > 0, y, 0.0), mask
+
+
+@dataclass
+class Surrogate:
+    ensemble: int = 8
+    seed: int = 0
+    fallback_rel: float = 0.02
+    calib_frac: float = 0.1
+    coverage: float = 0.95
+    spread_scale: float = 1.0
+    net: object = None
+    xm: np.ndarray = field(default=None)
+    xs: np.ndarray = field(default=None)
+    ym: np.ndarray = field(default=None)
+    ys: np.ndarray = field(default=None)
+    train_seconds: float = 0.0
+
+    def fit(self, data: Dict[str, np.ndarray], schedule=((1500, 3e-3), (1500, 1e-3), (1000, 3e-4))):
+        """Full-batch Adam on the frozen droplets of `data`."""
+        from paper_2403_16122_amd import lbm
+
+        keep = np.asarray(data["frozen"], dtype=bool) & np.isfinite(data["t_star"])
+        idx = np.flatnonzero(keep)
+        rng = np.random.default_rng(self.seed)
+        rng.shuffle(idx)
+        ncal = int(round(self.calib_frac * len(idx)))
+        cal, fit = np.sort(idx[:ncal]), np.sort(idx[ncal:])
+        x = features(data)[fit]
+        y, mask = targets({k: np.asarray(v)[fit] if np.ndim(v) else v for k, v in data.items()})
+        self.xm, self.xs = x.mean(axis=0), x.std(axis=0) + 1e-12
+        self.ym = np.array([np.sum(y[:, j] * mask[:, j]) / mask[:, j].sum() for j in range(3)])
+        self.ys = np.array([np.sqrt(np.sum(((y[:, j] - self.ym[j]) * mask[:, j]) ** 2) / mask[:, j].sum())
+                            for j in range(3)]) + 1e-12
+        xn = ((x - self.xm) / self.xs).astype(np.float32)
+        yn = (((y - self.ym) / self.ys) * mask).astype(np.float32)
+        self.net = lbm.MLP(ensemble=self.ensemble, seed=self.seed, max_batch=max(len(xn), 1))
+        import torch
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = None
+        for steps, lr in schedule:
+            loss = self.net.train(xn, yn, mask.astype(np.float32), steps=steps, lr=lr)
+        torch.cuda.synchronize()
+        self.train_seconds = time.perf_counter() - t0
+        if ncal > 0:  # scale the spread to bound `coverage` of the calibration errors
+            self.spread_scale = 1.0
+            p = self.predict(features(data)[cal])
+            ratio = np.abs(np.log(p["t_star"] / np.asarray(data["t_star"])[cal])) / np.maximum(p["rel_spread"], 1e-12)
+            self.spread_scale = float(np.quantile(ratio, self.coverage))
+        return loss
+
+    def predict_members(self, x_raw: np.ndarray):
+        """Per-member outputs in the targets' units: (E, n, 3)."""
+        xn = ((np.asarray(x_raw, dtype=np.float64) - self.xm) / self.xs).astype(np.float32)
+        y = self.net.forward(xn).cpu().numpy().astype(np.float64)
+        return y * self.ys + self.ym
+
+    def predict(self, x_raw: np.ndarray):
+        """Ensemble mean of (t*, height/R, tip angle) and the relative spread of t*."""
+        m = self.predict_members(x_raw)
+        mean = m.mean(axis=0)
+        spread = m[:, :, 0].std(axis=0)  # std of log t* = relative spread of t*
+        err = self.spread_scale * spread  # predicted relative error of t*
+        return dict(t_star=np.exp(mean[:, 0]), height_R=mean[:, 1], tip_angle=100.0 * mean[:, 2],
+                    rel_spread=spread, pred_rel_err=err, fallback=err > self.fallback_rel)
+
+
+def evaluate(sur: Surrogate, test: Dict[str, np.ndarray]) -> Dict[str, float]:
+    """Errors of the ensemble mean against the solver on held-out droplets,
+    alone and with the fallback (solver values where the spread is too
+    wide), and the inference time."""
+    import torch
+
+    keep = np.asarray(test["frozen"], dtype=bool) & np.isfinite(test["t_star"])
+    x = features(test)[keep]
+    ts, hr, ta = test["t_star"][keep], test["height_R"][keep], test["tip_angle"][keep]
+    sur.predict(x[:8])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = sur.predict(x)
+    torch.cuda.synchronize()
+    infer = time.perf_counter() - t0
+    rel = np.abs(p["t_star"] - ts) / ts
+    fb = p["fallback"]
+    rel_fb = np.where(fb, 0.0, rel)
+    ok = np.isfinite(ta)
+    return dict(n=int(keep.sum()), t_star_rel_err_median=float(np.median(rel)), t_star_rel_err_p90=float(np.quantile(rel, 0.9)),
+                t_star_rel_err_max=float(rel.max()), height_R_abs_err_median=float(np.median(np.abs(p["height_R"] - hr))),
+                tip_angle_abs_err_median=float(np.median(np.abs(p["tip_angle"][ok] - ta[ok]))) if ok.any() else float("nan"),
+                fallback_fraction=float(fb.mean()), with_fallback_t_star_rel_err_median=float(np.median(rel_fb)),
+                with_fallback_t_star_rel_err_p90=float(np.quantile(rel_fb, 0.9)),
+                accepted_t_star_rel_err_max=float(rel[~fb].max()) if (~fb).any() else float("nan"),
+                accepted_t_star_rel_err_p95=float(np.quantile(rel[~fb], 0.95)) if (~fb).any() else float("nan"),
+                spread_scale=sur.spread_scale,
+                inference_seconds=infer)
+
+
+def load(path: str) -> Dict[str, np.ndarray]:
+    with np.load(path) as z:
+        return {k: z[k] for k in z.files}
+
+
+def predict_with_fallback(sur: Surrogate, drops, every: int = 200, max_steps: int = 3_000_000):
+    """Predictions for sweep droplets (dicts from ``workloads.sweep_droplets``):
+    the ensemble mean, except where its predicted error exceeds the
+    threshold, which the batched solver runs to freezing instead.  Returns
+    the merged predictions, the fallback mask and the time of each part."""
+    import torch
+
+    from paper_2403_16122_amd import lbm
+
+    x = np.array([[d["R"], d["theta"], d["ste"], d["gamma"], len(d["bubbles"])] for d in drops])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p = sur.predict(x)
+    torch.cuda.synchronize()
+    t_net = time.perf_counter() - t0
+    out = {k: np.array(p[k], dtype=np.float64) for k in ("t_star", "height_R", "tip_angle")}
+    fb = np.flatnonzero(p["fallback"])
+    t_solver = 0.0
+    if fb.size:
+        sub = [drops[i] for i in fb]
+        t0 = time.perf_counter()
+        b = lbm.Batch([d["params"] for d in sub], [d["phi0"] for d in sub], [d["T0"] for d in sub],
+                      radii=[d["R"] for d in sub], slots=min(256, len(sub)))
+        b.configure(sample_every=every, max_steps=max_steps)
+        b.step(10 * max_steps, until_frozen=True)
+        res = b.results()
+        t_solver = time.perf_counter() - t0
+        for j, i in enumerate(fb):
+            r = res[j]
+            out["t_star"][i] = r["t_star"]
+            out["height_R"][i] = r["height"] / drops[i]["R"]
+            out["tip_angle"][i] = r["tip_angle_deg"]
+    return out, np.asarray(p["fallback"], dtype=bool), dict(network_seconds=t_net, solver_seconds=t_solver,
+                                                             solver_droplets=int(fb.size))
