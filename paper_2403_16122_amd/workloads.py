@@ -200,6 +200,7 @@ def workload(name: str, seed: int = 0):
     sessile512  : 512x256, R=80, theta 90, gamma 0.9, Ste 0.1, Bond 0.1 (planar)
     bubbles1024 : 1024x512, R=160, 1-8 bubbles r~U(3,10), theta~U(60,120)
     probe4096   : 4096x2048, the 512x256 physics scaled to R=640 (out-of-cache size)
+    hou400      : 400x200 droplet with C_p,s/C_p,l = 0.5, k_s/k_l = 3.8, Pr 7.25, Ste 0.02
     """
     if name == "sessile128":
         nx, ny, R, th = 128, 64, 20.0, 90.0
@@ -233,6 +234,19 @@ def workload(name: str, seed: int = 0):
         phi0 = droplet_with_bubbles(nx, ny, R, th, p["W"], bubbles)
         T0 = temperature_noise(nx, ny, p["T_melt"], 1e-3, seed)
         return p, phi0, T0, dict(R=R, theta=th, bubbles=bubbles)
+    if name == "hou400":
+        # the sessile-droplet setup of Sec. 4.2.1 (Hou et al.'s water droplet):
+        # 400x200, R = 40, W = 5, Pr = 7.25, Ste = 0.02, k_s/k_l = 3.8,
+        # C_p,s/C_p,l = 0.5, gamma = 0.9, theta = 86.4 deg (synthetic: no images)
+        nx, ny, R, th = 400, 200, 40.0, 86.4
+        mu_l, cp_l = 0.1, 1.0
+        k_l = mu_l * cp_l / 7.25
+        p = default_params(nx, ny, W=5.0, rho_s=0.9, mu_l=mu_l, cp_l=cp_l, cp_g=cp_l, cp_s=0.5 * cp_l,
+                           cp_ref=cp_l, k_l=k_l, k_g=k_l, k_s=3.8 * k_l, latent=stefan_latent(0.02),
+                           theta_bottom_deg=th)
+        phi0 = sessile_droplet(nx, ny, R, th, p["W"])
+        T0 = temperature_noise(nx, ny, p["T_melt"], 1e-3, seed)
+        return p, phi0, T0, dict(R=R, theta=th)
     raise KeyError(name)
 
 

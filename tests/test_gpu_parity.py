@@ -262,7 +262,7 @@ def gpu_state_as_oracle_checkpoint(blob, p):
     return np.array([ORACLE_MAGIC, p["nx"], p["ny"], step], dtype=np.int64).tobytes() + a[:32].tobytes()
 
 
-@pytest.mark.parametrize("name,steps", [("sessile128", 0), ("sessile128", 700), ("sessile512", 40)])
+@pytest.mark.parametrize("name,steps", [("sessile128", 0), ("sessile128", 700), ("sessile512", 40), ("hou400", 200)])
 def test_one_step_from_identical_state(oracle_mod, name, steps):
     """From the very same state (the GPU's, loaded into the oracle) one step
     of each must agree to FP32 rounding of O(1) populations, everywhere."""

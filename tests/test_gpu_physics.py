@@ -1,0 +1,110 @@
+"""Physics of the paper's variant setups on the GPU.
+
+- Two-phase Stefan problem (Sec. 4.1's setting with the liquid above T_m):
+  the front follows s = 2 lambda sqrt(alpha t), lambda from the two-phase
+  Neumann condition St_s / (e^l^2 erf l) - St_l / (e^l^2 erfc l) = l sqrt(pi)
+  (equal properties in both phases), in FP32 and FP16 storage.
+- Final frozen height of a layer under gas, H_f / H_0 = rho_l / rho_s
+  (Eq. (44)), with expansion and shrinkage.
+- The droplet setup of Sec. 4.2.1 (C_p,s/C_p,l = 0.5, k_s/k_l = 3.8,
+  Pr = 7.25, Ste = 0.02, theta = 86.4 deg) against the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+from paper_2403_16122_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_16122_amd import lbm
+
+    return lbm
+
+
+def two_phase_lambda(st_s, st_l):
+    f = lambda l: st_s / (math.exp(l * l) * math.erf(l)) - st_l / (math.exp(l * l) * math.erfc(l)) - l * math.sqrt(math.pi)
+    return brentq(f, 1e-6, 3.0)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_two_phase_stefan_front(oracle_mod, storage):
+    lbm = _lbm()
+    nx, ny, k, ste, sup = 4, 80, 0.1, 0.1, 1.0  # liquid 1.0 above T_m: lambda 14 % below one-phase
+    p = W.default_params(nx, ny, rho_s=1.0, latent=1.0 / ste, k_l=k, k_g=k, k_s=k, storage=lbm.STORAGE[storage])
+    T0 = np.full(nx * ny, p["T_melt"] + sup)
+    g = lbm.Solver(p, np.ones(nx * ny), T0)
+    o = oracle_mod.OracleSolver(dict(p, storage=0), np.ones(nx * ny), T0, threads=1)
+    lam = two_phase_lambda(ste, sup * p["cp_l"] / p["latent"])
+    errs = []
+    for t in (3000, 8000, 15000):
+        g.step(t - g.step_count)
+        o.step(t - o.step_count)
+        fg = g.fields(["fs"])["fs"][:, 1].sum()
+        fo = o.fields(["fs"])["fs"][:, 1].sum()
+        exact = 2.0 * lam * math.sqrt(k * t)
+        errs.append((fg - exact) / exact)
+        print(f"{storage} t={t}: front gpu {fg:.4f} oracle {fo:.4f} closed form {exact:.4f}", flush=True)
+        assert abs(fg - fo) <= 1e-3 * exact if storage == "fp32" else abs(fg - fo) <= 1e-2 * exact
+    # the half-spacing wall and the one-cell mushy zone: below 3 % and shrinking
+    assert all(abs(e) < 0.03 for e in errs), errs
+    assert abs(errs[-1]) < abs(errs[0])
+
+
+@pytest.mark.parametrize("gamma", [0.8, 1.2])
+def test_layer_final_height(gamma):
+    lbm = _lbm()
+    nx, ny, H0, k = 4, 40, 12.0, 0.3
+    p = W.default_params(nx, ny, rho_s=gamma, k_l=k, k_g=k, k_s=k, latent=10.0)
+    phi0 = W.flat_layer(nx, ny, H0, p["W"])
+    s = lbm.Solver(p, phi0, np.full(nx * ny, p["T_melt"]))
+    h0 = np.clip(phi0.reshape(ny, nx)[:, 0], 0, 1).sum()
+    while s.step_count < 40000:
+        s.step(500)
+        d = s.diag()
+        if d["sum_liquid"] < 1e-3 * H0 * nx and d["sum_solid"] > 0.5 * H0 * nx:
+            break
+    height = d["sum_phic"] / nx
+    print(f"gamma {gamma}: H_f/H_0 {height / h0:.4f} (rho_l/rho_s {1 / gamma:.4f}) after {s.step_count} steps", flush=True)
+    assert d["sum_liquid"] < 1e-3 * H0 * nx
+    assert abs(height / h0 - 1.0 / gamma) < 0.02 / gamma  # Eq. (44), interface-width effects
+
+
+def test_hou_setup_against_oracle(oracle_mod):
+    """At Ste = 0.02 and tau_h = 0.54 this case is sensitive: the oracle
+    against itself with phi0 perturbed by 1e-7 differs by ~1-2e-4 in phi
+    after 300 steps.  The GPU, which rounds every step rather than once,
+    stays within twice the larger of two such draws (measured here); the
+    exact check of this setup's arithmetic is the one-step comparison from
+    an identical state in the parity tests."""
+    lbm = _lbm()
+    p, phi0, T0, _ = W.workload("hou400", seed=0)
+    g = lbm.Solver(p, phi0, T0)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    g.step(300)
+    o.step(300)
+    names = ("phi", "T", "ux", "uy")
+    fg, fo = g.fields(names), o.fields(names)
+
+    def errs(a, b):
+        u = np.stack([a["ux"], a["uy"]]) - np.stack([b["ux"], b["uy"]])
+        return (np.abs(a["phi"] - b["phi"]).max(), np.abs(a["T"] - b["T"]).max(),
+                np.linalg.norm(u) / np.linalg.norm(np.stack([b["ux"], b["uy"]])))
+
+    env = np.zeros(3)
+    for draw in range(2):
+        z = np.random.default_rng(40 + draw).standard_normal(phi0.shape)
+        o2 = oracle_mod.OracleSolver(p, phi0 + 1e-7 * z, T0)
+        o2.step(300)
+        env = np.maximum(env, errs(o2.fields(names), fo))
+    e = errs(fg, fo)
+    print(f"hou400/300: gpu {e}, envelope {env}", flush=True)
+    assert np.all(np.asarray(e) <= 2.0 * np.maximum(env, [1e-5, 1e-5, 1e-4]))
