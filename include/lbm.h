@@ -132,9 +132,10 @@ const char* lbm_last_error(void);
 
 /* Launch shape of the fused step.  tile_variant 0..4: 2-D tiles of 64x4
  * (default), 32x8, 64x8, 64x16, 128x4 nodes per workgroup, halo macros
- * recomputed per tile; 5..7: column strips 60 nodes wide and 32, 64, 128
- * rows high, walked row by row (halo only at the strip sides; FP32 storage
- * only, LBM_EINVAL otherwise).
+ * recomputed per tile; 5..8: rolling tile columns (a workgroup walks a
+ * column segment upward, keeping the row below each block in LDS) of
+ * 64 columns x 8 rows per block over 128- and 256-row segments, 128 x 4
+ * over 128 rows, and 64 x 12 over 192 rows.
  * xcd_remap: 0 keeps the hardware's round-robin of workgroups over the 8
  * XCDs; 1 gives each XCD one contiguous band of tiles (its L2 then serves
  * the halo re-reads).  Results are bitwise identical for every choice. */

@@ -192,7 +192,6 @@ size_t ws_size(const lbm_params* p) {
   return lbmk::state_bytes(lbmk::plane_floats((long long)p->nx * p->ny), p->storage) + part_bytes();
 }
 
-bool is_strip(int tile_variant) { return tile_variant >= 5; }
 
 void carve(lbm_ctx* c) {
   const long long pl = c->K.plane;
@@ -464,10 +463,6 @@ int lbm_sync(lbm_ctx* c) {
 int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap) {
   if (!c || tile_variant < 0 || tile_variant >= lbmk::NTILE_VARIANTS || xcd_remap < 0 || xcd_remap > 1)
     return LBM_EINVAL;
-  if (is_strip(tile_variant) && c->P.storage != LBM_STORE_FP32) {
-    g_last_error = "column strips support FP32 population storage only";
-    return LBM_EINVAL;
-  }
   c->tile_variant = tile_variant;
   c->xcd = xcd_remap;
   return LBM_OK;
@@ -490,7 +485,6 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_r
   float best = 1e30f;
   int bv = c->tile_variant, bx = c->xcd;
   for (int v = 0; v < lbmk::NTILE_VARIANTS; ++v) {
-    if (is_strip(v) && c->P.storage != LBM_STORE_FP32) continue;
     for (int x = 0; x <= 1; ++x) {
       if (lbmk::launch_step(c->K, c->S, c->cur, false, v, x, c->stream))  // warm-up
         return dev_error(hipGetLastError(), "autotune launch");

@@ -79,7 +79,7 @@ struct StepOff {
 };
 
 enum { NFIELD = 10 };
-enum { NTILE_VARIANTS = 8 };  // tiles 64x4, 32x8, 64x8, 64x16, 128x4; strips 60x32, 60x64, 60x128
+enum { NTILE_VARIANTS = 9 };  // tiles 64x4, 32x8, 64x8, 64x16, 128x4; rolling columns 64x8/128, 64x8/256, 128x4/128, 64x12/192
 enum { RED_NVAL = 8 };
 constexpr int RED_BLOCKS = 512;
 

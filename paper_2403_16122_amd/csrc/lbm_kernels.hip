@@ -689,215 +689,162 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
   step_tile<TX, TY, FIELDS, PT>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
 }
 
-// Sliding-window variant for large grids.  A workgroup is one wavefront
-// whose 64 lanes own 64 consecutive columns: 60 that it updates and two
-// halo columns on each side whose macroscopic quantities it only rebuilds.
-// It walks a strip of up to SY rows upwards.  Each iteration rebuilds the
-// row above the one it updates into 4-slot LDS rings (phi - 1, rho, f_s^H;
-// lagged p and S; phi_ref), then updates its row.  Loads run one row ahead
-// (software pipelining), every population is fetched once as the window
-// passes, and a lane holds only raw inputs across iterations: the node
-// macros of the row being updated are recomputed from them.  Arithmetic is
-// shared with k_step, so both give bit-identical results.
-constexpr int CW = 64;        // lanes per strip
-constexpr int CI = CW - 4;    // columns updated per strip
+// Rolling tile-column variant.  A workgroup of TX x (RY+1) lanes owns TX
+// columns over a segment of `seg` rows and walks it upward in blocks of RY
+// rows.  Per block, lanes of rows 0..RY-1 rebuild the node macros of their
+// nodes and then update them; the last row of lanes rebuilds the row above
+// the block and, 4 (RY+1) of them, the two halo columns on either side.  The
+// row below the block was rebuilt by the previous block and stays in LDS,
+// so rows are neither fetched again nor rebuilt again for the halo (the
+// tile kernel rebuilds a ring around every tile).  A segment that does not
+// start at the wall first runs one block that only rebuilds the row below
+// it.  All arithmetic is the tile kernel's, so results are bitwise equal.
+template <int TX, int RY, bool FIELDS, class PT>
+__global__ __launch_bounds__(TX*(RY + 1)) __attribute__((amdgpu_waves_per_eu(6))) void k_roll(
+    KParams P, StepIO io, int ncol, int nblocks_total, int seg, int tiles_per_xcd, int mode) {
+  constexpr int LX = TX + 4, LY = RY + 2;  // LDS column c <-> x0 + c - 2, row r <-> Y + r - 1
+  constexpr int RX = LX + 2, RR = LY + 2;  // reference tile: row q <-> Y + q - 2
+  constexpr int NT = TX * (RY + 1);
+  static_assert(4 * (RY + 1) <= TX, "one side-halo cell per lane of the top row");
+  __shared__ float s_phi[LY][LX];
+  __shared__ float s_rho[LY][LX];
+  __shared__ float s_fsH[LY][LX];
+  __shared__ float s_p[LY][LX];
+  __shared__ float s_S[LY][LX];
+  __shared__ float s_ref[RR][RX];
+  constexpr bool NR = PopIO<PT>::kNodeRef;
+  __shared__ float s_th[NR ? RR : 1][NR ? RX : 1];
 
-struct RawNode {
-  float g[9], h[9], fprev;
-};
-
-template <int SY, bool FIELDS, class PT>
-__global__ __launch_bounds__(CW, 3) void k_column(KParams P, StepIO io, int nsx, int nstrips,
-                                                  int tiles_per_xcd, int mode) {
-  static_assert(!PopIO<PT>::kNodeRef, "column strips implement the FP32 storage shifts only");
-  constexpr int LR = CW + 2;  // phi_ref: columns x0-3 .. x0+CW-2
-  constexpr int LP = CW - 2;  // p/S:     columns x0-1 .. x0+CW-4
-  __shared__ float s_phi[4][CW];  // lane t <-> column x0 - 2 + t
-  __shared__ float s_rho[4][CW];
-  __shared__ float s_fsH[4][CW];
-  __shared__ float s_p[4][LP];
-  __shared__ float s_S[4][LP];
-  __shared__ float s_ref[4][LR];
-
+  const int b = map_tile(blockIdx.x, mode, tiles_per_xcd);
+  if (b >= nblocks_total) return;  // whole workgroup leaves before any barrier
   const void* __restrict__ A = io.A;
-  const int strip = map_tile(blockIdx.x, mode, tiles_per_xcd);
-  if (strip >= nstrips) return;
   const int nx = P.nx, ny = P.ny;
-  const int x0 = (strip % nsx) * CI, y0 = (strip / nsx) * SY;
-  const int yend = min(y0 + SY, ny);
-  const int t = threadIdx.x;
-  const int xg = x0 - 2 + t;              // this lane's column (unwrapped)
-  const int xw = wrapx(xg, nx);
-  const bool own = t >= 2 && t < CW - 2 && xg < nx;  // updated by this strip
-  const int xm = xw == 0 ? nx - 1 : xw - 1;
-  const int xp = xw == nx - 1 ? 0 : xw + 1;
-  // columns of the reference and p/S rows this lane loads (second entry for lanes 0, 1)
-  const int rj1 = t + CW;
-  const int rx0 = wrapx(x0 - 3 + t, nx), rx1 = wrapx(x0 - 3 + rj1, nx);
-  const int px0 = wrapx(x0 - 1 + t, nx);
-#define SLOT(gy) (((gy) + 4) & 3)
-#define CLAMPY(gy) min(max((gy), 0), ny - 1)
+  const int x0 = (b % ncol) * TX, y0 = (b / ncol) * seg;
+  const int y1 = min(y0 + seg, ny);
 
-  auto load_raw = [&](int gy, RawNode& w) {
-    pull9<0, PT>(A, P, xw, gy, xm, xp, w.g);
-    pull9<2, PT>(A, P, xw, gy, xm, xp, w.h);
-    w.fprev = io.fsH_in[gy * nx + xw];
-  };
-  auto rebase = [&](float q[9], int gy) -> float {
-#pragma clang fp contract(off)
-    const bool bot = (gy == 0), top = (gy == ny - 1);
-    const float rself = s_ref[SLOT(gy)][t + 1];
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      const int cy = cyv(i), cx = cxv(i);
-      const bool wall = (cy > 0 && bot) || (cy < 0 && top);
-      const float rs = wall ? rself : s_ref[SLOT(gy - cy)][t + 1 - cx];
-      q[i] += wt(i) * (rs - rself);
-    }
-    return rself;
-  };
-  // node macros of row gy from raw inputs (copied, so the raw set survives)
-  auto macro_of = [&](const RawNode& w, int gy, Macro& m) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      m.g[i] = w.g[i];
-      m.h[i] = w.h[i];
-    }
-    m.fprev = w.fprev;
-    const float rs = rebase(m.g, gy);
-    finish_macro<false>(P, rs, m);
-  };
-  auto to_rings = [&](const Macro& m, int gy) {
-    s_phi[SLOT(gy)][t] = (m.r - 1.0f) + m.dl;
-    s_rho[SLOT(gy)][t] = m.rho;
-    s_fsH[SLOT(gy)][t] = m.fsH;
-  };
-  auto ghost_row = [&](int gg, int ga, int gb, float tv) {
-    if (t >= 1 && t < CW - 1) {
-      const float pg = wetting_ghost(s_phi[SLOT(ga)][t - 1], s_phi[SLOT(ga)][t], s_phi[SLOT(ga)][t + 1],
-                                     s_phi[SLOT(gb)][t - 1], s_phi[SLOT(gb)][t + 1], tv);
-      const float pcg = clamp01(1.0f + pg);
-      s_phi[SLOT(gg)][t] = pg;
-      s_rho[SLOT(gg)][t] = mix3(pcg * s_fsH[SLOT(ga)][t], pcg, P.rho_s, P.rho_l, P.rho_g);
-    }
-  };
-
-  // ---- prologue ------------------------------------------------------------
-  for (int gy = y0 - 2; gy <= y0 + 1; ++gy) {
-    const int cy = CLAMPY(gy);
-    s_ref[SLOT(gy)][t] = ((const float*)io.ref_in)[cy * nx + rx0];
-    if (rj1 < LR) s_ref[SLOT(gy)][rj1] = ((const float*)io.ref_in)[cy * nx + rx1];
-  }
-  for (int gy = y0 - 1; gy <= y0; ++gy) {
-    if (t < LP) {
-      const int kk = CLAMPY(gy) * nx + px0;
-      s_p[SLOT(gy)][t] = io.p_in[kk];
-      s_S[SLOT(gy)][t] = io.S_in[kk];
-    }
-  }
-  RawNode rawC, rawL;  // rows y (being updated) and y+1 (lead)
-  if (y0 >= 1) load_raw(y0 - 1, rawL);
-  load_raw(y0, rawC);
-  __syncthreads();
-  {
-    Macro m;
-    if (y0 >= 1) {
-      macro_of(rawL, y0 - 1, m);
-      to_rings(m, y0 - 1);
-    }
-    macro_of(rawC, y0, m);
-    to_rings(m, y0);
-  }
-  // first prefetch: lead row y0+1, reference row y0+2, p/S row y0+1, f of row y0
-  if (y0 + 1 < ny) load_raw(y0 + 1, rawL);
-  float refV0, refV1 = 0.0f, pV = 0.0f, SV = 0.0f;
-  {
-    const int cy = CLAMPY(y0 + 2);
-    refV0 = ((const float*)io.ref_in)[cy * nx + rx0];
-    if (rj1 < LR) refV1 = ((const float*)io.ref_in)[cy * nx + rx1];
-    if (t < LP) {
-      const int kk = CLAMPY(y0 + 1) * nx + px0;
-      pV = io.p_in[kk];
-      SV = io.S_in[kk];
-    }
-  }
-  float fC[9], puxC = 0.0f, puyC = 0.0f;
-  if (own) {
-    pull9<1, PT>(A, P, xw, y0, xm, xp, fC);
-    puxC = io.phiu_in[y0 * nx + xw];
-    puyC = io.phiu_in[P.plane + y0 * nx + xw];
-  }
-  __syncthreads();
-
-  for (int y = y0; y < yend; ++y) {
-    const int yl = y + 1;
-    // (1) prefetched LDS rows
-    s_ref[SLOT(y + 2)][t] = refV0;
-    if (rj1 < LR) s_ref[SLOT(y + 2)][rj1] = refV1;
-    if (t < LP) {
-      s_p[SLOT(yl)][t] = pV;
-      s_S[SLOT(yl)][t] = SV;
-    }
-    __syncthreads();
-    // (2) lead row macros into the rings
-    if (yl < ny) {
-      Macro m;
-      macro_of(rawL, yl, m);
-      to_rings(m, yl);
-    }
-    __syncthreads();
-    const bool gtop = (yl == ny), gbot = (y == 0);
-    if (gtop) ghost_row(ny, ny - 1, ny - 2, P.tan_t);
-    if (gbot) ghost_row(-1, 0, 1, P.tan_b);
-    if (gtop || gbot) __syncthreads();
-    // (3) prefetch the next iteration's inputs
-    const bool more = yl < yend;
-    RawNode rawN;
-    if (more && y + 2 < ny) load_raw(y + 2, rawN);
-    if (more) {
-      const int cy = CLAMPY(y + 3);
-      refV0 = ((const float*)io.ref_in)[cy * nx + rx0];
-      if (rj1 < LR) refV1 = ((const float*)io.ref_in)[cy * nx + rx1];
-      if (t < LP) {
-        const int kk = CLAMPY(y + 2) * nx + px0;
-        pV = io.p_in[kk];
-        SV = io.S_in[kk];
-      }
-    }
-    float fN[9], puxN = 0.0f, puyN = 0.0f;
-    if (own && more) {
-      pull9<1, PT>(A, P, xw, yl, xm, xp, fN);
-      puxN = io.phiu_in[yl * nx + xw];
-      puyN = io.phiu_in[P.plane + yl * nx + xw];
-    }
-    // (4) update row y
+  for (int Y = (y0 > 0 ? y0 - RY : y0); Y < y1; Y += RY) {
+    // The lane's indices are rebuilt every block from an opaque copy of its
+    // id: hoisted out of the loop they would stay live across it and double
+    // the register count.
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int lx = t % TX, ly = t / TX;  // ly == RY: the top row of lanes
+    const int x = x0 + lx;
+    const int xw = wrapx(x, nx);
+    const bool top_lane = ly == RY;
+    // side-halo cell of a top-row lane: LDS row hr (1..RY+1), column hc
+    const bool side = top_lane && lx < 4 * (RY + 1);
+    const int hr = 1 + (lx >> 2), hs = lx & 3;
+    const int hc = hs < 2 ? hs : TX + hs;
+    const bool update = Y >= y0;  // false for the first block of an inner segment
+    // ---- loads: this lane's node (own row or the row above the block), its
+    // side-halo cell, f and (phi u) of own nodes, the reference and lagged tiles
+    Macro m, mh;
+    float f[9], phiux = 0.0f, phiuy = 0.0f;
+    const int y = Y + ly;  // own row (ly < RY) or the row above (ly == RY)
+    const bool row_ok = y >= 0 && y < ny;
+    if (row_ok) load_node<PT>(A, io.fsH_in, P, xw, y, m);
+    const bool own = !top_lane && update && y < y1 && x < nx;
     if (own) {
-      Macro mc;
-      macro_of(rawC, y, mc);
-      const int a = SLOT(y - 1), c0 = SLOT(y), u = SLOT(y + 1);
-      const int c = t, cp = t - 1;
-      Grads d;
-      stencil(s_phi[c0][c], s_phi[c0][c + 1], s_phi[c0][c - 1], s_phi[u][c], s_phi[a][c], s_phi[u][c + 1],
-              s_phi[u][c - 1], s_phi[a][c - 1], s_phi[a][c + 1], d.phx, d.phy, &d.lphi);
-      stencil(s_rho[c0][c], s_rho[c0][c + 1], s_rho[c0][c - 1], s_rho[u][c], s_rho[a][c], s_rho[u][c + 1],
-              s_rho[u][c - 1], s_rho[a][c - 1], s_rho[a][c + 1], d.rx, d.ry, nullptr);
-      stencil(s_p[c0][cp], s_p[c0][cp + 1], s_p[c0][cp - 1], s_p[u][cp], s_p[a][cp], s_p[u][cp + 1],
-              s_p[u][cp - 1], s_p[a][cp - 1], s_p[a][cp + 1], d.px, d.py, nullptr);
-      stencil(s_S[c0][cp], s_S[c0][cp + 1], s_S[c0][cp - 1], s_S[u][cp], s_S[a][cp], s_S[u][cp + 1],
-              s_S[u][cp - 1], s_S[a][cp - 1], s_S[a][cp + 1], d.Sx, d.Sy, nullptr);
-      update_node<FIELDS, PT>(P, io, mc, fC, puxC, puyC, d, y * nx + xw);
+      const int xm = x == 0 ? nx - 1 : x - 1;
+      const int xp = x == nx - 1 ? 0 : x + 1;
+      pull9<1, PT>(A, P, x, y, xm, xp, f);
+      phiux = ld(io.phiu_in, (unsigned)(y * nx + x));
+      phiuy = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
     }
-    __syncthreads();  // rings are overwritten from the next iteration on
-    // (5) rotate the pipeline
-    rawC = rawL;
-    rawL = rawN;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fC[i] = fN[i];
-    puxC = puxN;
-    puyC = puyN;
+    const int gyh = Y + hr - 1;
+    const bool halo = side && gyh >= 0 && gyh < ny;
+    if (halo) load_node<PT>(A, io.fsH_in, P, wrapx(x0 + hc - 2, nx), gyh, mh);
+    for (int j = t; j < (RR - 1) * RX; j += NT) {  // reference rows 1..RR-1 (Y-1 .. Y+RY+1)
+      const int q = 1 + j / RX, c = j - (j / RX) * RX;
+      const int gy = min(max(Y + q - 2, 0), ny - 1);
+      float rv, tv;
+      RefIO<NR>::load(io.ref_in, (unsigned)(gy * nx + wrapx(x0 + c - 3, nx)), rv, tv);
+      s_ref[q][c] = rv;
+      if constexpr (NR) s_th[q][c] = tv;
+    }
+    for (int j = t; j < LX * LY; j += NT) {
+      const int r = j / LX, c = j - (j / LX) * LX;
+      const int gy = min(max(Y + r - 1, 0), ny - 1);
+      const int kk = gy * nx + wrapx(x0 + c - 2, nx);
+      s_p[r][c] = ld(io.p_in, (unsigned)kk);
+      s_S[r][c] = ld(io.S_in, (unsigned)kk);
+    }
+    __syncthreads();
+
+    // ---- macros of rows Y .. Y+RY into LDS rows 1 .. RY+1 (row 0: carried)
+    if (row_ok) {
+      const float rs = rebase_g<RX>(m.g, s_ref, P, y, lx + 2, ly + 1);
+      if constexpr (NR) m.th = rebase_h<RX>(m.h, s_th, P, y, lx + 2, ly + 1);
+      finish_macro<NR>(P, rs, m);
+      s_phi[ly + 1][lx + 2] = (m.r - 1.0f) + m.dl;
+      s_rho[ly + 1][lx + 2] = m.rho;
+      s_fsH[ly + 1][lx + 2] = m.fsH;
+    }
+    if (halo) {
+      const float rs = rebase_g<RX>(mh.g, s_ref, P, gyh, hc, hr);
+      if constexpr (NR) mh.th = rebase_h<RX>(mh.h, s_th, P, gyh, hc, hr);
+      finish_macro<NR>(P, rs, mh);
+      s_phi[hr][hc] = (mh.r - 1.0f) + mh.dl;
+      s_rho[hr][hc] = mh.rho;
+      s_fsH[hr][hc] = mh.fsH;
+    }
+    __syncthreads();
+
+    // ---- wall ghost rows (Eq. (39)-(41))
+    const bool has_bot = (Y == 0), has_top = (ny <= Y + RY);
+    if (has_bot || has_top) {
+      for (int j = t; j < 2 * LX; j += NT) {
+        const bool isb = j < LX;
+        const int c = isb ? j : j - LX;
+        if (c < 1 || c > LX - 2) continue;
+        int r, r0, r1;
+        float tv;
+        if (isb) {
+          if (!has_bot) continue;
+          r = 0;
+          r0 = 1;
+          r1 = 2;
+          tv = P.tan_b;
+        } else {
+          if (!has_top) continue;
+          r = ny - Y + 1;
+          r0 = r - 1;
+          r1 = r - 2;
+          tv = P.tan_t;
+        }
+        const float pg = wetting_ghost(s_phi[r0][c - 1], s_phi[r0][c], s_phi[r0][c + 1], s_phi[r1][c - 1],
+                                       s_phi[r1][c + 1], tv);
+        const float pcg = clamp01(1.0f + pg);
+        s_phi[r][c] = pg;
+        s_rho[r][c] = mix3(pcg * s_fsH[r0][c], pcg, P.rho_s, P.rho_l, P.rho_g);
+      }
+      __syncthreads();
+    }
+
+    // ---- update own nodes of the block
+    if (own) {
+      const int r = ly + 1, c = lx + 2;
+      Grads d;
+#define LBM_ROLL_STENCIL(arr, ox, oy, lap)                                                          \
+  stencil(arr[r][c], arr[r][c + 1], arr[r][c - 1], arr[r + 1][c], arr[r - 1][c], arr[r + 1][c + 1], \
+          arr[r + 1][c - 1], arr[r - 1][c - 1], arr[r - 1][c + 1], ox, oy, lap)
+      LBM_ROLL_STENCIL(s_phi, d.phx, d.phy, &d.lphi);
+      LBM_ROLL_STENCIL(s_rho, d.rx, d.ry, nullptr);
+      LBM_ROLL_STENCIL(s_p, d.px, d.py, nullptr);
+      LBM_ROLL_STENCIL(s_S, d.Sx, d.Sy, nullptr);
+#undef LBM_ROLL_STENCIL
+      update_node<FIELDS, PT>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x));
+    }
+    __syncthreads();
+    // ---- carry row RY (y = Y + RY - 1) to row 0 for the next block
+    for (int j = t; j < LX; j += NT) {
+      s_phi[0][j] = s_phi[RY][j];
+      s_rho[0][j] = s_rho[RY][j];
+      s_fsH[0][j] = s_fsH[RY][j];
+    }
+    __syncthreads();
   }
-#undef SLOT
-#undef CLAMPY
 }
 
 // Initial state (no time-stepping yet): u = 0, p = 0, liquid fraction 1,
@@ -1149,20 +1096,22 @@ int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <int SY, class PT>
-int launch_column(const KParams& P, const State& S, int cur, bool fields_only, int xcd, hipStream_t st) {
-  const int nsx = (P.nx + CI - 1) / CI, nsy = (P.ny + SY - 1) / SY;
-  const int nstrips = nsx * nsy;
-  int tpx = 0, grid = nstrips;
+template <int TX, int RY, class PT>
+int launch_roll(const KParams& P, const State& S, int cur, bool fields_only, int seg, int xcd, hipStream_t st) {
+  const int ncol = (P.nx + TX - 1) / TX, nseg = (P.ny + seg - 1) / seg;
+  const int nb = ncol * nseg;
+  int tpx = 0, grid = nb;
   if (xcd == 1) {
-    tpx = (nstrips + 7) / 8;
+    tpx = (nb + 7) / 8;
     grid = 8 * tpx;
   }
   const StepIO io = make_io(S, cur);
   if (fields_only)
-    hipLaunchKernelGGL((k_column<SY, true, PT>), dim3(grid), dim3(CW), 0, st, P, io, nsx, nstrips, tpx, xcd);
+    hipLaunchKernelGGL((k_roll<TX, RY, true, PT>), dim3(grid), dim3(TX * (RY + 1)), 0, st, P, io, ncol, nb, seg, tpx,
+                       xcd);
   else
-    hipLaunchKernelGGL((k_column<SY, false, PT>), dim3(grid), dim3(CW), 0, st, P, io, nsx, nstrips, tpx, xcd);
+    hipLaunchKernelGGL((k_roll<TX, RY, false, PT>), dim3(grid), dim3(TX * (RY + 1)), 0, st, P, io, ncol, nb, seg, tpx,
+                       xcd);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1183,15 +1132,13 @@ int launch_step_t(const KParams& P, const State& S, int cur, bool fields_only, i
     case 4:
       return launch_tile<128, 4, PT>(P, S, cur, fields_only, xcd_remap, st);
     case 5:
+      return launch_roll<64, 8, PT>(P, S, cur, fields_only, 128, xcd_remap, st);
     case 6:
+      return launch_roll<64, 8, PT>(P, S, cur, fields_only, 256, xcd_remap, st);
     case 7:
-      if constexpr (PopIO<PT>::kNodeRef) {
-        return -1;  // strips exist for FP32 storage only (rejected by the host first)
-      } else {
-        if (tile_variant == 5) return launch_column<32, PT>(P, S, cur, fields_only, xcd_remap, st);
-        if (tile_variant == 6) return launch_column<64, PT>(P, S, cur, fields_only, xcd_remap, st);
-        return launch_column<128, PT>(P, S, cur, fields_only, xcd_remap, st);
-      }
+      return launch_roll<128, 4, PT>(P, S, cur, fields_only, 128, xcd_remap, st);
+    case 8:
+      return launch_roll<64, 12, PT>(P, S, cur, fields_only, 192, xcd_remap, st);
     default:
       return launch_tile<64, 4, PT>(P, S, cur, fields_only, xcd_remap, st);
   }

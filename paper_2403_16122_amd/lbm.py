@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 FIELD_BITS = {"phi": 0, "T": 1, "ux": 2, "uy": 3, "p": 4, "fs": 5, "fl": 6, "rho": 7, "H": 8, "mdot": 9}
 TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4,
-                 "strip60x32": 5, "strip60x64": 6, "strip60x128": 7}
+                 "roll64x8s128": 5, "roll64x8s256": 6, "roll128x4s128": 7, "roll64x12s192": 8}
 TILE_NAMES = {v: k for k, v in TILE_VARIANTS.items()}
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}  # LBM_STORE_FP32 / _FP16_SHIFT / _BF16_SHIFT
 
