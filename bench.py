@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--workload", default="sessile512")
     ap.add_argument("--tile", default="auto", help="auto (library autotuner) or a name of lbm.TILE_VARIANTS")
     ap.add_argument("--no-xcd", action="store_true", help="round-robin workgroup dispatch (xcd mode 0)")
-    ap.add_argument("--xcd", type=int, default=None, help="workgroup-to-XCD mapping mode 0/1 (fixed tiles only)")
+    ap.add_argument("--xcd", type=int, default=None, help="workgroup-to-XCD mapping mode 0/1/2 (fixed tiles only)")
     ap.add_argument("--storage", default="fp32", choices=("fp32", "fp16", "bf16"),
                     help="population storage format (compute is FP32 in every case)")
     ap.add_argument("--no-storage-variants", dest="storage_variants", action="store_false",

@@ -132,13 +132,13 @@ const char* lbm_last_error(void);
 
 /* Launch shape of the fused step.  tile_variant 0..4: 2-D tiles of 64x4
  * (default), 32x8, 64x8, 64x16, 128x4 nodes per workgroup, halo macros
- * recomputed per tile; 5..8: rolling tile columns (a workgroup walks a
- * column segment upward, keeping the row below each block in LDS) of
- * 64 columns x 8 rows per block over 128- and 256-row segments, 128 x 4
- * over 128 rows, and 64 x 12 over 192 rows.
- * xcd_remap: 0 keeps the hardware's round-robin of workgroups over the 8
- * XCDs; 1 gives each XCD one contiguous band of tiles (its L2 then serves
- * the halo re-reads).  Results are bitwise identical for every choice. */
+ * recomputed per tile.
+ * xcd_remap, the order in which the workgroups, dealt round-robin to the
+ * 8 XCDs, take tiles: 0 row-major (the XCDs sweep the grid together); 1 one
+ * contiguous row-major band of tiles per XCD; 2 one band of tile columns
+ * per XCD, swept row by row (the XCDs still sweep the rows together, and
+ * a tile's halo neighbours are mostly in its own XCD's L2).  Results are
+ * bitwise identical for every choice; anything else is LBM_EINVAL. */
 int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap);
 
 /* Time every launch shape for `reps` steps and keep the fastest (written to

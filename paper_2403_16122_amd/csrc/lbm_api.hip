@@ -461,7 +461,8 @@ int lbm_sync(lbm_ctx* c) {
 }
 
 int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap) {
-  if (!c || tile_variant < 0 || tile_variant >= lbmk::NTILE_VARIANTS || xcd_remap < 0 || xcd_remap > 1)
+  if (!c || tile_variant < 0 || tile_variant >= lbmk::NTILE_VARIANTS || xcd_remap < 0 ||
+      xcd_remap >= lbmk::NXCD_MODES)
     return LBM_EINVAL;
   c->tile_variant = tile_variant;
   c->xcd = xcd_remap;
@@ -485,7 +486,7 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_r
   float best = 1e30f;
   int bv = c->tile_variant, bx = c->xcd;
   for (int v = 0; v < lbmk::NTILE_VARIANTS; ++v) {
-    for (int x = 0; x <= 1; ++x) {
+    for (int x = 0; x < lbmk::NXCD_MODES; ++x) {
       if (lbmk::launch_step(c->K, c->S, c->cur, false, v, x, c->stream))  // warm-up
         return dev_error(hipGetLastError(), "autotune launch");
       LBM_CK(hipEventRecord(e0, c->stream));

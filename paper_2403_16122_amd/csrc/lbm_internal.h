@@ -79,7 +79,8 @@ struct StepOff {
 };
 
 enum { NFIELD = 10 };
-enum { NTILE_VARIANTS = 9 };  // tiles 64x4, 32x8, 64x8, 64x16, 128x4; rolling columns 64x8/128, 64x8/256, 128x4/128, 64x12/192
+enum { NTILE_VARIANTS = 5 };  // tiles 64x4, 32x8, 64x8, 64x16, 128x4
+enum { NXCD_MODES = 3 };      // workgroup -> tile orders (map_tile)
 enum { RED_NVAL = 8 };
 constexpr int RED_BLOCKS = 512;
 

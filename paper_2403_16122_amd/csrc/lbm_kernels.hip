@@ -503,11 +503,20 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
 }
 
 // Workgroup -> tile.  Workgroups are dispatched round-robin over the 8
-// XCDs (block b runs on XCD b mod 8).  Mode 0 keeps that order; mode 1
-// hands each XCD one contiguous band of tiles_per_xcd tiles, so the halo
-// re-reads of neighbouring tiles meet in one L2.
-__device__ __forceinline__ int map_tile(int b, int mode, int tiles_per_xcd) {
-  return mode == 1 ? (b & 7) * tiles_per_xcd + (b >> 3) : b;
+// XCDs (block b runs on XCD b mod 8).  Mode 0 keeps that order (the XCDs
+// sweep the grid together, row of tiles after row of tiles).  Mode 1 hands
+// each XCD one contiguous band of `band` tiles in row-major order.  Mode 2
+// hands each XCD a band of `band` tile columns, which it sweeps row by row:
+// the XCDs still work on the same rows at the same time, while the x and y
+// neighbours of a tile, whose halo cells it re-reads, are mostly on its own
+// XCD and in its L2.  Returns ntiles or more for padding workgroups.
+__device__ __forceinline__ int map_tile(int b, int mode, int band, int ntx, int ntiles) {
+  if (mode == 1) return (b & 7) * band + (b >> 3);
+  if (mode == 2) {
+    const int i = b >> 3, col = (b & 7) * band + i % band;
+    return col < ntx ? (i / band) * ntx + col : ntiles;
+  }
+  return b;
 }
 
 // One TX x TY tile (origin x0, y0) of the fused step; shared by the
@@ -658,8 +667,8 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
 
 template <int TX, int TY, bool FIELDS, class PT>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) void k_step(
-    KParams P, StepIO io, int ntx, int ntiles, int tiles_per_xcd, int mode) {
-  const int tile = map_tile(blockIdx.x, mode, tiles_per_xcd);
+    KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
+  const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
   if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
   step_tile<TX, TY, FIELDS, PT>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
 }
@@ -687,164 +696,6 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
   const StepIO io = io_of(base, otab[2 * slot + par]);
   const int ntx = (P.nx + TX - 1) / TX;
   step_tile<TX, TY, FIELDS, PT>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
-}
-
-// Rolling tile-column variant.  A workgroup of TX x (RY+1) lanes owns TX
-// columns over a segment of `seg` rows and walks it upward in blocks of RY
-// rows.  Per block, lanes of rows 0..RY-1 rebuild the node macros of their
-// nodes and then update them; the last row of lanes rebuilds the row above
-// the block and, 4 (RY+1) of them, the two halo columns on either side.  The
-// row below the block was rebuilt by the previous block and stays in LDS,
-// so rows are neither fetched again nor rebuilt again for the halo (the
-// tile kernel rebuilds a ring around every tile).  A segment that does not
-// start at the wall first runs one block that only rebuilds the row below
-// it.  All arithmetic is the tile kernel's, so results are bitwise equal.
-template <int TX, int RY, bool FIELDS, class PT>
-__global__ __launch_bounds__(TX*(RY + 1)) __attribute__((amdgpu_waves_per_eu(6))) void k_roll(
-    KParams P, StepIO io, int ncol, int nblocks_total, int seg, int tiles_per_xcd, int mode) {
-  constexpr int LX = TX + 4, LY = RY + 2;  // LDS column c <-> x0 + c - 2, row r <-> Y + r - 1
-  constexpr int RX = LX + 2, RR = LY + 2;  // reference tile: row q <-> Y + q - 2
-  constexpr int NT = TX * (RY + 1);
-  static_assert(4 * (RY + 1) <= TX, "one side-halo cell per lane of the top row");
-  __shared__ float s_phi[LY][LX];
-  __shared__ float s_rho[LY][LX];
-  __shared__ float s_fsH[LY][LX];
-  __shared__ float s_p[LY][LX];
-  __shared__ float s_S[LY][LX];
-  __shared__ float s_ref[RR][RX];
-  constexpr bool NR = PopIO<PT>::kNodeRef;
-  __shared__ float s_th[NR ? RR : 1][NR ? RX : 1];
-
-  const int b = map_tile(blockIdx.x, mode, tiles_per_xcd);
-  if (b >= nblocks_total) return;  // whole workgroup leaves before any barrier
-  const void* __restrict__ A = io.A;
-  const int nx = P.nx, ny = P.ny;
-  const int x0 = (b % ncol) * TX, y0 = (b / ncol) * seg;
-  const int y1 = min(y0 + seg, ny);
-
-  for (int Y = (y0 > 0 ? y0 - RY : y0); Y < y1; Y += RY) {
-    // The lane's indices are rebuilt every block from an opaque copy of its
-    // id: hoisted out of the loop they would stay live across it and double
-    // the register count.
-    int t = threadIdx.x;
-    asm volatile("" : "+v"(t));
-    const int lx = t % TX, ly = t / TX;  // ly == RY: the top row of lanes
-    const int x = x0 + lx;
-    const int xw = wrapx(x, nx);
-    const bool top_lane = ly == RY;
-    // side-halo cell of a top-row lane: LDS row hr (1..RY+1), column hc
-    const bool side = top_lane && lx < 4 * (RY + 1);
-    const int hr = 1 + (lx >> 2), hs = lx & 3;
-    const int hc = hs < 2 ? hs : TX + hs;
-    const bool update = Y >= y0;  // false for the first block of an inner segment
-    // ---- loads: this lane's node (own row or the row above the block), its
-    // side-halo cell, f and (phi u) of own nodes, the reference and lagged tiles
-    Macro m, mh;
-    float f[9], phiux = 0.0f, phiuy = 0.0f;
-    const int y = Y + ly;  // own row (ly < RY) or the row above (ly == RY)
-    const bool row_ok = y >= 0 && y < ny;
-    if (row_ok) load_node<PT>(A, io.fsH_in, P, xw, y, m);
-    const bool own = !top_lane && update && y < y1 && x < nx;
-    if (own) {
-      const int xm = x == 0 ? nx - 1 : x - 1;
-      const int xp = x == nx - 1 ? 0 : x + 1;
-      pull9<1, PT>(A, P, x, y, xm, xp, f);
-      phiux = ld(io.phiu_in, (unsigned)(y * nx + x));
-      phiuy = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
-    }
-    const int gyh = Y + hr - 1;
-    const bool halo = side && gyh >= 0 && gyh < ny;
-    if (halo) load_node<PT>(A, io.fsH_in, P, wrapx(x0 + hc - 2, nx), gyh, mh);
-    for (int j = t; j < (RR - 1) * RX; j += NT) {  // reference rows 1..RR-1 (Y-1 .. Y+RY+1)
-      const int q = 1 + j / RX, c = j - (j / RX) * RX;
-      const int gy = min(max(Y + q - 2, 0), ny - 1);
-      float rv, tv;
-      RefIO<NR>::load(io.ref_in, (unsigned)(gy * nx + wrapx(x0 + c - 3, nx)), rv, tv);
-      s_ref[q][c] = rv;
-      if constexpr (NR) s_th[q][c] = tv;
-    }
-    for (int j = t; j < LX * LY; j += NT) {
-      const int r = j / LX, c = j - (j / LX) * LX;
-      const int gy = min(max(Y + r - 1, 0), ny - 1);
-      const int kk = gy * nx + wrapx(x0 + c - 2, nx);
-      s_p[r][c] = ld(io.p_in, (unsigned)kk);
-      s_S[r][c] = ld(io.S_in, (unsigned)kk);
-    }
-    __syncthreads();
-
-    // ---- macros of rows Y .. Y+RY into LDS rows 1 .. RY+1 (row 0: carried)
-    if (row_ok) {
-      const float rs = rebase_g<RX>(m.g, s_ref, P, y, lx + 2, ly + 1);
-      if constexpr (NR) m.th = rebase_h<RX>(m.h, s_th, P, y, lx + 2, ly + 1);
-      finish_macro<NR>(P, rs, m);
-      s_phi[ly + 1][lx + 2] = (m.r - 1.0f) + m.dl;
-      s_rho[ly + 1][lx + 2] = m.rho;
-      s_fsH[ly + 1][lx + 2] = m.fsH;
-    }
-    if (halo) {
-      const float rs = rebase_g<RX>(mh.g, s_ref, P, gyh, hc, hr);
-      if constexpr (NR) mh.th = rebase_h<RX>(mh.h, s_th, P, gyh, hc, hr);
-      finish_macro<NR>(P, rs, mh);
-      s_phi[hr][hc] = (mh.r - 1.0f) + mh.dl;
-      s_rho[hr][hc] = mh.rho;
-      s_fsH[hr][hc] = mh.fsH;
-    }
-    __syncthreads();
-
-    // ---- wall ghost rows (Eq. (39)-(41))
-    const bool has_bot = (Y == 0), has_top = (ny <= Y + RY);
-    if (has_bot || has_top) {
-      for (int j = t; j < 2 * LX; j += NT) {
-        const bool isb = j < LX;
-        const int c = isb ? j : j - LX;
-        if (c < 1 || c > LX - 2) continue;
-        int r, r0, r1;
-        float tv;
-        if (isb) {
-          if (!has_bot) continue;
-          r = 0;
-          r0 = 1;
-          r1 = 2;
-          tv = P.tan_b;
-        } else {
-          if (!has_top) continue;
-          r = ny - Y + 1;
-          r0 = r - 1;
-          r1 = r - 2;
-          tv = P.tan_t;
-        }
-        const float pg = wetting_ghost(s_phi[r0][c - 1], s_phi[r0][c], s_phi[r0][c + 1], s_phi[r1][c - 1],
-                                       s_phi[r1][c + 1], tv);
-        const float pcg = clamp01(1.0f + pg);
-        s_phi[r][c] = pg;
-        s_rho[r][c] = mix3(pcg * s_fsH[r0][c], pcg, P.rho_s, P.rho_l, P.rho_g);
-      }
-      __syncthreads();
-    }
-
-    // ---- update own nodes of the block
-    if (own) {
-      const int r = ly + 1, c = lx + 2;
-      Grads d;
-#define LBM_ROLL_STENCIL(arr, ox, oy, lap)                                                          \
-  stencil(arr[r][c], arr[r][c + 1], arr[r][c - 1], arr[r + 1][c], arr[r - 1][c], arr[r + 1][c + 1], \
-          arr[r + 1][c - 1], arr[r - 1][c - 1], arr[r - 1][c + 1], ox, oy, lap)
-      LBM_ROLL_STENCIL(s_phi, d.phx, d.phy, &d.lphi);
-      LBM_ROLL_STENCIL(s_rho, d.rx, d.ry, nullptr);
-      LBM_ROLL_STENCIL(s_p, d.px, d.py, nullptr);
-      LBM_ROLL_STENCIL(s_S, d.Sx, d.Sy, nullptr);
-#undef LBM_ROLL_STENCIL
-      update_node<FIELDS, PT>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x));
-    }
-    __syncthreads();
-    // ---- carry row RY (y = Y + RY - 1) to row 0 for the next block
-    for (int j = t; j < LX; j += NT) {
-      s_phi[0][j] = s_phi[RY][j];
-      s_rho[0][j] = s_rho[RY][j];
-      s_fsH[0][j] = s_fsH[RY][j];
-    }
-    __syncthreads();
-  }
 }
 
 // Initial state (no time-stepping yet): u = 0, p = 0, liquid fraction 1,
@@ -1083,35 +934,19 @@ template <int TX, int TY, class PT>
 int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int xcd, hipStream_t st) {
   const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
   const int ntiles = ntx * nty;
-  int tpx = 0, grid = ntiles;
+  int band = 0, grid = ntiles;
   if (xcd == 1) {
-    tpx = (ntiles + 7) / 8;
-    grid = 8 * tpx;
+    band = (ntiles + 7) / 8;
+    grid = 8 * band;
+  } else if (xcd == 2) {
+    band = (ntx + 7) / 8;
+    grid = 8 * band * nty;
   }
   const StepIO io = make_io(S, cur);
   if (fields_only)
-    hipLaunchKernelGGL((k_step<TX, TY, true, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx, xcd);
+    hipLaunchKernelGGL((k_step<TX, TY, true, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
   else
-    hipLaunchKernelGGL((k_step<TX, TY, false, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, tpx, xcd);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-template <int TX, int RY, class PT>
-int launch_roll(const KParams& P, const State& S, int cur, bool fields_only, int seg, int xcd, hipStream_t st) {
-  const int ncol = (P.nx + TX - 1) / TX, nseg = (P.ny + seg - 1) / seg;
-  const int nb = ncol * nseg;
-  int tpx = 0, grid = nb;
-  if (xcd == 1) {
-    tpx = (nb + 7) / 8;
-    grid = 8 * tpx;
-  }
-  const StepIO io = make_io(S, cur);
-  if (fields_only)
-    hipLaunchKernelGGL((k_roll<TX, RY, true, PT>), dim3(grid), dim3(TX * (RY + 1)), 0, st, P, io, ncol, nb, seg, tpx,
-                       xcd);
-  else
-    hipLaunchKernelGGL((k_roll<TX, RY, false, PT>), dim3(grid), dim3(TX * (RY + 1)), 0, st, P, io, ncol, nb, seg, tpx,
-                       xcd);
+    hipLaunchKernelGGL((k_step<TX, TY, false, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1131,14 +966,6 @@ int launch_step_t(const KParams& P, const State& S, int cur, bool fields_only, i
       return launch_tile<64, 16, PT>(P, S, cur, fields_only, xcd_remap, st);
     case 4:
       return launch_tile<128, 4, PT>(P, S, cur, fields_only, xcd_remap, st);
-    case 5:
-      return launch_roll<64, 8, PT>(P, S, cur, fields_only, 128, xcd_remap, st);
-    case 6:
-      return launch_roll<64, 8, PT>(P, S, cur, fields_only, 256, xcd_remap, st);
-    case 7:
-      return launch_roll<128, 4, PT>(P, S, cur, fields_only, 128, xcd_remap, st);
-    case 8:
-      return launch_roll<64, 12, PT>(P, S, cur, fields_only, 192, xcd_remap, st);
     default:
       return launch_tile<64, 4, PT>(P, S, cur, fields_only, xcd_remap, st);
   }

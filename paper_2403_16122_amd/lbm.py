@@ -17,8 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 FIELD_BITS = {"phi": 0, "T": 1, "ux": 2, "uy": 3, "p": 4, "fs": 5, "fl": 6, "rho": 7, "H": 8, "mdot": 9}
-TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4,
-                 "roll64x8s128": 5, "roll64x8s256": 6, "roll128x4s128": 7, "roll64x12s192": 8}
+TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4}
+XCD_MODES = (0, 1, 2)  # row-major tiles; one row-major band per XCD; one column band per XCD
 TILE_NAMES = {v: k for k, v in TILE_VARIANTS.items()}
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}  # LBM_STORE_FP32 / _FP16_SHIFT / _BF16_SHIFT
 
@@ -201,7 +201,8 @@ class Solver:
             self._h = None
 
     def set_launch(self, tile: str = "64x4", xcd_remap=1):
-        """xcd_remap: 0 round-robin dispatch over the XCDs, 1 one contiguous band per XCD."""
+        """xcd_remap: workgroup -> tile order, 0 row-major, 1 one contiguous band
+        of tiles per XCD, 2 one band of tile columns per XCD (lbm_set_launch)."""
         self._check(self.L.lbm_set_launch(self._h, TILE_VARIANTS[tile], int(xcd_remap)), "lbm_set_launch")
 
     def autotune(self, reps: int = 20):
