@@ -38,9 +38,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, storage: str = "fp32"):
+def measured_traffic(workload: str, storage: str, tile: str, xcd: int):
     """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE runs stored
-    under profiles/, valid only for the kernel source they were taken on."""
+    under profiles/, valid only for the kernel source and the launch shape
+    (tile, workgroup order) they were taken on."""
     tag = workload if storage == "fp32" else f"{workload}_{storage}"
     path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
     if not os.path.exists(path):
@@ -48,7 +49,8 @@ def measured_traffic(workload: str, storage: str = "fp32"):
     rec = json.load(open(path))
     if rec.get("kernel_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    rec = rec.get("launches", {}).get(f"{tile}/{int(xcd)}")
+    return rec["bytes_per_launch"] if rec else None
 
 
 def time_steps(solver, steps: int, warmup: int):
@@ -190,6 +192,11 @@ def cpu_baseline(params, phi0, T0, budget_s: float):
                 sample=f"{n} steps of the same workload from its initial state ({dt:.1f} s, FP64, OpenMP rows)")
 
 
+def note(msg: str):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,7 +255,7 @@ def main():
     mlups = N * args.steps / secs / 1e6
     launch_s = secs / args.steps
     achieved = bpn * N / launch_s / 1e9
-    traffic = measured_traffic(args.workload, args.storage)
+    traffic = measured_traffic(args.workload, args.storage, tile, xcd)
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -280,6 +287,7 @@ def main():
     }
     del solver
     torch.cuda.empty_cache()
+    note(f"{args.workload}: {out['value']} MLUPS ({tile}, order {xcd})")
     if args.probe_steps > 0:
         pp, pphi, pT, _ = W.workload("probe4096", seed=0)
         pp["storage"] = params["storage"]
@@ -294,10 +302,11 @@ def main():
             "steps": args.probe_steps, "MLUPS": round(Np * args.probe_steps / psecs / 1e6, 1),
             "tile": ptile, "xcd_remap": pxcd,
             "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("probe4096", args.storage),
+            "traffic": measured_traffic("probe4096", args.storage, ptile, pxcd),
         }
         del ps
         torch.cuda.empty_cache()
+        note(f"probe4096: {out['hbm_probe']['MLUPS']} MLUPS ({ptile}, order {pxcd})")
         # the same probe with 16-bit population storage (FP32 compute)
         if args.storage == "fp32" and args.storage_variants:
             out["storage_variants"] = {}
@@ -312,15 +321,17 @@ def main():
                     "workload": "probe4096", "MLUPS": round(Np * args.probe_steps / vsecs / 1e6, 1),
                     "tile": vtile, "xcd_remap": vxcd, "bytes_per_node": BYTES_PER_NODE[st],
                     "achieved": round(vach, 1), "unit": "GB/s", "frac": round(vach / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic("probe4096", st),
+                    "traffic": measured_traffic("probe4096", st, vtile, vxcd),
                 }
                 del vs
                 torch.cuda.empty_cache()
+                note(f"probe4096 {st}: {out['storage_variants'][st]['MLUPS']} MLUPS ({vtile}, order {vxcd})")
     if args.sweep_droplets > 0:
         out["sweep"] = sweep_bench(lbm, W, args.sweep_droplets, args.sweep_plain, args.sweep_time_limit)
         torch.cuda.empty_cache()
     if args.surrogate:
         out["surrogate"] = surrogate_bench(out.get("sweep"))
+        note("surrogate done")
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(params, phi0, T0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
