@@ -25,6 +25,11 @@ if ROOT not in sys.path:
 
 # algorithmic bytes per node update: 27 populations and 5 FP32 history
 # values, each read and written once
+# Unfused two-kernel step: the macro pass reads g, h (18 populations) and
+# f_s^H and writes phi, rho, f_s^H; the collide pass reads all populations,
+# the history fields and those three planes, and writes what the fused step
+# writes: 256 + 18 pop reads + 4 B + 3 x 4 B written and read back.
+UNFUSED_BYTES_PER_NODE = {"fp32": 256 + 18 * 4 + 4 + 24, "fp16": 148 + 18 * 2 + 4 + 24, "bf16": 148 + 18 * 2 + 4 + 24}
 BYTES_PER_NODE = {"fp32": 27 * 8 + 40, "fp16": 27 * 4 + 40, "bf16": 27 * 4 + 40}
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS (φ+flow+T lattices), % HBM peak; batched sweep droplets/s vs plain"
@@ -176,20 +181,29 @@ def surrogate_bench(sweep):
     return out
 
 
+def oracle_rate(oracle, params, phi0, T0, budget_s: float, threads: int):
+    """MLUPS of the FP64 oracle over `budget_s` seconds of steps from the
+    initial state, and the number of steps taken."""
+    o = oracle.OracleSolver(params, phi0, T0, threads=threads)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        o.step(5)
+        n += 5
+    dt = time.perf_counter() - t0
+    return params["nx"] * params["ny"] * n / dt / 1e6, n, dt
+
+
 def cpu_baseline(params, phi0, T0, budget_s: float):
     import oracle
 
-    o = oracle.OracleSolver(params, phi0, T0)
-    n = 0
-    t0 = time.perf_counter()
-    chunk = 5
-    while time.perf_counter() - t0 < budget_s:
-        o.step(chunk)
-        n += chunk
-    dt = time.perf_counter() - t0
-    return dict(value=round(params["nx"] * params["ny"] * n / dt / 1e6, 3), unit="MLUPS",
-                cores=oracle.oracle.default_threads(), kind="oracle",
-                sample=f"{n} steps of the same workload from its initial state ({dt:.1f} s, FP64, OpenMP rows)")
+    cores = oracle.oracle.default_threads()
+    v, n, dt = oracle_rate(oracle, params, phi0, T0, budget_s, cores)
+    v1, n1, dt1 = oracle_rate(oracle, params, phi0, T0, budget_s / 3, 1)
+    return dict(value=round(v, 3), unit="MLUPS", cores=cores, kind="oracle",
+                sample=f"{n} steps of the same workload from its initial state ({dt:.1f} s, FP64, OpenMP rows)",
+                single_thread={"value": round(v1, 3), "unit": "MLUPS", "cores": 1,
+                               "sample": f"{n1} steps from the initial state ({dt1:.1f} s, FP64, one thread)"})
 
 
 def note(msg: str):
@@ -303,6 +317,15 @@ def main():
             "tile": ptile, "xcd_remap": pxcd,
             "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("probe4096", args.storage, ptile, pxcd),
+        }
+        # the unfused two-kernel step on the same grid: what fusion saves
+        ps.set_launch("unfused64x8", pxcd)
+        usecs, _ = time_steps(ps, args.probe_steps, 10)
+        ubpn = UNFUSED_BYTES_PER_NODE[args.storage]
+        out["hbm_probe"]["unfused"] = {
+            "launch": f"unfused64x8, order {pxcd}", "MLUPS": round(Np * args.probe_steps / usecs / 1e6, 1),
+            "bytes_per_node": ubpn, "achieved": round(ubpn * Np / (usecs / args.probe_steps) / 1e9, 1),
+            "fused_speedup": round(usecs / psecs, 3),
         }
         del ps
         torch.cuda.empty_cache()

@@ -132,7 +132,10 @@ const char* lbm_last_error(void);
 
 /* Launch shape of the fused step.  tile_variant 0..4: 2-D tiles of 64x4
  * (default), 32x8, 64x8, 64x16, 128x4 nodes per workgroup, halo macros
- * recomputed per tile.
+ * recomputed per tile.  5: the unfused two-kernel step on 64x8 tiles (a
+ * macro pass writes phi, rho and f_s^H of every node, then the collide pass
+ * reads its halo from there), bitwise equal to the fused step and kept to
+ * measure what fusion saves; lbm_autotune does not consider it.
  * xcd_remap, the order in which the workgroups, dealt round-robin to the
  * 8 XCDs, take tiles: 0 row-major (the XCDs sweep the grid together); 1 one
  * contiguous row-major band of tiles per XCD; 2 one band of tile columns

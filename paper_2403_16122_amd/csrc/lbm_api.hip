@@ -485,7 +485,7 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_r
   hipEvent_t e0 = ev.a, e1 = ev.b;
   float best = 1e30f;
   int bv = c->tile_variant, bx = c->xcd;
-  for (int v = 0; v < lbmk::NTILE_VARIANTS; ++v) {
+  for (int v = 0; v < lbmk::NTUNED_VARIANTS; ++v) {
     for (int x = 0; x < lbmk::NXCD_MODES; ++x) {
       if (lbmk::launch_step(c->K, c->S, c->cur, false, v, x, c->stream))  // warm-up
         return dev_error(hipGetLastError(), "autotune launch");

@@ -79,7 +79,8 @@ struct StepOff {
 };
 
 enum { NFIELD = 10 };
-enum { NTILE_VARIANTS = 5 };  // tiles 64x4, 32x8, 64x8, 64x16, 128x4
+enum { NTILE_VARIANTS = 6 };  // tiles 64x4, 32x8, 64x8, 64x16, 128x4; 5: unfused two-kernel 64x8
+enum { NTUNED_VARIANTS = 5 };  // the autotuner times the fused shapes only
 enum { NXCD_MODES = 3 };      // workgroup -> tile orders (map_tile)
 enum { RED_NVAL = 8 };
 constexpr int RED_BLOCKS = 512;

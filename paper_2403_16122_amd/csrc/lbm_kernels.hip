@@ -520,8 +520,11 @@ __device__ __forceinline__ int map_tile(int b, int mode, int band, int ntx, int 
 }
 
 // One TX x TY tile (origin x0, y0) of the fused step; shared by the
-// single-grid kernel and the batched one.
-template <int TX, int TY, bool FIELDS, class PT>
+// single-grid kernel and the batched one.  MACRO_IN: the collide pass of
+// the unfused two-kernel step; phi - 1, rho and f_s^H of every node were
+// written by k_macro to the first three output-field planes, and the halo
+// is read from there instead of being rebuilt from pulled populations.
+template <int TX, int TY, bool FIELDS, class PT, bool MACRO_IN = false>
 __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, int x0, int y0) {
   constexpr int NT = TX * TY;
   constexpr int LX = TX + 4, LY = TY + 2;  // LDS column c <-> x0 + c - 2, row r <-> y0 + r - 1
@@ -562,7 +565,7 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
   }
   int hr = 0, hc = 0;
   bool halo = false;
-  if (t < NRING) {
+  if (!MACRO_IN && t < NRING) {
     if (t < LX) {
       hr = 0;
       hc = t;
@@ -596,6 +599,11 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
     const int kk = gy * nx + wrapx(x0 + c - 2, nx);
     s_p[r][c] = ld(io.p_in, (unsigned)kk);
     s_S[r][c] = ld(io.S_in, (unsigned)kk);
+    if constexpr (MACRO_IN) {
+      s_phi[r][c] = ld(io.fields, (unsigned)kk);
+      s_rho[r][c] = ld(io.fields, P.plane + (unsigned)kk);
+      s_fsH[r][c] = ld(io.fields, 2u * P.plane + (unsigned)kk);
+    }
   }
   __syncthreads();
 
@@ -671,6 +679,55 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
   const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
   if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
   step_tile<TX, TY, FIELDS, PT>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
+}
+
+// Unfused two-kernel step, kept to measure what fusion saves.  Pass 1
+// (k_macro) pulls g and h and writes phi - 1, rho and f_s^H of time t of
+// every node to the first three output-field planes; pass 2 (k_collide)
+// pulls all 27 populations again, rebuilds its own node's macros and takes
+// the halo values from those planes.  The arithmetic is the fused kernel's,
+// so the results are bitwise equal.
+template <int TX, int TY, class PT>
+__global__ __launch_bounds__(TX* TY) void k_macro(KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
+  const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
+  if (tile >= ntiles) return;
+  constexpr int RX = TX + 2, RR = TY + 2;  // reference tile: row q <-> y0 + q - 1, column c <-> x0 + c - 1
+  constexpr bool NR = PopIO<PT>::kNodeRef;
+  __shared__ float s_ref[RR][RX];
+  __shared__ float s_th[NR ? RR : 1][NR ? RX : 1];
+  const int nx = P.nx, ny = P.ny;
+  const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+  const int t = threadIdx.x, lx = t % TX, ly = t / TX;
+  const int x = x0 + lx, y = y0 + ly;
+  const bool active = y < ny && x < nx;
+  Macro m;
+  if (active) load_node<PT>(io.A, io.fsH_in, P, x, y, m);
+  for (int j = t; j < RX * RR; j += TX * TY) {
+    const int q = j / RX, c = j - (j / RX) * RX;
+    const int gy = min(max(y0 + q - 1, 0), ny - 1);
+    float rv, tv;
+    RefIO<NR>::load(io.ref_in, (unsigned)(gy * nx + wrapx(x0 + c - 1, nx)), rv, tv);
+    s_ref[q][c] = rv;
+    if constexpr (NR) s_th[q][c] = tv;
+  }
+  __syncthreads();
+  if (!active) return;
+  // rebase_* read cell (c, r) at [r + 1][c + 1]: the node is cell (lx, ly)
+  const float rs = rebase_g<RX>(m.g, s_ref, P, y, lx, ly);
+  if constexpr (NR) m.th = rebase_h<RX>(m.h, s_th, P, y, lx, ly);
+  finish_macro<NR>(P, rs, m);
+  const unsigned k = (unsigned)(y * nx + x);
+  io.fields[k] = (m.r - 1.0f) + m.dl;
+  io.fields[P.plane + k] = m.rho;
+  io.fields[2u * P.plane + k] = m.fsH;
+}
+
+template <int TX, int TY, class PT>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) void k_collide(
+    KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
+  const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
+  if (tile >= ntiles) return;
+  step_tile<TX, TY, false, PT, true>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
 }
 
 __device__ __forceinline__ StepIO io_of(char* base, const StepOff& o) {
@@ -954,10 +1011,31 @@ int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int
 
 namespace {
 
+template <int TX, int TY, class PT>
+int launch_unfused(const KParams& P, const State& S, int cur, bool fields_only, int xcd, hipStream_t st) {
+  if (fields_only) return launch_tile<TX, TY, PT>(P, S, cur, true, xcd, st);
+  const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+  const int ntiles = ntx * nty;
+  int band = 0, grid = ntiles;
+  if (xcd == 1) {
+    band = (ntiles + 7) / 8;
+    grid = 8 * band;
+  } else if (xcd == 2) {
+    band = (ntx + 7) / 8;
+    grid = 8 * band * nty;
+  }
+  const StepIO io = make_io(S, cur);
+  hipLaunchKernelGGL((k_macro<TX, TY, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
+  hipLaunchKernelGGL((k_collide<TX, TY, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <class PT>
 int launch_step_t(const KParams& P, const State& S, int cur, bool fields_only, int tile_variant,
                   int xcd_remap, hipStream_t st) {
   switch (tile_variant) {
+    case 5:
+      return launch_unfused<64, 8, PT>(P, S, cur, fields_only, xcd_remap, st);
     case 1:
       return launch_tile<32, 8, PT>(P, S, cur, fields_only, xcd_remap, st);
     case 2:

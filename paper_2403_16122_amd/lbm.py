@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 FIELD_BITS = {"phi": 0, "T": 1, "ux": 2, "uy": 3, "p": 4, "fs": 5, "fl": 6, "rho": 7, "H": 8, "mdot": 9}
-TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4}
+TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4,
+                 "unfused64x8": 5}  # two-kernel step, kept to measure the gain from fusion
 XCD_MODES = (0, 1, 2)  # row-major tiles; one row-major band per XCD; one column band per XCD
 TILE_NAMES = {v: k for k, v in TILE_VARIANTS.items()}
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}  # LBM_STORE_FP32 / _FP16_SHIFT / _BF16_SHIFT
