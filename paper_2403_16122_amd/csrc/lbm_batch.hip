@@ -422,6 +422,16 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
         g_batch_error = "non-finite initial field";
         return LBM_EINVAL;
       }
+    // 16-bit storage needs the temperature span to fit its FP16 node
+    // references: refuse here rather than when the droplet reaches a slot
+    lbmk::KParams K;
+    lbmk::IParams I;
+    double Href;
+    lbmk::fill_constants(p[i], K, I, Href);
+    if (lbmk::storage_setup(p[i], T0[i], N, K)) {
+      g_batch_error = "temperature span too wide for the FP16 node references of 16-bit storage";
+      return LBM_EINVAL;
+    }
   }
   if (d_workspace && (ws_bytes < need || ((uintptr_t)d_workspace & 255))) {
     g_batch_error = "workspace too small or not 256-byte aligned";

@@ -55,3 +55,25 @@ def test_strerror_names_every_code():
     L = lbm.load_library()
     for code in (0, -1, -2, -3, -4, -5):
         assert L.lbm_strerror(code).decode() != "unknown error"
+
+
+def test_batch_refuses_a_wide_temperature_span_before_any_device_call():
+    """16-bit storage keeps T - T_m per node as an FP16 reference; a batch
+    whose droplet exceeds that span is refused by lbm_batch_init itself,
+    before it creates a stream or touches the workspace (both NULL here)."""
+    import ctypes as C
+
+    import numpy as np
+
+    L = lbm.load_library()
+    nx, ny = 16, 12
+    p = dict(W.default_params(nx, ny), storage=lbm.STORAGE["fp16"])
+    phi = np.zeros(nx * ny)
+    T = np.full(nx * ny, p["T_melt"] + 5.0e4)
+    params = (lbm.Params * 1)(lbm.make_params(p))
+    pa = (C.POINTER(C.c_double) * 1)(lbm._dptr(phi))
+    ta = (C.POINTER(C.c_double) * 1)(lbm._dptr(T))
+    h = C.c_void_p()
+    rc = L.lbm_batch_init(params, 1, pa, ta, None, 1, None, 0, None, C.byref(h))
+    assert rc == lbm.LBM_EINVAL and not h.value
+    assert "temperature span" in L.lbm_batch_last_error().decode()
