@@ -54,7 +54,8 @@ enum {
 /* Physical parameters in lattice units.  Mixture properties follow Eq. (1)
  * with subscripts s (solid), l (liquid), g (gas). */
 typedef struct {
-  int32_t nx, ny;                 /* >= 3 each */
+  int32_t nx, ny;                 /* >= 3 each; nx*ny below 39.77M nodes (FP32 storage) or
+                                     79.5M (16-bit), so that one buffer spans < 4 GiB */
   double W, M, sigma;             /* interface width, mobility (tau_g = M/cs^2 + 1/2, Sec. 3.1),
                                      surface tension (beta = 12 sigma/W, kappa = 3 sigma W/2, Eq. (13)) */
   double rho_l, rho_g, rho_s;     /* densities (> 0); rho_s/rho_l sets the mass source, Eq. (19) */

@@ -53,7 +53,15 @@ bool all_finite(const lbm_params* p) {
 int validate_params(const lbm_params* p) {
   if (!p) return LBM_EINVAL;
   if (p->nx < 3 || p->ny < 3) return LBM_EINVAL;
-  if ((long long)p->nx * p->ny > (1LL << 32) / 80) return LBM_EINVAL;  // 32-bit element indices over the workspace
+  {
+    // The kernels address a buffer by a 32-bit byte offset from its base:
+    // the 27 population planes of one buffer and the 10 output-field planes
+    // must each span less than 4 GiB.
+    const long long nodes = (long long)p->nx * p->ny;
+    const long long plane = (nodes + 63) / 64 * 64;
+    const long long pb = p->storage == LBM_STORE_FP32 ? 4 : 2;
+    if (27 * plane * pb >= (1LL << 32) || 10 * plane * 4 >= (1LL << 32)) return LBM_EINVAL;
+  }
   if (!all_finite(p)) return LBM_EINVAL;
   if (!(p->W > 0) || !(p->M > 0) || p->sigma < 0) return LBM_EINVAL;
   if (!(p->rho_l > 0 && p->rho_g > 0 && p->rho_s > 0)) return LBM_EINVAL;

@@ -77,3 +77,20 @@ def test_batch_refuses_a_wide_temperature_span_before_any_device_call():
     rc = L.lbm_batch_init(params, 1, pa, ta, None, 1, None, 0, None, C.byref(h))
     assert rc == lbm.LBM_EINVAL and not h.value
     assert "temperature span" in L.lbm_batch_last_error().decode()
+
+
+def test_largest_grid_keeps_a_buffer_below_4_GiB():
+    """Kernels address a buffer by a 32-bit byte offset: the 27 FP32
+    population planes (108 B per node) must span less than 2^32 bytes, the
+    16-bit ones (54 B per node) too, and so must the 10 output-field planes."""
+    ny = 16
+    nx_max = ((1 << 32) - 1) // 108 // 64 * 64 // ny  # 39,768,192 nodes
+    ok = W.default_params(nx_max, ny)
+    assert lbm.workspace_bytes(ok) > 0
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.workspace_bytes(dict(ok, nx=nx_max + 4))  # one more 64-node plane block
+    assert e.value.code == lbm.LBM_EINVAL
+    half = dict(W.default_params(2 * nx_max, ny), storage=lbm.STORAGE["fp16"])
+    assert lbm.workspace_bytes(half) > 0  # 16-bit populations take twice the nodes
+    with pytest.raises(lbm.LbmError):
+        lbm.workspace_bytes(dict(half, storage=lbm.STORAGE["fp32"]))

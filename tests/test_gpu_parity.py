@@ -312,3 +312,48 @@ def test_invalid_parameters_rejected_at_init():
     with pytest.raises(lbm.LbmError) as e:
         lbm.Solver(p, np.zeros(128), np.ones(128))
     assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_maximum_grid_size_flat_layer(oracle_mod):
+    """The largest FP32 grid the library accepts (the 27 population planes of
+    a buffer just below 4 GiB, which its 32-bit byte offsets can address:
+    16 rows of 2,485,512 columns, a 12.7 GB workspace).  A liquid
+    layer on the cold wall that is uniform in x stays uniform in x, so after
+    20 steps every column must equal column 0 bit for bit, and column 0 must
+    equal a 3-column run of the same problem bit for bit (the arithmetic of
+    a node does not depend on nx); the 3-column run is checked against the
+    oracle."""
+    lbm = _gpu()
+    ny = 16
+    nx = ((1 << 32) - 1) // 108 // 64 * 64 // ny
+
+    def case(n):
+        p = W.default_params(n, ny, rho_s=0.9, theta_bottom_deg=90.0, gy=-1e-6)
+        col_phi = W.flat_layer(1, ny, 9.0, p["W"])
+        col_T = p["T_melt"] + 1e-3 * np.linspace(0.0, 1.0, ny)
+        return p, np.repeat(col_phi, n), np.repeat(col_T, n)
+
+    p, phi0, T0 = case(nx)
+    print(f"maximum grid {nx}x{ny} = {nx * ny} nodes", flush=True)
+    g = lbm.Solver(p, phi0, T0)
+    del phi0, T0
+    g.step(20)
+    assert g.diag()["rc"] == 0
+    names = ("phi", "T", "uy", "p")
+    fg = g.fields(names)
+    del g
+    ps, phis, Ts = case(3)
+    s = lbm.Solver(ps, phis, Ts)
+    s.step(20)
+    fs = s.fields(names)
+    for k in names:
+        a = fg[k].reshape(ny, nx)
+        assert np.array_equal(a, np.repeat(a[:, :1], nx, axis=1)), k
+        assert np.array_equal(a[:, :3], fs[k].reshape(ny, 3)), k
+    o = oracle_mod.OracleSolver(ps, phis, Ts)
+    o.step(20)
+    compare(s.fields(FIELDS), o.fields(FIELDS), "flat layer 3x16 (column of the maximum grid)")
+    del fg
+    import torch
+
+    torch.cuda.empty_cache()  # hand the 17 GB workspace back before the next test
