@@ -208,3 +208,42 @@ def test_storage_report_bubbles1024(oracle_mod):
             assert dg["rc"] == 0
             ints = {k: abs(dg[k] - do[k]) / abs(do[k]) for k in ("sum_phi", "sum_H", "sum_solid")}
             show(f"report bubbles1024 step {n} {st}", dict(e, **ints, dh_c=abs(dg["h_c"] - do["h_c"])))
+
+
+def test_fp16_at_the_largest_grid_it_admits(oracle_mod):
+    """16-bit populations halve the bytes of a buffer, so the library admits
+    twice the FP32 maximum: 16 rows of 4,971,024 columns (79.5M nodes, the
+    27 FP16 population planes just below 4 GiB).  A flat liquid layer,
+    uniform in x, after 20 steps: every column within the early FP16 bounds
+    of the oracle's 3-column run (stochastic rounding draws differ from
+    column to column, so columns are not bitwise equal here)."""
+    lbm = _lbm()
+    ny = 16
+    nx = ((1 << 32) - 1) // 54 // 64 * 64 // ny
+
+    def case(n):
+        p = W.default_params(n, ny, rho_s=0.9, theta_bottom_deg=90.0, gy=-1e-6)
+        col_phi = W.flat_layer(1, ny, 9.0, p["W"])
+        col_T = p["T_melt"] + 1e-3 * np.linspace(0.0, 1.0, ny)
+        return p, np.repeat(col_phi, n), np.repeat(col_T, n)
+
+    p, phi0, T0 = case(nx)
+    print(f"fp16 maximum grid {nx}x{ny} = {nx * ny} nodes", flush=True)
+    g = solver(lbm, p, phi0, T0, "fp16")
+    del phi0, T0
+    g.step(20)
+    assert g.diag()["rc"] == 0
+    f = g.fields(("phi", "T"))
+    del g
+    ps, phis, Ts = case(3)
+    o = oracle_mod.OracleSolver(ps, phis, Ts)
+    o.step(20)
+    fo = o.fields(("phi", "T"))
+    dphi = float(np.abs(f["phi"] - fo["phi"][:, :1]).max())
+    dT = float(np.abs(f["T"] - fo["T"][:, :1]).max())
+    print(f"[fp16 maximum grid] max|dphi| {dphi:.2e} max|dT| {dT:.2e} over all columns", flush=True)
+    assert dphi <= EARLY["fp16"][0] and dT <= EARLY["fp16"][2]
+    del f
+    import torch
+
+    torch.cuda.empty_cache()
