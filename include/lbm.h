@@ -145,6 +145,13 @@ const char* lbm_last_error(void);
  * bitwise identical for every choice; anything else is LBM_EINVAL. */
 int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap);
 
+/* How the step kernel stores its outputs: 0 (default) streaming stores when
+ * the state exceeds MI355X's 256 MiB Infinity Cache, so that it cannot stay
+ * cached from one step's stores to the next step's loads, else cached
+ * stores; 1 always cached; 2 always streaming.  Results are bitwise
+ * identical; anything else is LBM_EINVAL. */
+int lbm_set_store_mode(lbm_ctx* c, int32_t mode);
+
 /* Time every launch shape for `reps` steps and keep the fastest (written to
  * the optional out-pointers).  The state is not advanced: each timed launch
  * recomputes the next step from the same buffers.  Synchronises. */
@@ -209,6 +216,9 @@ int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, d
  * droplet after droplet (0); results are bitwise identical either way. */
 int lbm_batch_set_launch(lbm_batch* b, int32_t tile_variant, int32_t xcd_group);
 int lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* tile_variant, int32_t* xcd_group);
+/* Store mode of the batched step, as lbm_set_store_mode (mode 0 compares
+ * the whole batch workspace with the Infinity Cache). */
+int lbm_batch_set_store_mode(lbm_batch* b, int32_t mode);
 
 /* Advance the resident droplets by nsteps (whole sampling intervals).  With
  * until_frozen, finished droplets retire and queued ones take their slots,

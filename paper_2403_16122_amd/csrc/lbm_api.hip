@@ -151,6 +151,7 @@ void fill_constants(const lbm_params& p, KParams& K, IParams& I, double& Href) {
   K.bq_Tref = (float)p.bq_Tref;
   K.chi = (float)p.st_solid_mask;
   K.seed = 0;
+  K.stream_stores = 0;
   K.storage = p.storage;
   for (int j = 0; j < 3; ++j) K.sc_st[j] = K.sc_ld[j] = 1.0f;
   I.cp_l = p.cp_l;
@@ -188,6 +189,7 @@ struct lbm_ctx {
   int64_t step;
   int tile_variant;
   int xcd;
+  int store_mode;  // 0 by resident size, 1 cached, 2 streaming stores
   double Href;
   std::vector<float> stage;
 };
@@ -287,12 +289,14 @@ int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_
   c->step = 0;
   c->tile_variant = 0;
   c->xcd = 1;
+  c->store_mode = 0;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
     delete c;
     return dev_error(e, "hipGetDevice");
   }
   c->K = K;
+  c->K.stream_stores = need > lbmk::kInfinityCacheBytes;
   c->I = I;
   c->Href = Href;
   if (d_workspace) {
@@ -474,6 +478,13 @@ int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap) {
     return LBM_EINVAL;
   c->tile_variant = tile_variant;
   c->xcd = xcd_remap;
+  return LBM_OK;
+}
+
+int lbm_set_store_mode(lbm_ctx* c, int32_t mode) {
+  if (!c || mode < 0 || mode > 2) return LBM_EINVAL;
+  c->store_mode = mode;
+  c->K.stream_stores = mode == 2 || (mode == 0 && ws_size(&c->P) > lbmk::kInfinityCacheBytes);
   return LBM_OK;
 }
 

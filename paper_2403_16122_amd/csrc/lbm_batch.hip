@@ -121,6 +121,8 @@ struct lbm_batch {
   int64_t max_steps;
   double freeze_frac;
   int tile_variant, xcd_group;
+  int store_mode;  // 0 by resident size, 1 cached, 2 streaming stores
+  bool nt;         // the step kernels stream their stores
   bool use_graph;
   hipGraphExec_t exec;
   bool graph_valid;
@@ -213,10 +215,10 @@ int enqueue_chunk(lbm_batch* b, hipStream_t st) {
   // step numbers at the start of the interval (read from pinned memory when the copy runs)
   LBMB_CK(hipMemcpyAsync(b->d_steps(), b->h_steps, sizeof(unsigned) * b->slots, hipMemcpyHostToDevice, st));
   for (int s = 0; s < b->sample_every; ++s)
-    if (lbmk::launch_batch(b->storage, b->tile_variant, false, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(),
+    if (lbmk::launch_batch(b->storage, b->tile_variant, false, b->nt, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(),
                            b->d_steps(), b->nblocks, s, st))
       return bdev_error(hipGetLastError(), "batch step launch");
-  if (lbmk::launch_batch(b->storage, b->tile_variant, true, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(),
+  if (lbmk::launch_batch(b->storage, b->tile_variant, true, false, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(),
                          b->d_steps(), b->nblocks, 0, st))
     return bdev_error(hipGetLastError(), "batch fields launch");
   const int na = (int)b->active.size();
@@ -255,7 +257,7 @@ int sample_now(lbm_batch* b, const std::vector<int>& slots) {
   std::vector<int> keep_active = b->active;
   b->active = slots;
   int rc = upload_map(b);
-  if (!rc && lbmk::launch_batch(b->storage, b->tile_variant, true, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(),
+  if (!rc && lbmk::launch_batch(b->storage, b->tile_variant, true, false, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(),
                                 b->d_steps(), b->nblocks, 0, b->stream))
     rc = bdev_error(hipGetLastError(), "batch fields launch");
   if (!rc && lbmk::launch_batch_liquid(b->ws, b->d_ptab(), b->d_otab(), b->d_slots(), (int)slots.size(), b->d_liq(),
@@ -456,6 +458,8 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
   b->freeze_frac = 0.01;
   b->tile_variant = 0;
   b->xcd_group = 1;
+  b->store_mode = 0;
+  b->nt = b->L.total > lbmk::kInfinityCacheBytes;
   b->use_graph = true;
   b->drops.resize(n);
   for (int i = 0; i < n; ++i) {
@@ -529,6 +533,14 @@ int lbm_batch_set_launch(lbm_batch* b, int32_t tile_variant, int32_t xcd_group) 
   return upload_map(b);
 }
 
+int lbm_batch_set_store_mode(lbm_batch* b, int32_t mode) {
+  if (!b || mode < 0 || mode > 2) return LBM_EINVAL;
+  b->store_mode = mode;
+  b->nt = mode == 2 || (mode == 0 && b->L.total > lbmk::kInfinityCacheBytes);
+  drop_graph(b);  // the captured launches name the kernel
+  return LBM_OK;
+}
+
 int lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* tile_variant, int32_t* xcd_group) {
   if (!b || reps < 1) return LBM_EINVAL;
   if (b->active.empty()) return LBM_OK;
@@ -552,12 +564,12 @@ int lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* tile_variant, int32_
       b->xcd_group = x;
       int rc = upload_map(b);
       if (rc) return rc;
-      if (lbmk::launch_batch(b->storage, v, false, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(), b->d_steps(),
+      if (lbmk::launch_batch(b->storage, v, false, b->nt, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(), b->d_steps(),
                              b->nblocks, 0, b->stream))
         return bdev_error(hipGetLastError(), "autotune launch");
       LBMB_CK(hipEventRecord(ev.a, b->stream));
       for (int r = 0; r < reps; ++r)
-        if (lbmk::launch_batch(b->storage, v, false, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(), b->d_steps(),
+        if (lbmk::launch_batch(b->storage, v, false, b->nt, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(), b->d_steps(),
                                b->nblocks, 0, b->stream))
           return bdev_error(hipGetLastError(), "autotune launch");
       LBMB_CK(hipEventRecord(ev.c, b->stream));

@@ -30,7 +30,12 @@ struct KParams {
   int storage;                     // STORE_FP32 / STORE_FP16 / STORE_BF16
   float sc_st[3], sc_ld[3];        // FP16 only: per-lattice power-of-two scale on store / load
   unsigned seed;                   // 16-bit storage: step number, seeds the stochastic rounding
+  int stream_stores;               // host-side launch choice: streaming (non-temporal) stores
 };
+
+// Resident state beyond this (MI355X's Infinity Cache) cannot stay cached from
+// one step's stores to the next step's loads: the step then streams its stores.
+constexpr size_t kInfinityCacheBytes = size_t(256) << 20;
 
 enum { STORE_FP32 = 0, STORE_FP16 = 1, STORE_BF16 = 2 };
 
@@ -123,7 +128,8 @@ void tile_shape(int tile_variant, int* tx, int* ty);
 // slot << 16 | tile, ~0u = none), with the per-slot constants d_ptab[slot],
 // buffer sets d_otab[2 slot + (s & 1)] (offsets from d_base) and step
 // numbers d_steps[slot] + s (seeds of the stochastic rounding).
-int launch_batch(int storage, int tile_variant, bool fields_only, char* d_base, const KParams* d_ptab,
+int launch_batch(int storage, int tile_variant, bool fields_only, bool stream_stores, char* d_base,
+                 const KParams* d_ptab,
                  const StepOff* d_otab, const unsigned* d_tmap, const unsigned* d_steps, int nblocks, int s,
                  hipStream_t st);
 // Per listed slot (d_slots, nslots entries), from its field planes:

@@ -50,8 +50,22 @@ __device__ __forceinline__ int wrapx(int x, int nx) {
 __device__ __forceinline__ float ld(const float* __restrict__ base, unsigned idx) {
   return *(const float*)((const char*)base + (idx << 2));
 }
+// NT: a streaming store, which does not keep the line in the caches (for
+// state that cannot stay cache-resident until the next step reads it).
+template <bool NT = false>
 __device__ __forceinline__ void st(float* __restrict__ base, unsigned idx, float v) {
-  *(float*)((char*)base + (idx << 2)) = v;
+  float* a = (float*)((char*)base + (idx << 2));
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, a);
+  else
+    *a = v;
+}
+template <bool NT, class T>
+__device__ __forceinline__ void st_as(void* a, T v) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, (T*)a);
+  else
+    *(T*)a = v;
 }
 
 // Hardware reciprocal (1 ulp); used identically wherever a node is rebuilt.
@@ -97,7 +111,10 @@ struct PopIO<float> {
   static constexpr bool kNodeRef = false;
   static constexpr bool kScaled = false;
   static __device__ __forceinline__ float get(const void* b, unsigned idx) { return ld((const float*)b, idx); }
-  static __device__ __forceinline__ void put(void* b, unsigned idx, float v, unsigned) { st((float*)b, idx, v); }
+  template <bool NT>
+  static __device__ __forceinline__ void put(void* b, unsigned idx, float v, unsigned) {
+    st<NT>((float*)b, idx, v);
+  }
 };
 template <>
 struct PopIO<_Float16> {
@@ -106,10 +123,11 @@ struct PopIO<_Float16> {
   static __device__ __forceinline__ float get(const void* b, unsigned idx) {
     return (float)*(const _Float16*)((const char*)b + (idx << 1));
   }
+  template <bool NT>
   static __device__ __forceinline__ void put(void* b, unsigned idx, float v, unsigned rnd) {
     half2v h = {0, 0};
     h = __builtin_amdgcn_cvt_sr_f16_f32(h, v, rnd, false);
-    *(_Float16*)((char*)b + (idx << 1)) = h.x;
+    st_as<NT, _Float16>((char*)b + (idx << 1), h.x);
   }
 };
 template <>
@@ -119,10 +137,11 @@ struct PopIO<__bf16> {
   static __device__ __forceinline__ float get(const void* b, unsigned idx) {
     return (float)*(const __bf16*)((const char*)b + (idx << 1));
   }
+  template <bool NT>
   static __device__ __forceinline__ void put(void* b, unsigned idx, float v, unsigned rnd) {
     bf162v h = {0, 0};
     h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, rnd, false);
-    *(__bf16*)((char*)b + (idx << 1)) = h.x;
+    st_as<NT, __bf16>((char*)b + (idx << 1), h.x);
   }
 };
 // Node references.  FP32 storage keeps phi_ref, the reference of the stored
@@ -142,7 +161,10 @@ struct RefIO<false> {
     r = phi;
     th = 0.0f;
   }
-  static __device__ __forceinline__ void store(void* b, unsigned k, float r, float) { st((float*)b, k, r); }
+  template <bool NT = false>
+  static __device__ __forceinline__ void store(void* b, unsigned k, float r, float) {
+    st<NT>((float*)b, k, r);
+  }
 };
 template <>
 struct RefIO<true> {
@@ -155,11 +177,12 @@ struct RefIO<true> {
     r = (float)(_Float16)phi;
     th = (float)(_Float16)dT;
   }
+  template <bool NT = false>
   static __device__ __forceinline__ void store(void* b, unsigned k, float r, float th) {
     half2v v;
     v.x = (_Float16)r;  // exact: r and th are already FP16 values
     v.y = (_Float16)th;
-    *(half2v*)((char*)b + (k << 2)) = v;
+    st_as<NT, half2v>((char*)b + (k << 2), v);
   }
 };
 
@@ -170,10 +193,10 @@ __device__ __forceinline__ float pop_ld(const void* A, unsigned idx, const KPara
   return v;
 }
 // rnd: the node's hash (sr_node) xor sr_pop(population); unused for FP32
-template <class PT, int LAT>
+template <class PT, int LAT, bool NT = false>
 __device__ __forceinline__ void pop_st(void* B, unsigned idx, float v, const KParams& P, unsigned rnd) {
   if constexpr (PopIO<PT>::kScaled) v *= P.sc_st[LAT];
-  PopIO<PT>::put(B, idx, v, rnd);
+  PopIO<PT>::template put<NT>(B, idx, v, rnd);
 }
 // Plane `j` of a population buffer.
 template <class PT>
@@ -369,7 +392,7 @@ __device__ __forceinline__ float wetting_ghost(float a0m, float a0c, float a0p, 
 // Everything after the stencils for one node k: interface terms (Eq. (3),
 // (12), (13)), forces (Eq. (11)), flow macros (Eq. (34)-(36)) and the three
 // BGK collisions with their stores, or the output fields when FIELDS.
-template <bool FIELDS, class PT>
+template <bool FIELDS, class PT, bool STREAM = false>
 __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, const Macro& m,
                                             const float f[9], float phiux, float phiuy,
                                             const Grads& d, unsigned k) {
@@ -443,7 +466,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float feq = 3.0f * p * (wt(i) - (i == 0 ? 1.0f : 0.0f)) + rho * si;
       const float cF = cx * Ftx + cy * Fty;
       const float Fi = wt(i) * (Ssrc + 3.0f * (cx * Gx + cy * Gy) + 9.0f * cu * cF - 3.0f * uFt);
-      pop_st<PT, 1>(Bf, i * pl + k, f[i] - (f[i] - feq) * itau + sf * Fi, P, rb ^ sr_pop(9 + i));
+      pop_st<PT, 1, STREAM>(Bf, i * pl + k, f[i] - (f[i] - feq) * itau + sf * Fi, P, rb ^ sr_pop(9 + i));
     }
   }
   // phase-field collision (Eq. (21), (24), (25), (37))
@@ -464,11 +487,11 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float gi = m.g[i] + wt(i) * dr;                 // g_i - w_i phi_ref
       const float geq = wt(i) * (dln + 3.0f * phi * cu);  // g_i^eq - w_i phi_ref
       const float Gi = wt(i) * (cx * ax + cy * ay + pm);
-      pop_st<PT, 0>(B, i * pl + k, gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi, P, rb ^ sr_pop(i));
+      pop_st<PT, 0, STREAM>(B, i * pl + k, gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi, P, rb ^ sr_pop(i));
     }
-    RefIO<PopIO<PT>::kNodeRef>::store(io.ref_out, k, r_new, th_new);
-    st(io.phiu_out, k, pux);
-    st(io.phiu_out, pl + k, puy);
+    RefIO<PopIO<PT>::kNodeRef>::template store<STREAM>(io.ref_out, k, r_new, th_new);
+    st<STREAM>(io.phiu_out, k, pux);
+    st<STREAM>(io.phiu_out, pl + k, puy);
   }
   // enthalpy collision (Eq. (27)-(28)) in the shifted variables
   constexpr bool NR = PopIO<PT>::kNodeRef;
@@ -487,7 +510,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float heq = wt(i) * (crd + cpT * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
       float hn = m.h[i] - (m.h[i] - heq) * itau;
       if (NR) hn += wt(i) * cmove;
-      pop_st<PT, 2>(Bh, i * pl + k, hn, P, rb ^ sr_pop(18 + i));
+      pop_st<PT, 2, STREAM>(Bh, i * pl + k, hn, P, rb ^ sr_pop(18 + i));
       hs += m.h[i];
     }
     // rest population: h0eq - h0 = sum_{i>0} h_i - cp_ref dT + w0 (cp_ref dT - 1.5 cp T u.u);
@@ -495,11 +518,11 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
     const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
     float h0 = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
     if (NR) h0 += W0 * cmove;
-    pop_st<PT, 2>(Bh, k, h0, P, rb ^ sr_pop(18));
+    pop_st<PT, 2, STREAM>(Bh, k, h0, P, rb ^ sr_pop(18));
   }
-  st(io.fsH_out, k, m.fsH);
-  st(io.p_out, k, p);
-  st(io.S_out, k, Ssrc);
+  st<STREAM>(io.fsH_out, k, m.fsH);
+  st<STREAM>(io.p_out, k, p);
+  st<STREAM>(io.S_out, k, Ssrc);
 }
 
 // Workgroup -> tile.  Workgroups are dispatched round-robin over the 8
@@ -524,7 +547,7 @@ __device__ __forceinline__ int map_tile(int b, int mode, int band, int ntx, int 
 // the unfused two-kernel step; phi - 1, rho and f_s^H of every node were
 // written by k_macro to the first three output-field planes, and the halo
 // is read from there instead of being rebuilt from pulled populations.
-template <int TX, int TY, bool FIELDS, class PT, bool MACRO_IN = false>
+template <int TX, int TY, bool FIELDS, class PT, bool MACRO_IN = false, bool STREAM = false>
 __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, int x0, int y0) {
   constexpr int NT = TX * TY;
   constexpr int LX = TX + 4, LY = TY + 2;  // LDS column c <-> x0 + c - 2, row r <-> y0 + r - 1
@@ -670,15 +693,15 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
   LBM_TILE_STENCIL(s_p, d.px, d.py, nullptr);
   LBM_TILE_STENCIL(s_S, d.Sx, d.Sy, nullptr);
 #undef LBM_TILE_STENCIL
-  update_node<FIELDS, PT>(P, io, m, f, phiux, phiuy, d, k);
+  update_node<FIELDS, PT, STREAM>(P, io, m, f, phiux, phiuy, d, k);
 }
 
-template <int TX, int TY, bool FIELDS, class PT>
+template <int TX, int TY, bool FIELDS, class PT, bool STREAM = false>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) void k_step(
     KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
   const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
   if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
-  step_tile<TX, TY, FIELDS, PT>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
+  step_tile<TX, TY, FIELDS, PT, false, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
 }
 
 // Unfused two-kernel step, kept to measure what fusion saves.  Pass 1
@@ -740,7 +763,7 @@ __device__ __forceinline__ StepIO io_of(char* base, const StepOff& o) {
 // Many grids in one launch: workgroup b updates tile tmap[b] & 0xffff of the
 // grid in slot tmap[b] >> 16 (entries of ~0u are padding), with that slot's
 // constants and its buffer set for parity `par`.
-template <int TX, int TY, bool FIELDS, class PT>
+template <int TX, int TY, bool FIELDS, class PT, bool STREAM = false>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) void k_batch(
     char* __restrict__ base, const KParams* __restrict__ ptab, const StepOff* __restrict__ otab,
     const unsigned* __restrict__ tmap, const unsigned* __restrict__ steps, int s) {
@@ -752,7 +775,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
   P.seed = steps[slot] + (unsigned)s;  // the grid's own step number
   const StepIO io = io_of(base, otab[2 * slot + par]);
   const int ntx = (P.nx + TX - 1) / TX;
-  step_tile<TX, TY, FIELDS, PT>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
+  step_tile<TX, TY, FIELDS, PT, false, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
 }
 
 // Initial state (no time-stepping yet): u = 0, p = 0, liquid fraction 1,
@@ -1002,6 +1025,9 @@ int launch_tile(const KParams& P, const State& S, int cur, bool fields_only, int
   const StepIO io = make_io(S, cur);
   if (fields_only)
     hipLaunchKernelGGL((k_step<TX, TY, true, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
+  else if (P.stream_stores)
+    hipLaunchKernelGGL((k_step<TX, TY, false, PT, true>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, band,
+                       xcd);
   else
     hipLaunchKernelGGL((k_step<TX, TY, false, PT>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
   return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -1103,47 +1129,50 @@ void tile_shape(int tile_variant, int* tx, int* ty) {
 
 namespace {
 template <int TX, int TY, class PT>
-int launch_batch_t(bool fields_only, char* base, const KParams* ptab, const StepOff* otab, const unsigned* tmap,
-                   const unsigned* steps, int nblocks, int s, hipStream_t st) {
+int launch_batch_t(bool fields_only, bool nt, char* base, const KParams* ptab, const StepOff* otab,
+                   const unsigned* tmap, const unsigned* steps, int nblocks, int s, hipStream_t st) {
   if (fields_only)
     hipLaunchKernelGGL((k_batch<TX, TY, true, PT>), dim3(nblocks), dim3(TX * TY), 0, st, base, ptab, otab, tmap,
                        steps, s);
+  else if (nt)
+    hipLaunchKernelGGL((k_batch<TX, TY, false, PT, true>), dim3(nblocks), dim3(TX * TY), 0, st, base, ptab, otab,
+                       tmap, steps, s);
   else
     hipLaunchKernelGGL((k_batch<TX, TY, false, PT>), dim3(nblocks), dim3(TX * TY), 0, st, base, ptab, otab, tmap,
                        steps, s);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 template <class PT>
-int launch_batch_v(int variant, bool fields_only, char* base, const KParams* ptab, const StepOff* otab,
+int launch_batch_v(int variant, bool fields_only, bool nt, char* base, const KParams* ptab, const StepOff* otab,
                    const unsigned* tmap, const unsigned* steps, int nblocks, int s, hipStream_t st) {
   switch (variant) {
     case 0:
-      return launch_batch_t<64, 4, PT>(fields_only, base, ptab, otab, tmap, steps, nblocks, s, st);
+      return launch_batch_t<64, 4, PT>(fields_only, nt, base, ptab, otab, tmap, steps, nblocks, s, st);
     case 1:
-      return launch_batch_t<32, 8, PT>(fields_only, base, ptab, otab, tmap, steps, nblocks, s, st);
+      return launch_batch_t<32, 8, PT>(fields_only, nt, base, ptab, otab, tmap, steps, nblocks, s, st);
     case 2:
-      return launch_batch_t<64, 8, PT>(fields_only, base, ptab, otab, tmap, steps, nblocks, s, st);
+      return launch_batch_t<64, 8, PT>(fields_only, nt, base, ptab, otab, tmap, steps, nblocks, s, st);
     case 3:
-      return launch_batch_t<64, 16, PT>(fields_only, base, ptab, otab, tmap, steps, nblocks, s, st);
+      return launch_batch_t<64, 16, PT>(fields_only, nt, base, ptab, otab, tmap, steps, nblocks, s, st);
     case 4:
-      return launch_batch_t<128, 4, PT>(fields_only, base, ptab, otab, tmap, steps, nblocks, s, st);
+      return launch_batch_t<128, 4, PT>(fields_only, nt, base, ptab, otab, tmap, steps, nblocks, s, st);
     default:
       return -1;
   }
 }
 }  // namespace
 
-int launch_batch(int storage, int tile_variant, bool fields_only, char* d_base, const KParams* d_ptab,
+int launch_batch(int storage, int tile_variant, bool fields_only, bool nt, char* d_base, const KParams* d_ptab,
                  const StepOff* d_otab, const unsigned* d_tmap, const unsigned* d_steps, int nblocks, int s,
                  hipStream_t st) {
   if (nblocks <= 0) return 0;
   if (storage == STORE_FP16)
-    return launch_batch_v<_Float16>(tile_variant, fields_only, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s,
+    return launch_batch_v<_Float16>(tile_variant, fields_only, nt, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s,
                                     st);
   if (storage == STORE_BF16)
-    return launch_batch_v<__bf16>(tile_variant, fields_only, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s,
+    return launch_batch_v<__bf16>(tile_variant, fields_only, nt, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s,
                                   st);
-  return launch_batch_v<float>(tile_variant, fields_only, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s, st);
+  return launch_batch_v<float>(tile_variant, fields_only, nt, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s, st);
 }
 
 int launch_batch_liquid(const char* d_base, const KParams* d_ptab, const StepOff* d_otab, const int* d_slots,

@@ -21,16 +21,17 @@ TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4,
                  "unfused64x8": 5}  # two-kernel step, kept to measure the gain from fusion
 XCD_MODES = (0, 1, 2)  # row-major tiles; one row-major band per XCD; one column band per XCD
 TILE_NAMES = {v: k for k, v in TILE_VARIANTS.items()}
-STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}  # LBM_STORE_FP32 / _FP16_SHIFT / _BF16_SHIFT
+STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
+STORE_MODES = {"auto": 0, "cached": 1, "streaming": 2}  # lbm_set_store_mode  # LBM_STORE_FP32 / _FP16_SHIFT / _BF16_SHIFT
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 
 EXPORTED = [
     "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_diag",
     "lbm_pops", "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_step_count", "lbm_sync",
-    "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_set_launch", "lbm_autotune",
+    "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_set_launch", "lbm_set_store_mode", "lbm_autotune",
     "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_configure", "lbm_batch_set_launch",
-    "lbm_batch_autotune", "lbm_batch_step", "lbm_batch_results", "lbm_batch_fields",
+    "lbm_batch_autotune", "lbm_batch_set_store_mode", "lbm_batch_step", "lbm_batch_results", "lbm_batch_fields",
     "lbm_batch_last_error", "lbm_batch_destroy", "lbm_shape_of",
     "lbm_mlp_param_count", "lbm_mlp_create", "lbm_mlp_set_params", "lbm_mlp_get_params", "lbm_mlp_forward",
     "lbm_mlp_gradient", "lbm_mlp_train", "lbm_mlp_last_error", "lbm_mlp_destroy",
@@ -109,12 +110,14 @@ def load_library():
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = C.c_char_p
     L.lbm_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
+    L.lbm_set_store_mode.argtypes = [vp, C.c_int32]
     L.lbm_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.lbm_batch_workspace_bytes.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
     L.lbm_batch_init.argtypes = [C.POINTER(Params), C.c_int32, C.POINTER(dp), C.POINTER(dp), dp, C.c_int32, vp,
                                  C.c_size_t, vp, C.POINTER(vp)]
     L.lbm_batch_configure.argtypes = [vp, C.c_int32, C.c_int64, C.c_double, C.c_int32]
     L.lbm_batch_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
+    L.lbm_batch_set_store_mode.argtypes = [vp, C.c_int32]
     L.lbm_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.lbm_batch_step.argtypes = [vp, C.c_int64, C.c_int32]
     L.lbm_batch_results.argtypes = [vp, C.POINTER(DropResult)]
@@ -205,6 +208,11 @@ class Solver:
         """xcd_remap: workgroup -> tile order, 0 row-major, 1 one contiguous band
         of tiles per XCD, 2 one band of tile columns per XCD (lbm_set_launch)."""
         self._check(self.L.lbm_set_launch(self._h, TILE_VARIANTS[tile], int(xcd_remap)), "lbm_set_launch")
+
+    def set_store_mode(self, mode: str = "auto"):
+        """auto (streaming stores once the state exceeds the Infinity Cache),
+        cached or streaming (lbm_set_store_mode)."""
+        self._check(self.L.lbm_set_store_mode(self._h, STORE_MODES[mode]), "lbm_set_store_mode")
 
     def autotune(self, reps: int = 20):
         """Pick the fastest launch shape for this grid; returns (tile, xcd_remap)."""
@@ -351,6 +359,9 @@ class Batch:
 
     def set_launch(self, tile: str = "64x4", xcd_group: int = 1):
         self._check(self.L.lbm_batch_set_launch(self._h, TILE_VARIANTS[tile], int(xcd_group)), "lbm_batch_set_launch")
+
+    def set_store_mode(self, mode: str = "auto"):
+        self._check(self.L.lbm_batch_set_store_mode(self._h, STORE_MODES[mode]), "lbm_batch_set_store_mode")
 
     def autotune(self, reps: int = 10):
         v, x = C.c_int32(), C.c_int32()

@@ -159,3 +159,19 @@ def test_device_shape_equals_checker(kind):
     for k in ("height", "base_radius", "tip_angle_deg"):
         assert g[k] == pytest.approx(c[k], rel=1e-7, abs=1e-9)
     assert g["npts"] == c["npts"]
+
+
+def test_batch_streaming_stores_bitwise_equal_cached():
+    lbm = _lbm()
+    drops = small_sweep(4, seed=19, storage=1)
+    fields = []
+    for mode in ("cached", "streaming"):
+        print(f"batch store mode {mode}", flush=True)
+        b = make_batch(lbm, drops)
+        b.configure(sample_every=40, use_graph=True)
+        b.set_store_mode(mode)
+        b.step(120)
+        fields.append([b.fields(i, ("phi", "T", "ux", "p")) for i in range(len(drops))])
+    for fa, fb in zip(*fields):
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), k

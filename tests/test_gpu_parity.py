@@ -357,3 +357,30 @@ def test_maximum_grid_size_flat_layer(oracle_mod):
     import torch
 
     torch.cuda.empty_cache()  # hand the 17 GB workspace back before the next test
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_streaming_and_cached_stores_are_bitwise_identical(storage):
+    """lbm_set_store_mode changes only the cache policy of the step's stores:
+    the checkpointed state after 60 steps is the same byte for byte."""
+    lbm = _gpu()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    p = dict(p, storage=lbm.STORAGE[storage])
+    blobs = {}
+    for mode in ("cached", "streaming", "auto"):
+        print(f"storage={storage} store mode {mode}", flush=True)
+        g = lbm.Solver(p, phi0, T0)
+        g.set_launch("64x8", 2)
+        g.set_store_mode(mode)
+        g.step(60)
+        blobs[mode] = g.save()
+    assert blobs["cached"] == blobs["streaming"] == blobs["auto"]
+
+
+def test_store_mode_is_validated():
+    lbm = _gpu()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    g = lbm.Solver(p, phi0, T0)
+    with pytest.raises(lbm.LbmError) as e:
+        g._check(g.L.lbm_set_store_mode(g._h, 3), "lbm_set_store_mode")
+    assert e.value.code == lbm.LBM_EINVAL
