@@ -236,7 +236,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the y-slab multi-GPU decomposition is described in DESIGN.md but not built", file=sys.stderr)
+              "sharding a grid into y-slabs, or a sweep by droplets, across GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
