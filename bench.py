@@ -25,12 +25,14 @@ if ROOT not in sys.path:
 
 # algorithmic bytes per node update: 27 populations and 5 FP32 history
 # values, each read and written once
+BYTES_PER_NODE = {"fp32": 27 * 8 + 40, "fp16": 27 * 4 + 40, "bf16": 27 * 4 + 40}
 # Unfused two-kernel step: the macro pass reads g, h (18 populations) and
 # f_s^H and writes phi, rho, f_s^H; the collide pass reads all populations,
 # the history fields and those three planes, and writes what the fused step
-# writes: 256 + 18 pop reads + 4 B + 3 x 4 B written and read back.
-UNFUSED_BYTES_PER_NODE = {"fp32": 256 + 18 * 4 + 4 + 24, "fp16": 148 + 18 * 2 + 4 + 24, "bf16": 148 + 18 * 2 + 4 + 24}
-BYTES_PER_NODE = {"fp32": 27 * 8 + 40, "fp16": 27 * 4 + 40, "bf16": 27 * 4 + 40}
+# writes: the fused figure + 18 population reads + 4 B + 3 x 4 B written and
+# read back.
+UNFUSED_BYTES_PER_NODE = {st: BYTES_PER_NODE[st] + 18 * (4 if st == "fp32" else 2) + 4 + 24
+                          for st in ("fp32", "fp16", "bf16")}
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS (φ+flow+T lattices), % HBM peak; batched sweep droplets/s vs plain"
 
