@@ -176,14 +176,15 @@ def surrogate_bench(sweep):
     sur.fit(tr)
     ev = S.evaluate(sur, te)
     out = {"ensemble": 8, "train_droplets": int(len(tr["R"])), "train_seconds": round(sur.train_seconds, 2)}
-    out.update({k: (round(v, 5) if isinstance(v, float) else v) for k, v in ev.items()})
+    out.update({k: (round(v, 5) if v == v else None) if isinstance(v, float) else v for k, v in ev.items()})
     out["droplets_per_s"] = round(ev["n"] / ev["inference_seconds"], 1)
     out["fallback_rel"] = sur.fallback_rel
     # the same network with the 2 % fallback threshold
     sur.fallback_rel = 0.02
     ev2 = S.evaluate(sur, te)
-    out["at_2pct"] = {k: round(ev2[k], 5) for k in ("fallback_fraction", "with_fallback_t_star_rel_err_median",
-                                                    "with_fallback_t_star_rel_err_p90", "accepted_t_star_rel_err_max")}
+    out["at_2pct"] = {k: (round(ev2[k], 5) if ev2[k] == ev2[k] else None)  # NaN (nothing accepted) -> null
+                      for k in ("fallback_fraction", "with_fallback_t_star_rel_err_median",
+                                "with_fallback_t_star_rel_err_p90", "accepted_t_star_rel_err_max")}
     if sweep and sweep.get("droplets_per_s"):
         out["speedup_vs_batched_solver"] = round(out["droplets_per_s"] / sweep["droplets_per_s"], 1)
     return out
