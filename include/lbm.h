@@ -107,7 +107,10 @@ int lbm_step(lbm_ctx* c, int32_t nsteps);
 int lbm_fields(lbm_ctx* c, uint32_t field_mask, double* const* host_out);
 
 /* Same fields as FP32 into device buffers (nx*ny floats each), enqueued on
- * the context's stream; no synchronisation. */
+ * the context's stream; no synchronisation.  H is given relative to
+ * H_ref = cp_ref*T_melt + latent, as the step keeps it (lbm_fields adds H_ref
+ * back in FP64; in FP32 the sum would lose the resolution of the relative
+ * value). */
 int lbm_fields_device(lbm_ctx* c, uint32_t field_mask, float* const* d_out);
 
 /* FP64 sums over the grid: sum phi, sum clamp(phi), solid and liquid

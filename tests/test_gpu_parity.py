@@ -384,3 +384,21 @@ def test_store_mode_is_validated():
     with pytest.raises(lbm.LbmError) as e:
         g._check(g.L.lbm_set_store_mode(g._h, 3), "lbm_set_store_mode")
     assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_device_fields_equal_host_fields():
+    """lbm_fields_device writes the same FP32 planes that lbm_fields widens to
+    FP64; H on the device is relative to H_ref = cp_ref T_m + L."""
+    lbm = _gpu()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    g = lbm.Solver(p, phi0, T0)
+    g.step(50)
+    names = ("phi", "T", "ux", "uy", "p", "fs", "fl", "rho", "H", "mdot")
+    fh = g.fields(names)
+    fd = {k: v.cpu().numpy() for k, v in g.fields_device(names).items()}
+    href = p["cp_ref"] * p["T_melt"] + p["latent"]
+    for k in names:
+        if k == "H":
+            assert np.array_equal(fd[k].astype(np.float64) + href, fh[k]), k
+        else:
+            assert np.array_equal(fd[k].astype(np.float64), fh[k]), k
