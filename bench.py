@@ -327,6 +327,23 @@ def main():
             "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("probe4096", args.storage, ptile, pxcd),
         }
+        # practical bandwidth beside the nominal peak: a 2 GiB device copy
+        # (read + write) and the step's measured traffic per second
+        cn = (2 << 30) // 4
+        ca = torch.ones(cn, dtype=torch.float32, device="cuda")
+        cb = torch.empty_like(ca)
+        cb.copy_(ca)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(10):
+            cb.copy_(ca)
+        c1.record()
+        torch.cuda.synchronize()
+        out["hbm_probe"]["plain_copy_GBps"] = round(2 * cn * 4 * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9, 1)
+        if out["hbm_probe"]["traffic"]:
+            out["hbm_probe"]["traffic_GBps"] = round(out["hbm_probe"]["traffic"] / pl / 1e9, 1)
+        del ca, cb
+        torch.cuda.empty_cache()
         # the unfused two-kernel step on the same grid: what fusion saves
         ps.set_launch("unfused64x8", pxcd)
         usecs, _ = time_steps(ps, args.probe_steps, 10)
