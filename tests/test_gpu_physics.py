@@ -108,3 +108,34 @@ def test_hou_setup_against_oracle(oracle_mod):
     e = errs(fg, fo)
     print(f"hou400/300: gpu {e}, envelope {env}", flush=True)
     assert np.all(np.asarray(e) <= 2.0 * np.maximum(env, [1e-5, 1e-5, 1e-4]))
+
+
+def test_sessile512_freezes_with_the_area_expansion_of_its_density_ratio():
+    """The 512x256 droplet (R = 80, theta = 90, rho_s/rho_l = 0.9, Ste 0.1,
+    Bond 0.1) run to full solidification.  Mass conservation with the density
+    change fixes the final condensed area: rho_l A_0 = rho_s A_f, so
+    sum(clamp(phi)) grows by 1/gamma = 1.111 (the mass source of Eq. (19)
+    is what makes it grow).  The frozen drop ends taller than it started and
+    with a tip; its shape is reported."""
+    lbm = _lbm()
+    p, phi0, T0, meta = W.workload("sessile512", seed=0)
+    gamma = p["rho_s"] / p["rho_l"]
+    s = lbm.Solver(p, phi0, T0)
+    s.autotune(reps=5)
+    d0 = s.diag()
+    h_init = lbm.shape_of(phi0.reshape(p["ny"], p["nx"]))["height"]
+    while s.step_count < 1_000_000:
+        s.step(5000)
+        d = s.diag()
+        assert d["rc"] == 0
+        if d["sum_liquid"] <= 0.01 * d0["sum_liquid"]:
+            break
+    shape = lbm.shape_of(s.fields(("phi",))["phi"])
+    ratio = d["sum_phic"] / d0["sum_phic"]
+    print(f"frozen after {s.step_count} steps: area ratio {ratio:.4f} (1/gamma {1 / gamma:.4f}), "
+          f"height {h_init:.1f} -> {shape['height']:.1f} (H_f/H_0 {shape['height'] / h_init:.3f}), "
+          f"base radius {shape['base_radius']:.1f}, tip angle {shape['tip_angle_deg']:.1f} deg", flush=True)
+    assert d["sum_liquid"] <= 0.01 * d0["sum_liquid"]
+    assert abs(ratio - 1.0 / gamma) < 0.02 / gamma
+    assert shape["height"] > h_init
+    assert 90.0 < shape["tip_angle_deg"] < 180.0
