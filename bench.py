@@ -190,6 +190,37 @@ def surrogate_bench(sweep):
     return out
 
 
+def to_frozen(lbm, params, phi0, T0, tile, xcd):
+    """The bench's droplet from its initial state until 1 % of its liquid is
+    left (diagnostics every 5000 steps): wall time, steps, and the frozen
+    shape."""
+    import torch
+
+    solver = lbm.Solver(params, phi0, T0)
+    solver.set_launch(tile, xcd)
+    d0 = solver.diag()
+    h0 = lbm.shape_of(phi0.reshape(params["ny"], params["nx"]))["height"]
+    start = solver.step_count
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while solver.step_count - start < 1_000_000:
+        solver.step(5000)
+        d = solver.diag()
+        if d["sum_liquid"] <= 0.01 * d0["sum_liquid"]:
+            break
+    secs = time.perf_counter() - t0
+    shape = lbm.shape_of(solver.fields(("phi",))["phi"])
+    note(f"droplet frozen after {solver.step_count} steps in {secs:.1f} s")
+    return {"steps": int(solver.step_count), "seconds": round(secs, 2),
+            "frozen": bool(d["sum_liquid"] <= 0.01 * d0["sum_liquid"]),
+            "area_ratio": round(d["sum_phic"] / d0["sum_phic"], 4),
+            "rho_l_over_rho_s": round(params["rho_l"] / params["rho_s"], 4),
+            "height_ratio": round(shape["height"] / h0, 4), "base_radius": round(shape["base_radius"], 2),
+            "aspect_ratio": round(shape["height"] / shape["base_radius"], 4),
+            "tip_angle_deg": round(shape["tip_angle_deg"], 1),
+            "note": "from the initial state, launch as timed above; diagnostics every 5000 steps inside the wall time"}
+
+
 def oracle_rate(oracle, params, phi0, T0, budget_s: float, threads: int):
     """MLUPS of the FP64 oracle over `budget_s` seconds of steps from the
     initial state, and the number of steps taken."""
@@ -238,6 +269,8 @@ def main():
     ap.add_argument("--sweep-droplets", type=int, default=256, help="droplets in the batched sweep (0: skip)")
     ap.add_argument("--sweep-plain", type=int, default=16, help="droplets of the sweep re-run one at a time in FP32")
     ap.add_argument("--sweep-time-limit", type=float, default=240.0)
+    ap.add_argument("--no-to-frozen", dest="to_frozen", action="store_false",
+                    help="skip running the 512x256 droplet to full solidification")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
                     help="skip training and scoring the surrogate network")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -309,6 +342,8 @@ def main():
         "wall_s": round(wall, 3),
     }
     del solver
+    if args.to_frozen and args.workload == "sessile512" and args.storage == "fp32":
+        out["to_frozen"] = to_frozen(lbm, params, phi0, T0, tile, xcd)
     torch.cuda.empty_cache()
     note(f"{args.workload}: {out['value']} MLUPS ({tile}, order {xcd})")
     if args.probe_steps > 0:
