@@ -166,12 +166,12 @@ def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float):
 
 
 def surrogate_bench(sweep):
-    """The learned surrogate: trained on the stored 4096-droplet sweep,
+    """The learned surrogate: trained on the stored sweeps (sweep_train*.npz),
     scored on the 512 held-out droplets against the solver's values."""
     from paper_2403_16122_amd import surrogate as S
 
     data = os.path.join(ROOT, "paper_2403_16122_amd", "data")
-    tr, te = S.load(os.path.join(data, "sweep_train.npz")), S.load(os.path.join(data, "sweep_test.npz"))
+    tr, te = S.load_training(data), S.load(os.path.join(data, "sweep_test.npz"))
     sur = S.Surrogate(ensemble=8, seed=0, fallback_rel=0.05)
     sur.fit(tr)
     ev = S.evaluate(sur, te)

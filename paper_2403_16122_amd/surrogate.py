@@ -11,6 +11,7 @@ relative errors, is the predicted error of the mean: where it exceeds
 """
 from __future__ import annotations
 
+import os
 import time
 from dataclasses import dataclass, field
 from typing import Dict, Optional
@@ -131,6 +132,18 @@ def evaluate(sur: Surrogate, test: Dict[str, np.ndarray]) -> Dict[str, float]:
 def load(path: str) -> Dict[str, np.ndarray]:
     with np.load(path) as z:
         return {k: z[k] for k in z.files}
+
+
+def load_training(data_dir: str) -> Dict[str, np.ndarray]:
+    """Every ``sweep_train*.npz`` in ``data_dir`` (one file per generator
+    seed), concatenated droplet by droplet."""
+    import glob
+
+    parts = [load(p) for p in sorted(glob.glob(os.path.join(data_dir, "sweep_train*.npz")))]
+    if not parts:
+        raise FileNotFoundError(f"no sweep_train*.npz in {data_dir}")
+    keys = [k for k in parts[0] if np.ndim(parts[0][k]) == 1]
+    return {k: np.concatenate([p[k] for p in parts]) for k in keys}
 
 
 def predict_with_fallback(sur: Surrogate, drops, every: int = 200, max_steps: int = 3_000_000):

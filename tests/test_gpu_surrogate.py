@@ -32,7 +32,7 @@ def _mods():
 @pytest.fixture(scope="module")
 def fitted():
     S = _mods()
-    tr = S.load(os.path.join(DATA, "sweep_train.npz"))
+    tr = S.load_training(DATA)
     te = S.load(os.path.join(DATA, "sweep_test.npz"))
     sur = S.Surrogate(ensemble=8, seed=0, fallback_rel=0.05)
     sur.fit(tr)

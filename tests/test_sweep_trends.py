@@ -1,6 +1,7 @@
 """The paper's qualitative results of the parametric study (Sec. 4.2.2) in
 the sweep data the batched GPU solver wrote (paper_2403_16122_amd/data,
-4096 droplets, FP16 storage; each droplet's initial cap is regenerated here
+8192 droplets from two generator seeds, FP16 storage; each droplet's
+initial cap is regenerated here
 from its seed).  These are physics checks of the solver's output, not
 parity: the freezing time grows with the droplet volume and the contact
 angle, the volume change on freezing is vertical (the contact line stays,
@@ -13,14 +14,14 @@ import pytest
 
 from paper_2403_16122_amd import workloads as W
 
-DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2403_16122_amd", "data",
-                    "sweep_train.npz")
+DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2403_16122_amd", "data")
 
 
 @pytest.fixture(scope="module")
 def sweep():
-    with np.load(DATA) as z:
-        d = {k: z[k] for k in z.files if z[k].ndim == 1}  # per-droplet arrays (the file also holds scalars)
+    from paper_2403_16122_amd.surrogate import load_training
+
+    d = load_training(DATA)
     keep = d["frozen"] & np.isfinite(d["t_star"])
     d = {k: v[keep] for k, v in d.items()}
     rc = np.array([W.cap_radius(r, t) for r, t in zip(d["R"], d["theta"])])
