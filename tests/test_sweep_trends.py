@@ -2,11 +2,11 @@
 the sweep data the batched GPU solver wrote (paper_2403_16122_amd/data,
 16384 droplets from four generator seeds, FP16 storage; each droplet's
 initial cap is regenerated here from its seed).  These are physics checks
-of the solver's output, not
-parity: the freezing time grows with the droplet volume and the contact
-angle, the volume change on freezing is vertical (the contact line stays,
-the height changes by about rho_l/rho_s), and gamma < 1 ends in a conical
-tip while gamma > 1 ends flatter."""
+of the solver's output, not parity: the freezing time grows with the
+droplet volume and the contact angle, the volume change on freezing is
+vertical (the contact line stays, the height changes by about
+rho_l/rho_s), and gamma < 1 ends in a conical tip while gamma > 1 ends
+flatter."""
 import os
 
 import numpy as np
