@@ -1,13 +1,19 @@
 """Physics pins of the oracle against closed forms (no GPU).
 
+- Pure conduction from a Dirichlet wall into a liquid above T_m (no phase
+  change): T = T_w + (T_0 - T_w) erf(z / 2 sqrt(alpha t)), z the distance
+  from the wall at y = -1/2 (textbook closed form; pins alpha = k / C_p of
+  the enthalpy LBE and the anti-bounce-back wall).
 - One-phase Neumann solution of the Stefan problem (textbook closed form;
   the paper's Sec. 4.1 validates its enthalpy LBE on a Stefan problem).
 - Final frozen height H_f = (rho_l/rho_s) H_0 of a liquid layer under gas
   (Eq. (44)) and the intermediate height H_0 + (1 - gamma) s(t) that mass
   conservation implies while the front is at s(t).
-- Laplace's law for a static drop (surface tension Eq. (11)-(13)).
+- Laplace's law for a static drop (surface tension Eq. (11)-(13)), exact
+  to 0.04 % with the interface resolved by 8 spacings.
 - Equilibrium contact angle of a sessile drop (wetting condition
-  Eq. (39)-(41)).
+  Eq. (39)-(41)) at 60, 90 and 120 deg, and at 150 deg in the limit of
+  small W/R.
 - Stationarity of the flat tanh layer (Eq. (43)) and the fluid-solid force
   (Sec. 3.3) bringing a fully solid node to rest.
 
@@ -26,6 +32,25 @@ from paper_2403_16122_amd import workloads as W
 
 def neumann_lambda(ste):
     return brentq(lambda l: l * math.exp(l * l) * math.erf(l) - ste / math.sqrt(math.pi), 1e-8, 5.0)
+
+
+@pytest.mark.parametrize("k", [0.1, 0.05])
+def test_conduction_from_dirichlet_wall(oracle_mod, k):
+    nx, ny, Tw, T0 = 4, 96, 1.5, 2.0  # all liquid, above T_m = 1 throughout
+    p = W.default_params(nx, ny, T_bottom=Tw, rho_s=1.0, k_l=k, k_g=k, k_s=k)
+    s = oracle_mod.OracleSolver(p, np.ones(nx * ny), np.full(nx * ny, T0), threads=1)
+    z = np.arange(ny) + 0.5  # node y sits y + 1/2 above the wall
+    errs = []
+    for t in (100, 400, 1600):
+        s.step(t - s.step_count)
+        T = s.fields(["T"])["T"]
+        exact = Tw + (T0 - Tw) * np.array([math.erf(v / (2.0 * math.sqrt(k * t))) for v in z])
+        assert np.ptp(T, axis=1).max() < 1e-13  # one-dimensional
+        errs.append(np.abs(T[:, 0] - exact).max() / (T0 - Tw))
+    # the initial jump at the wall decays like 1/t (measured 4e-3, 1e-3,
+    # 2.5e-4 of T_0 - T_w at k = 0.1); a 5 % error in alpha or a wall half a
+    # spacing off moves the profile by >= 1.2e-2
+    assert errs[-1] < 1e-3 and errs[0] > errs[1] > errs[2], errs
 
 
 @pytest.mark.parametrize("ste,k", [(0.1, 0.1), (0.2, 0.15)])
@@ -73,30 +98,36 @@ def test_layer_final_height_and_mass(oracle_mod, gamma):
     assert mids and max(abs(a - b) for a, b in mids) < 0.3
 
 
-def _laplace_ratio(oracle_mod, n, R, steps):
-    p = W.default_params(n, n, T_bottom=2.0, rho_s=1.0)
-    phi0 = W.free_droplet(n, n, R, p["W"])
-    s = oracle_mod.OracleSolver(p, phi0, np.full(n * n, 2.0))
+def _laplace_ratio(oracle_mod, n, R, width, steps, every=50):
+    """Time-averaged dp R / sigma of a free droplet over the second half of
+    the run (the droplet breathes slowly; the average over many samples is
+    stable to ~1e-3)."""
+    p = W.default_params(n, n, T_bottom=2.0, rho_s=1.0, W=width)
+    s = oracle_mod.OracleSolver(p, W.free_droplet(n, n, R, p["W"]), np.full(n * n, 2.0))
+    s.step(steps // 2)
     vals = []
     while s.step_count < steps:
-        s.step(250)
-        if s.step_count > steps // 2:
-            f = s.fields(["phi", "p"])
-            Reff = math.sqrt(np.clip(f["phi"], 0, 1).sum() / math.pi)
-            dp = f["p"][f["phi"] > 0.99].mean() - f["p"][f["phi"] < 0.01].mean()
-            vals.append(dp * Reff / p["sigma"])
+        s.step(every)
+        f = s.fields(["phi", "p"])
+        Reff = math.sqrt(np.clip(f["phi"], 0, 1).sum() / math.pi)
+        dp = f["p"][f["phi"] > 0.99].mean() - f["p"][f["phi"] < 0.01].mean()
+        vals.append(dp * Reff / p["sigma"])
     return float(np.mean(vals))
 
 
 @pytest.mark.slow
 def test_laplace_law(oracle_mod):
-    r12 = _laplace_ratio(oracle_mod, 64, 12.0, 8000)
-    r16 = _laplace_ratio(oracle_mod, 80, 16.0, 8000)
-    # dp = sigma / R up to the diffuse-interface bias at W/R ~ 1/3-1/4
-    # (measured about -5%); a wrong beta/kappa changes sigma by >= 40%
-    for r in (r12, r16):
-        assert 0.88 < r < 1.05, (r12, r16)
-    assert abs(r12 - r16) < 0.05
+    """dp = sigma / R (2-D).  With the interface resolved by 8 lattice
+    spacings the law holds to 0.04 % at R = 24 (measured 1.0004); at the
+    default W = 4 the discrete interface carries 6-7 % less tension
+    (measured 0.934 at R = 24, 0.940 at R = 16, 0.969 at W = 6), a lattice
+    effect in dx / W, not in W / R.  A wrong beta or kappa in Eq. (12)-(13)
+    changes sigma by tens of percent."""
+    r8 = _laplace_ratio(oracle_mod, 96, 24.0, 8.0, 16000)
+    r4 = _laplace_ratio(oracle_mod, 96, 24.0, 4.0, 16000)
+    print(f"dp R / sigma at R = 24: W = 8 {r8:.4f}, W = 4 {r4:.4f}")
+    assert abs(r8 - 1.0) < 0.02, r8
+    assert 0.90 < r4 < 0.97 and r4 < r8, (r4, r8)
 
 
 def _contour_points(phi, level=0.5):
@@ -122,19 +153,39 @@ def _fit_circle(pts):
     return xc, yc, math.sqrt(c + xc * xc + yc * yc)
 
 
-@pytest.mark.slow
-@pytest.mark.parametrize("theta", [60.0, 120.0])
-def test_equilibrium_contact_angle(oracle_mod, theta):
-    nx, ny = 128, 64
+def _relaxed_angle(oracle_mod, theta, R, steps):
+    nx, ny = int(8 * R), int(4 * R)
     p = W.default_params(nx, ny, T_bottom=2.0, rho_s=1.0, theta_bottom_deg=theta)
-    phi0 = W.sessile_droplet(nx, ny, 16.0, 90.0, p["W"])  # starts as a semicircle
+    phi0 = W.sessile_droplet(nx, ny, R, 90.0, p["W"])  # starts as a semicircle
     s = oracle_mod.OracleSolver(p, phi0, np.full(nx * ny, 2.0))
-    s.step(10000)
+    s.step(steps)
     pts = _contour_points(s.fields(["phi"])["phi"])
     pts = pts[pts[:, 1] > 2 * p["W"]]
     xc, yc, Rc = _fit_circle(pts)
-    ang = math.degrees(math.acos(np.clip((-0.5 - yc) / Rc, -1, 1)))
+    return math.degrees(math.acos(np.clip((-0.5 - yc) / Rc, -1, 1)))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("theta", [60.0, 90.0, 120.0])
+def test_equilibrium_contact_angle(oracle_mod, theta):
+    ang = _relaxed_angle(oracle_mod, theta, 16.0, 10000)
     assert abs(ang - theta) < 3.0, ang
+
+
+@pytest.mark.slow
+def test_large_contact_angle_converges_with_resolution(oracle_mod):
+    """At 150 deg the cap meets the wall over a few interface widths and the
+    diffuse interface overshoots the angle by an amount first order in W/R
+    (measured 162.3 deg at R = 16, 158.3 at R = 24, 156.4 at R = 32, i.e.
+    (theta - 150) R ~ 195).  The two smaller droplets, extrapolated in 1/R,
+    land on the prescribed angle; a wrong sign or factor in the wetting
+    formula (Eq. (39)-(41)) would not."""
+    a16 = _relaxed_angle(oracle_mod, 150.0, 16.0, 8000)
+    a24 = _relaxed_angle(oracle_mod, 150.0, 24.0, 12000)
+    limit = a24 - (a16 - a24) * 16.0 / (24.0 - 16.0)  # theta(R) = theta_inf + c / R
+    print(f"150 deg: R=16 {a16:.2f}, R=24 {a24:.2f}, extrapolated {limit:.2f}")
+    assert 150.0 < a24 < a16
+    assert abs(limit - 150.0) < 1.0, (a16, a24, limit)
 
 
 def test_flat_layer_stationary(oracle_mod):
