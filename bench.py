@@ -277,7 +277,7 @@ def main():
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
               "sharding a grid into y-slabs, or a sweep by droplets, across GPUs is not built", file=sys.stderr)
         sys.exit(2)
 

@@ -57,6 +57,31 @@ def test_strerror_names_every_code():
         assert L.lbm_strerror(code).decode() != "unknown error"
 
 
+def test_batch_workspace_validation():
+    """The batch's sizing call validates every droplet on the host: an empty
+    batch, slot counts outside 1..65535, mixed storage formats and one
+    invalid droplet are refused; the workspace grows with the number of
+    droplets resident at once (slots), not with the queue behind them."""
+    small = [W.default_params(24 + 4 * i, 18 + 2 * i) for i in range(6)]
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.batch_workspace_bytes([], 4)
+    assert e.value.code == lbm.LBM_EINVAL
+    for slots in (0, 65536):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.batch_workspace_bytes(small, slots)
+        assert e.value.code == lbm.LBM_EINVAL
+    for bad in (dict(storage=lbm.STORAGE["fp16"]), dict(nx=2), dict(M=0.0)):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.batch_workspace_bytes(small[:3] + [dict(small[3], **bad)] + small[4:], 6)
+        assert e.value.code == lbm.LBM_EINVAL, bad
+    full = lbm.batch_workspace_bytes(small, 6)
+    two = lbm.batch_workspace_bytes(small, 2)
+    assert 0 < two < full
+    assert lbm.batch_workspace_bytes(small, 6) == lbm.batch_workspace_bytes(small, 600)  # slots capped at n
+    one = lbm.batch_workspace_bytes(small[:1], 1)
+    assert one < two
+
+
 def test_batch_refuses_a_wide_temperature_span_before_any_device_call():
     """16-bit storage keeps T - T_m per node as an FP16 reference; a batch
     whose droplet exceeds that span is refused by lbm_batch_init itself,

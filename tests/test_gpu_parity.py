@@ -306,6 +306,27 @@ def test_nonfinite_is_reported():
     assert d["rc"] == lbm.LBM_ENONFINITE and d["nonfinite"] == 1
 
 
+def test_zero_steps_is_a_no_op_and_negative_counts_are_refused():
+    lbm = _gpu()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    g = lbm.Solver(p, phi0, T0)
+    g.step(7)
+    before = g.fields(FIELDS)
+    g.step(0)
+    assert g.step_count == 7
+    after = g.fields(FIELDS)
+    assert all(np.array_equal(before[k], after[k]) for k in FIELDS)
+    with pytest.raises(lbm.LbmError) as e:
+        g.step(-1)
+    assert e.value.code == lbm.LBM_EINVAL and g.step_count == 7
+    drops = W.sweep_droplets(2, seed=5)
+    b = lbm.Batch([d["params"] for d in drops], [d["phi0"] for d in drops], [d["T0"] for d in drops],
+                  radii=[d["R"] for d in drops], slots=2)
+    with pytest.raises(lbm.LbmError) as e:
+        b.step(-5)
+    assert e.value.code == lbm.LBM_EINVAL
+
+
 def test_invalid_parameters_rejected_at_init():
     lbm = _gpu()
     p = W.default_params(16, 8, M=0.0)
