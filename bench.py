@@ -190,6 +190,32 @@ def surrogate_bench(sweep):
     return out
 
 
+def host_io(lbm, params, phi0, T0, N, steps, step_secs):
+    """The boundary takes the initial fields from host memory and returns
+    fields to host memory: time lbm_init from host arrays (workspace, copy
+    in, population set-up) and one read-back of all ten fields, and the rate
+    of a job that does both around the timed steps."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = lbm.Solver(params, phi0, T0)
+    s.sync()
+    t_init = time.perf_counter() - t0
+    s.step(1)
+    s.sync()
+    t0 = time.perf_counter()
+    s.fields(tuple(lbm.FIELD_BITS))
+    t_fields = time.perf_counter() - t0
+    del s
+    torch.cuda.empty_cache()
+    job = t_init + step_secs + t_fields
+    return {"init_s": round(t_init, 4), "fields_all_s": round(t_fields, 4),
+            "host_bytes": int(N * 8 * (2 + len(lbm.FIELD_BITS))),
+            "job_MLUPS": round(N * steps / job / 1e6, 1),
+            "note": "init from host arrays + the timed steps + one read-back of every field, wall clock"}
+
+
 def to_frozen(lbm, params, phi0, T0, tile, xcd):
     """The bench's droplet from its initial state until 1 % of its liquid is
     left (diagnostics every 5000 steps): wall time, steps, and the frozen
@@ -342,6 +368,7 @@ def main():
         "wall_s": round(wall, 3),
     }
     del solver
+    out["host_io"] = host_io(lbm, params, phi0, T0, N, args.steps, secs)
     if args.to_frozen and args.workload == "sessile512" and args.storage == "fp32":
         out["to_frozen"] = to_frozen(lbm, params, phi0, T0, tile, xcd)
     torch.cuda.empty_cache()
