@@ -335,8 +335,11 @@ def main():
         print(f"bench.py: non-finite state after the timed steps ({d})", file=sys.stderr)
         sys.exit(3)
     mlups = N * args.steps / secs / 1e6
-    launch_s = secs / args.steps
-    achieved = bpn * N / launch_s / 1e9
+    # a two-step launch processes 2 N node-steps; achieved counts the
+    # algorithmic bytes of those node-steps over the launch's duration
+    spl = 2 if tile in lbm.TWO_STEP_VARIANTS else 1
+    launch_s = secs * spl / args.steps
+    achieved = bpn * N * spl / launch_s / 1e9
     traffic = measured_traffic(args.workload, args.storage, tile, xcd)
     out = {
         "metric": METRIC,
@@ -361,9 +364,13 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_step (fused collide + pull-stream)",
-            "bytes_per_launch": bpn * N,
-            "note": "working set fits the 256 MB Infinity Cache at this size; see hbm_probe",
+            "kernel": ("k_step2 (two fused collide + pull-stream steps per launch)" if spl == 2
+                       else "k_step (fused collide + pull-stream)"),
+            "steps_per_launch": spl,
+            "bytes_per_launch": bpn * N * spl,
+            "note": ("working set fits the 256 MB Infinity Cache at this size; see hbm_probe"
+                     + ("; bytes_per_launch counts 256 B per node-step for the launch's 2 N node-steps, while "
+                        "the launch itself reads and writes the state once" if spl == 2 else "")),
         },
         "wall_s": round(wall, 3),
     }

@@ -139,7 +139,13 @@ const char* lbm_last_error(void);
  * recomputed per tile.  5: the unfused two-kernel step on 64x8 tiles (a
  * macro pass writes phi, rho and f_s^H of every node, then the collide pass
  * reads its halo from there), bitwise equal to the fused step and kept to
- * measure what fusion saves; lbm_autotune does not consider it.
+ * measure what fusion saves; lbm_autotune does not consider it.  6, 7, 8
+ * (FP32 storage only, else LBM_EINVAL): two steps per launch on 64x8, 32x8,
+ * 32x16 tiles -- each workgroup runs the first step on its tile plus 3 columns and 2 rows
+ * of halo from global memory, keeps those results in LDS and runs the
+ * second step on the tile from there, so the state crosses HBM once per two
+ * steps at ~1.3-1.5x the arithmetic; lbm_step issues pairs and a single
+ * 64x8 step for an odd remainder; bitwise equal to single steps.
  * xcd_remap, the order in which the workgroups, dealt round-robin to the
  * 8 XCDs, take tiles: 0 row-major (the XCDs sweep the grid together); 1 one
  * contiguous row-major band of tiles per XCD; 2 one band of tile columns
@@ -155,9 +161,11 @@ int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap);
  * identical; anything else is LBM_EINVAL. */
 int lbm_set_store_mode(lbm_ctx* c, int32_t mode);
 
-/* Time every launch shape for `reps` steps and keep the fastest (written to
- * the optional out-pointers).  The state is not advanced: each timed launch
- * recomputes the next step from the same buffers.  Synchronises. */
+/* Time every launch shape for `reps` launches and keep the fastest per step
+ * (written to the optional out-pointers): tile variants 0-4, and under FP32
+ * storage the two-step variants 6-8 at half their time per launch.  The
+ * state is not advanced: each timed launch recomputes the next step(s) from
+ * the same buffers.  Synchronises. */
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_remap);
 
 /* ---- Batched sweep -----------------------------------------------------

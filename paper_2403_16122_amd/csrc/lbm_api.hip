@@ -332,12 +332,21 @@ int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_
 
 int lbm_step(lbm_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
-  for (int32_t s = 0; s < nsteps; ++s) {
+  for (int32_t s = 0; s < nsteps;) {
+    if (lbmk::is_two_step(c->tile_variant) && nsteps - s >= 2) {
+      if (lbmk::launch_step2(c->K, c->S, c->cur, c->tile_variant, c->xcd, c->stream))
+        return dev_error(hipGetLastError(), "two-step kernel launch");
+      c->cur ^= 1;
+      c->step += 2;
+      s += 2;
+      continue;
+    }
     c->K.seed = (unsigned)c->step;  // the step number seeds 16-bit stochastic rounding
     if (lbmk::launch_step(c->K, c->S, c->cur, false, c->tile_variant, c->xcd, c->stream))
       return dev_error(hipGetLastError(), "step kernel launch");
     c->cur ^= 1;
     c->step++;
+    ++s;
   }
   return LBM_OK;
 }
@@ -476,6 +485,7 @@ int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap) {
   if (!c || tile_variant < 0 || tile_variant >= lbmk::NTILE_VARIANTS || xcd_remap < 0 ||
       xcd_remap >= lbmk::NXCD_MODES)
     return LBM_EINVAL;
+  if (lbmk::is_two_step(tile_variant) && c->P.storage != LBM_STORE_FP32) return LBM_EINVAL;
   c->tile_variant = tile_variant;
   c->xcd = xcd_remap;
   return LBM_OK;
@@ -504,18 +514,24 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_r
   hipEvent_t e0 = ev.a, e1 = ev.b;
   float best = 1e30f;
   int bv = c->tile_variant, bx = c->xcd;
-  for (int v = 0; v < lbmk::NTUNED_VARIANTS; ++v) {
+  const int nv = c->P.storage == LBM_STORE_FP32 ? lbmk::NTILE_VARIANTS : lbmk::NTUNED_VARIANTS;
+  for (int v = 0; v < nv; ++v) {
+    const bool two = lbmk::is_two_step(v);
+    if (v >= lbmk::NTUNED_VARIANTS && !two) continue;  // the unfused reference step
     for (int x = 0; x < lbmk::NXCD_MODES; ++x) {
-      if (lbmk::launch_step(c->K, c->S, c->cur, false, v, x, c->stream))  // warm-up
-        return dev_error(hipGetLastError(), "autotune launch");
+      auto launch = [&]() {
+        return two ? lbmk::launch_step2(c->K, c->S, c->cur, v, x, c->stream)
+                   : lbmk::launch_step(c->K, c->S, c->cur, false, v, x, c->stream);
+      };
+      if (launch()) return dev_error(hipGetLastError(), "autotune launch");  // warm-up
       LBM_CK(hipEventRecord(e0, c->stream));
       for (int r = 0; r < reps; ++r)
-        if (lbmk::launch_step(c->K, c->S, c->cur, false, v, x, c->stream))
-          return dev_error(hipGetLastError(), "autotune launch");
+        if (launch()) return dev_error(hipGetLastError(), "autotune launch");
       LBM_CK(hipEventRecord(e1, c->stream));
       LBM_CK(hipEventSynchronize(e1));
       float ms = 0.0f;
       LBM_CK(hipEventElapsedTime(&ms, e0, e1));
+      if (two) ms *= 0.5f;  // two steps per launch: compare time per step
       if (ms < best) {
         best = ms;
         bv = v;

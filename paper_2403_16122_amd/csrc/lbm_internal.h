@@ -84,8 +84,13 @@ struct StepOff {
 };
 
 enum { NFIELD = 10 };
-enum { NTILE_VARIANTS = 6 };  // tiles 64x4, 32x8, 64x8, 64x16, 128x4; 5: unfused two-kernel 64x8
-enum { NTUNED_VARIANTS = 5 };  // the autotuner times the fused shapes only
+// tiles 64x4, 32x8, 64x8, 64x16, 128x4; 5: unfused two-kernel 64x8; 6, 7, 8:
+// two steps per launch on 64x8, 32x8, 32x16 tiles (FP32 storage)
+enum { NTILE_VARIANTS = 9, TWO_STEP_VARIANT = 6, NTWO_STEP_VARIANTS = 3 };
+inline bool is_two_step(int tile_variant) {
+  return tile_variant >= TWO_STEP_VARIANT && tile_variant < TWO_STEP_VARIANT + NTWO_STEP_VARIANTS;
+}
+enum { NTUNED_VARIANTS = 5 };  // single-step shapes the autotuner times (plus the two-step ones in FP32)
 enum { NXCD_MODES = 3 };      // workgroup -> tile orders (map_tile)
 enum { RED_NVAL = 8 };
 constexpr int RED_BLOCKS = 512;
@@ -99,6 +104,9 @@ int launch_init(const KParams& P, const IParams& I, const State& S, int cur, con
                 const double* d_T0, hipStream_t st);
 int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int tile_variant,
                 int xcd_remap, hipStream_t st);
+// Two steps n -> n+2 in one launch (FP32 storage only): reads buffer cur,
+// writes buffer cur^1, like one step.
+int launch_step2(const KParams& P, const State& S, int cur, int tile_variant, int xcd_remap, hipStream_t st);
 // The 9 populations of `lattice` as FP32 (shifted variables) into the first
 // nine field planes.
 int launch_expand(const KParams& P, const State& S, int cur, int lattice, hipStream_t st);

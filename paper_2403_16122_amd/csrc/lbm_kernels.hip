@@ -15,6 +15,7 @@
 #include "lbm_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace lbmk {
 namespace {
@@ -392,10 +393,15 @@ __device__ __forceinline__ float wetting_ghost(float a0m, float a0c, float a0p, 
 // Everything after the stencils for one node k: interface terms (Eq. (3),
 // (12), (13)), forces (Eq. (11)), flow macros (Eq. (34)-(36)) and the three
 // BGK collisions with their stores, or the output fields when FIELDS.
-template <bool FIELDS, class PT, bool STREAM = false>
+// LS > 0 (FP32 only): the node's 33 results go to LDS instead, plane j at
+// lo[j * LS] (populations 0-26 as in the global layout, then phi_ref,
+// (phi u)_x, (phi u)_y, f_s^H, p, S), for a second step in the same launch.
+enum { LDS_REF = 27, LDS_PHIUX = 28, LDS_PHIUY = 29, LDS_FSH = 30, LDS_P = 31, LDS_S = 32, LDS_NOUT = 33 };
+template <bool FIELDS, class PT, bool STREAM = false, int LS = 0>
 __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, const Macro& m,
                                             const float f[9], float phiux, float phiuy,
-                                            const Grads& d, unsigned k) {
+                                            const Grads& d, unsigned k, float* lo = nullptr) {
+  static_assert(LS == 0 || (!FIELDS && std::is_same<PT, float>::value), "LDS results: FP32 step only");
   const float phi = m.phi, rho = m.rho;
   const float om = (1.0f - m.r) - m.dl;  // 1 - phi without cancellation in either bulk
   // interface terms (Eq. (3), (12), (13))
@@ -410,9 +416,13 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
   const float muphi = -P.beta4 * phi * om * (phi - 0.5f) - P.kappa * d.lphi;
   const float smask = 1.0f - P.chi * m.fsol;
   const float T = P.T_melt + m.dT;
-  const float gcoef = rho - P.bq_coef * (T - P.bq_Tref);
-  const float Fx = smask * muphi * d.phx + gcoef * P.gx;
-  const float Fy = smask * muphi * d.phy + gcoef * P.gy;
+  // explicit FMAs: contraction here is otherwise left to the code
+  // generator, which may fuse either product with the sum depending on the
+  // surrounding kernel, and every launch variant must round alike
+  const float gcoef = __builtin_fmaf(-P.bq_coef, T - P.bq_Tref, rho);
+  const float smu = smask * muphi;
+  const float Fx = __builtin_fmaf(gcoef, P.gx, smu * d.phx);
+  const float Fy = __builtin_fmaf(gcoef, P.gy, smu * d.phy);
 
   // flow populations (Eq. (34)-(35)), loaded in phase 0
   const float mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
@@ -466,7 +476,11 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float feq = 3.0f * p * (wt(i) - (i == 0 ? 1.0f : 0.0f)) + rho * si;
       const float cF = cx * Ftx + cy * Fty;
       const float Fi = wt(i) * (Ssrc + 3.0f * (cx * Gx + cy * Gy) + 9.0f * cu * cF - 3.0f * uFt);
-      pop_st<PT, 1, STREAM>(Bf, i * pl + k, f[i] - (f[i] - feq) * itau + sf * Fi, P, rb ^ sr_pop(9 + i));
+      const float fn = f[i] - (f[i] - feq) * itau + sf * Fi;
+      if constexpr (LS > 0)
+        lo[(9 + i) * LS] = fn;
+      else
+        pop_st<PT, 1, STREAM>(Bf, i * pl + k, fn, P, rb ^ sr_pop(9 + i));
     }
   }
   // phase-field collision (Eq. (21), (24), (25), (37))
@@ -487,11 +501,21 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float gi = m.g[i] + wt(i) * dr;                 // g_i - w_i phi_ref
       const float geq = wt(i) * (dln + 3.0f * phi * cu);  // g_i^eq - w_i phi_ref
       const float Gi = wt(i) * (cx * ax + cy * ay + pm);
-      pop_st<PT, 0, STREAM>(B, i * pl + k, gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi, P, rb ^ sr_pop(i));
+      const float gn = gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi;
+      if constexpr (LS > 0)
+        lo[i * LS] = gn;
+      else
+        pop_st<PT, 0, STREAM>(B, i * pl + k, gn, P, rb ^ sr_pop(i));
     }
-    RefIO<PopIO<PT>::kNodeRef>::template store<STREAM>(io.ref_out, k, r_new, th_new);
-    st<STREAM>(io.phiu_out, k, pux);
-    st<STREAM>(io.phiu_out, pl + k, puy);
+    if constexpr (LS > 0) {
+      lo[LDS_REF * LS] = r_new;
+      lo[LDS_PHIUX * LS] = pux;
+      lo[LDS_PHIUY * LS] = puy;
+    } else {
+      RefIO<PopIO<PT>::kNodeRef>::template store<STREAM>(io.ref_out, k, r_new, th_new);
+      st<STREAM>(io.phiu_out, k, pux);
+      st<STREAM>(io.phiu_out, pl + k, puy);
+    }
   }
   // enthalpy collision (Eq. (27)-(28)) in the shifted variables
   constexpr bool NR = PopIO<PT>::kNodeRef;
@@ -510,7 +534,10 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float heq = wt(i) * (crd + cpT * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
       float hn = m.h[i] - (m.h[i] - heq) * itau;
       if (NR) hn += wt(i) * cmove;
-      pop_st<PT, 2, STREAM>(Bh, i * pl + k, hn, P, rb ^ sr_pop(18 + i));
+      if constexpr (LS > 0)
+        lo[(18 + i) * LS] = hn;
+      else
+        pop_st<PT, 2, STREAM>(Bh, i * pl + k, hn, P, rb ^ sr_pop(18 + i));
       hs += m.h[i];
     }
     // rest population: h0eq - h0 = sum_{i>0} h_i - cp_ref dT + w0 (cp_ref dT - 1.5 cp T u.u);
@@ -518,11 +545,20 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
     const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
     float h0 = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
     if (NR) h0 += W0 * cmove;
-    pop_st<PT, 2, STREAM>(Bh, k, h0, P, rb ^ sr_pop(18));
+    if constexpr (LS > 0)
+      lo[18 * LS] = h0;
+    else
+      pop_st<PT, 2, STREAM>(Bh, k, h0, P, rb ^ sr_pop(18));
   }
-  st<STREAM>(io.fsH_out, k, m.fsH);
-  st<STREAM>(io.p_out, k, p);
-  st<STREAM>(io.S_out, k, Ssrc);
+  if constexpr (LS > 0) {
+    lo[LDS_FSH * LS] = m.fsH;
+    lo[LDS_P * LS] = p;
+    lo[LDS_S * LS] = Ssrc;
+  } else {
+    st<STREAM>(io.fsH_out, k, m.fsH);
+    st<STREAM>(io.p_out, k, p);
+    st<STREAM>(io.S_out, k, Ssrc);
+  }
 }
 
 // Workgroup -> tile.  Workgroups are dispatched round-robin over the 8
@@ -702,6 +738,289 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
   const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
   if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
   step_tile<TX, TY, FIELDS, PT, false, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
+}
+
+// ---- two steps per launch (FP32) -----------------------------------------
+// The second step of a TX x TY tile reads first-step results on the tile
+// plus 3 columns and 2 rows on each side (its halo macros pull from one cell
+// further, and their reference phi one more).  The workgroup first runs the
+// step on that region E from global memory, keeping its results in LDS, then
+// runs the second step on the tile from LDS and writes it out: one read and
+// one write of the state per two steps, for ~1.3x the arithmetic (the
+// overlap of neighbouring regions is computed by both tiles).  Every node
+// goes through the same macro and update code as in k_step, so the results
+// are bitwise those of two single steps.
+
+// Pull-stream one lattice into E cell (ex, ey) of grid row y from
+// first-step results in LDS (plane j at eo[j * ES]), with pull9's wall rules.
+template <int LAT, int EX, int ES>
+__device__ __forceinline__ void pull9_lds(const float* __restrict__ eo, const KParams& P, int ex, int ey,
+                                          int y, float q[9]) {
+  const bool bot = (y == 0), top = (y == P.ny - 1);
+  const int e = ey * EX + ex;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cy = cyv(i), cx = cxv(i);
+    const bool wall = (cy > 0 && bot) || (cy < 0 && top);
+    const int idx = wall ? (LAT * 9 + opp(i)) * ES + e : (LAT * 9 + i) * ES + e - cy * EX - cx;
+    float v = eo[idx];
+    if (LAT == 2 && cy > 0) v = bot ? (P.hwall[i] - v) : v;
+    q[i] = v;
+  }
+}
+
+template <int EX, int ES>
+__device__ __forceinline__ void load_node_lds(const float* __restrict__ eo, const KParams& P, int ex, int ey,
+                                              int y, Macro& m) {
+  pull9_lds<0, EX, ES>(eo, P, ex, ey, y, m.g);
+  pull9_lds<2, EX, ES>(eo, P, ex, ey, y, m.h);
+  m.fprev = eo[LDS_FSH * ES + ey * EX + ex];
+}
+
+// Halo cell of a macro region LXR x LYR around an inner block of TXR x
+// TYR cells (two columns and one row on each side): lane q < 2 LXR + 4 TYR
+// takes the bottom row, the top row, then the side columns row by row.
+template <int LXR, int LYR, int TXR>
+__device__ __forceinline__ void ring_cell(int q, int& hr, int& hc) {
+  if (q < LXR) {
+    hr = 0;
+    hc = q;
+  } else if (q < 2 * LXR) {
+    hr = LYR - 1;
+    hc = q - LXR;
+  } else {
+    const int u = q - 2 * LXR;
+    hr = 1 + (u >> 2);
+    const int s = u & 3;
+    hc = s < 2 ? s : TXR + s;
+  }
+}
+
+// Wetting ghost rows (Eq. (39)-(41)) of a macro region of width LXR: the
+// row rb below grid row 0 and the row rt above grid row ny-1, where present.
+template <int LXR>
+__device__ __forceinline__ void ghost_rows(const KParams& P, float (*sphi)[LXR], float (*srho)[LXR],
+                                           const float (*sfsH)[LXR], bool gb, int rb, bool gt, int rt, int t,
+                                           int nt) {
+  for (int j = t; j < 2 * LXR; j += nt) {
+    const bool isb = j < LXR;
+    const int c = isb ? j : j - LXR;
+    if (c < 1 || c > LXR - 2) continue;
+    int r, r0, r1;
+    float tv;
+    if (isb) {
+      if (!gb) continue;
+      r = rb;
+      r0 = rb + 1;
+      r1 = rb + 2;
+      tv = P.tan_b;
+    } else {
+      if (!gt) continue;
+      r = rt;
+      r0 = rt - 1;
+      r1 = rt - 2;
+      tv = P.tan_t;
+    }
+    const float pg = wetting_ghost(sphi[r0][c - 1], sphi[r0][c], sphi[r0][c + 1], sphi[r1][c - 1],
+                                   sphi[r1][c + 1], tv);
+    const float pcg = clamp01(1.0f + pg);
+    sphi[r][c] = pg;
+    srho[r][c] = mix3(pcg * sfsH[r0][c], pcg, P.rho_s, P.rho_l, P.rho_g);
+  }
+}
+
+template <int LXR>
+__device__ __forceinline__ void tile_grads(const float (*sphi)[LXR], const float (*srho)[LXR],
+                                           const float (*sp)[LXR], const float (*sS)[LXR], int r, int c,
+                                           Grads& d) {
+#define LBM_GRAD(arr, ox, oy, lap)                                                                 \
+  stencil(arr[r][c], arr[r][c + 1], arr[r][c - 1], arr[r + 1][c], arr[r - 1][c], arr[r + 1][c + 1], \
+          arr[r + 1][c - 1], arr[r - 1][c - 1], arr[r - 1][c + 1], ox, oy, lap)
+  LBM_GRAD(sphi, d.phx, d.phy, &d.lphi);
+  LBM_GRAD(srho, d.rx, d.ry, nullptr);
+  LBM_GRAD(sp, d.px, d.py, nullptr);
+  LBM_GRAD(sS, d.Sx, d.Sy, nullptr);
+#undef LBM_GRAD
+}
+
+template <int TX, int TY, bool STREAM = false>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) void k_step2(
+    KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
+  constexpr int NT = TX * TY;
+  constexpr int EX = TX + 6, EY = TY + 4, ES = EX * EY;  // E: cell (ex, ey) <-> (x0 - 3 + ex, y0 - 2 + ey)
+  // first step: macro cells (c, r) <-> (x0 - 5 + c, y0 - 3 + r); reference tile one more cell around
+  constexpr int LXA = EX + 4, LYA = EY + 2, RXA = LXA + 2, RYA = LYA + 2;
+  constexpr int NRA = 2 * LXA + 4 * EY;  // macro cells of the first step outside E
+  // second step: the single-step layout, macro cells (c, r) <-> (x0 - 2 + c, y0 - 1 + r)
+  constexpr int LX = TX + 4, LY = TY + 2;
+  constexpr int NRB = 2 * LX + 4 * TY;
+  static_assert(ES <= 2 * NT && NRA <= NT && NRB <= NT, "lane assignment");
+  static_assert(EX == LX + 2 && EY == LY + 2, "E doubles as the second step's reference tile");
+  __shared__ float s_eo[LDS_NOUT * ES];
+  __shared__ float s_work[5 * LYA * LXA + RYA * RXA];
+
+  const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
+  if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
+  const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+  const void* __restrict__ A = io.A;
+  const int nx = P.nx, ny = P.ny;
+  const int t = threadIdx.x;
+
+  // ===== step n -> n+1 on E, from global memory, results to LDS ===========
+  {
+    float(*sphi)[LXA] = reinterpret_cast<float(*)[LXA]>(s_work);
+    float(*srho)[LXA] = sphi + LYA;
+    float(*sfsH)[LXA] = srho + LYA;
+    float(*sp)[LXA] = sfsH + LYA;
+    float(*sS)[LXA] = sp + LYA;
+    float(*sref)[RXA] = reinterpret_cast<float(*)[RXA]>(s_work + 5 * LYA * LXA);
+    const int xa0 = x0 - 5, ya0 = y0 - 3;
+
+    // phase 0: every global load at once (two E cells per lane at most,
+    // one macro cell outside E, the reference tile and lagged p, S)
+    Macro m[2], mh;
+    float f[2][9], pux[2] = {0.0f, 0.0f}, puy[2] = {0.0f, 0.0f};
+    bool on[2];
+    int ex[2], ey[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int e = t + s * NT;
+      ex[s] = e % EX;
+      ey[s] = e / EX;
+      const int y = y0 - 2 + ey[s];
+      on[s] = e < ES && y >= 0 && y < ny;
+      if (on[s]) {
+        const int x = wrapx(x0 - 3 + ex[s], nx);
+        load_node<float>(A, io.fsH_in, P, x, y, m[s]);
+        const int xm = x == 0 ? nx - 1 : x - 1;
+        const int xp = x == nx - 1 ? 0 : x + 1;
+        pull9<1, float>(A, P, x, y, xm, xp, f[s]);
+        pux[s] = ld(io.phiu_in, (unsigned)(y * nx + x));
+        puy[s] = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
+      }
+    }
+    int hr = 0, hc = 0;
+    bool halo = false;
+    if (t < NRA) {
+      ring_cell<LXA, LYA, EX>(t, hr, hc);
+      const int gy = ya0 + hr;
+      halo = gy >= 0 && gy < ny;
+      if (halo) load_node<float>(A, io.fsH_in, P, wrapx(xa0 + hc, nx), gy, mh);
+    }
+    for (int j = t; j < RXA * RYA; j += NT) {
+      const int r = j / RXA, c = j - (j / RXA) * RXA;
+      const int gy = min(max(ya0 + r - 1, 0), ny - 1);
+      float rv, tv;
+      RefIO<false>::load(io.ref_in, (unsigned)(gy * nx + wrapx(xa0 + c - 1, nx)), rv, tv);
+      sref[r][c] = rv;
+    }
+    for (int j = t; j < LXA * LYA; j += NT) {
+      const int r = j / LXA, c = j - (j / LXA) * LXA;
+      const int gy = min(max(ya0 + r, 0), ny - 1);
+      const int kk = gy * nx + wrapx(xa0 + c, nx);
+      sp[r][c] = ld(io.p_in, (unsigned)kk);
+      sS[r][c] = ld(io.S_in, (unsigned)kk);
+    }
+    __syncthreads();
+
+    // phase 1: macros of time n
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (!on[s]) continue;
+      const int c = ex[s] + 2, r = ey[s] + 1;
+      const float rs = rebase_g<RXA>(m[s].g, sref, P, ya0 + r, c, r);
+      finish_macro<false>(P, rs, m[s]);
+      sphi[r][c] = (m[s].r - 1.0f) + m[s].dl;
+      srho[r][c] = m[s].rho;
+      sfsH[r][c] = m[s].fsH;
+    }
+    if (halo) {
+      const float rs = rebase_g<RXA>(mh.g, sref, P, ya0 + hr, hc, hr);
+      finish_macro<false>(P, rs, mh);
+      sphi[hr][hc] = (mh.r - 1.0f) + mh.dl;
+      srho[hr][hc] = mh.rho;
+      sfsH[hr][hc] = mh.fsH;
+    }
+    __syncthreads();
+
+    const int rb = -1 - ya0, rt = ny - ya0;  // rows of y = -1 and y = ny
+    const bool gb = rb >= 0 && rb < LYA, gt = rt >= 0 && rt < LYA;
+    if (gb || gt) {
+      ghost_rows<LXA>(P, sphi, srho, sfsH, gb, rb, gt, rt, t, NT);
+      __syncthreads();
+    }
+
+    // phase 2: stencils, collisions; results of time n+1 to LDS
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (!on[s]) continue;
+      Grads d;
+      tile_grads<LXA>(sphi, srho, sp, sS, ey[s] + 1, ex[s] + 2, d);
+      update_node<false, float, false, ES>(P, io, m[s], f[s], pux[s], puy[s], d, 0u,
+                                           s_eo + ey[s] * EX + ex[s]);
+    }
+    __syncthreads();
+  }
+
+  // ===== step n+1 -> n+2 on the tile, from LDS, results to global =========
+  float(*sphi)[LX] = reinterpret_cast<float(*)[LX]>(s_work);
+  float(*srho)[LX] = sphi + LY;
+  float(*sfsH)[LX] = srho + LY;
+  float(*sp)[LX] = sfsH + LY;
+  float(*sS)[LX] = sp + LY;
+  const float(*sref)[EX] = reinterpret_cast<const float(*)[EX]>(s_eo + LDS_REF * ES);
+  const int lx = t % TX, ly = t / TX;
+  const int x = x0 + lx, y = y0 + ly;
+  const bool yin = y < ny;
+  const bool active = yin && x < nx;
+  Macro m, mh;
+  float f[9], phiux = 0.0f, phiuy = 0.0f;
+  if (yin) load_node_lds<EX, ES>(s_eo, P, lx + 3, ly + 2, y, m);
+  if (active) {
+    const int e = (ly + 2) * EX + lx + 3;
+    pull9_lds<1, EX, ES>(s_eo, P, lx + 3, ly + 2, y, f);
+    phiux = s_eo[LDS_PHIUX * ES + e];
+    phiuy = s_eo[LDS_PHIUY * ES + e];
+  }
+  int hr = 0, hc = 0;
+  bool halo = false;
+  if (t < NRB) {
+    ring_cell<LX, LY, TX>(t, hr, hc);
+    const int gy = y0 + hr - 1;
+    halo = gy >= 0 && gy < ny;
+    if (halo) load_node_lds<EX, ES>(s_eo, P, hc + 1, hr + 1, gy, mh);
+  }
+  for (int j = t; j < LX * LY; j += NT) {
+    const int r = j / LX, c = j - (j / LX) * LX;
+    const int gy = min(max(y0 + r - 1, 0), ny - 1);
+    const int e = (gy - y0 + 2) * EX + c + 1;
+    sp[r][c] = s_eo[LDS_P * ES + e];
+    sS[r][c] = s_eo[LDS_S * ES + e];
+  }
+  if (yin) {
+    const float rs = rebase_g<EX>(m.g, sref, P, y, lx + 2, ly + 1);
+    finish_macro<false>(P, rs, m);
+    sphi[ly + 1][lx + 2] = (m.r - 1.0f) + m.dl;
+    srho[ly + 1][lx + 2] = m.rho;
+    sfsH[ly + 1][lx + 2] = m.fsH;
+  }
+  if (halo) {
+    const float rs = rebase_g<EX>(mh.g, sref, P, y0 + hr - 1, hc, hr);
+    finish_macro<false>(P, rs, mh);
+    sphi[hr][hc] = (mh.r - 1.0f) + mh.dl;
+    srho[hr][hc] = mh.rho;
+    sfsH[hr][hc] = mh.fsH;
+  }
+  __syncthreads();
+  const bool has_bot = (y0 == 0), has_top = (ny <= y0 + TY);
+  if (has_bot || has_top) {
+    ghost_rows<LX>(P, sphi, srho, sfsH, has_bot, 0, has_top, ny - y0 + 1, t, NT);
+    __syncthreads();
+  }
+  if (!active) return;  // no barrier below
+  Grads d;
+  tile_grads<LX>(sphi, srho, sp, sS, ly + 1, lx + 2, d);
+  update_node<false, float, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x));
 }
 
 // Unfused two-kernel step, kept to measure what fusion saves.  Pass 1
@@ -1056,6 +1375,26 @@ int launch_unfused(const KParams& P, const State& S, int cur, bool fields_only, 
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <int TX, int TY>
+int launch_tile2(const KParams& P, const State& S, int cur, int xcd, hipStream_t st) {
+  const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+  const int ntiles = ntx * nty;
+  int band = 0, grid = ntiles;
+  if (xcd == 1) {
+    band = (ntiles + 7) / 8;
+    grid = 8 * band;
+  } else if (xcd == 2) {
+    band = (ntx + 7) / 8;
+    grid = 8 * band * nty;
+  }
+  const StepIO io = make_io(S, cur);
+  if (P.stream_stores)
+    hipLaunchKernelGGL((k_step2<TX, TY, true>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
+  else
+    hipLaunchKernelGGL((k_step2<TX, TY, false>), dim3(grid), dim3(TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <class PT>
 int launch_step_t(const KParams& P, const State& S, int cur, bool fields_only, int tile_variant,
                   int xcd_remap, hipStream_t st) {
@@ -1064,6 +1403,9 @@ int launch_step_t(const KParams& P, const State& S, int cur, bool fields_only, i
       return launch_unfused<64, 8, PT>(P, S, cur, fields_only, xcd_remap, st);
     case 1:
       return launch_tile<32, 8, PT>(P, S, cur, fields_only, xcd_remap, st);
+    case 6:  // single steps (an odd remainder) and field output of the two-step variants
+    case 7:
+    case 8:
     case 2:
       return launch_tile<64, 8, PT>(P, S, cur, fields_only, xcd_remap, st);
     case 3:
@@ -1104,6 +1446,20 @@ int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int
   if (P.storage == STORE_BF16)
     return launch_step_t<__bf16>(P, S, cur, fields_only, tile_variant, xcd_remap, st);
   return launch_step_t<float>(P, S, cur, fields_only, tile_variant, xcd_remap, st);
+}
+
+int launch_step2(const KParams& P, const State& S, int cur, int tile_variant, int xcd_remap, hipStream_t st) {
+  if (P.storage != STORE_FP32) return -1;
+  switch (tile_variant) {
+    case TWO_STEP_VARIANT:
+      return launch_tile2<64, 8>(P, S, cur, xcd_remap, st);
+    case TWO_STEP_VARIANT + 1:
+      return launch_tile2<32, 8>(P, S, cur, xcd_remap, st);
+    case TWO_STEP_VARIANT + 2:
+      return launch_tile2<32, 16>(P, S, cur, xcd_remap, st);
+    default:
+      return -1;
+  }
 }
 
 int launch_expand(const KParams& P, const State& S, int cur, int lattice, hipStream_t st) {

@@ -6,6 +6,7 @@ other cases use the same bounds; pressure, which is not in that list, is
 held to a relative L2 of 1e-3 of its own scale (it is ~1e-4 in absolute
 terms, so FP32 rounding of the 27 populations shows up relatively larger).
 """
+import itertools
 import math
 
 import numpy as np
@@ -207,6 +208,45 @@ def test_launch_shapes_bitwise_on_ragged_grids(nx, ny):
             fb = b.fields(FIELDS)
             for k in FIELDS:
                 assert np.array_equal(fa[k], fb[k]), (tile, xcd, k)
+
+
+@pytest.mark.parametrize("nx,ny,steps", [(3, 3, 9), (70, 13, 15), (130, 19, 8), (512, 256, 21)])
+def test_two_step_launch_equals_single_steps(nx, ny, steps):
+    """Two steps per launch (the first on the tile plus its halo, kept in
+    LDS) reproduce single steps bit for bit: state after an odd remainder,
+    in every workgroup order and with streaming stores; refused under
+    16-bit storage."""
+    lbm = _gpu()
+    if (nx, ny) == (512, 256):
+        p, phi0, T0, _ = W.workload("sessile512", seed=0)
+    else:
+        p = W.default_params(nx, ny, rho_s=0.88, theta_bottom_deg=65.0, theta_top_deg=115.0,
+                             gx=2e-6, gy=-5e-6, cp_s=0.7, k_s=0.2, cp_g=0.9, k_g=0.05)
+        R = max(2.0, min(nx, ny, 40) / 2.5)
+        phi0 = W.sessile_droplet(nx, ny, R, 90.0, 4.0, x0=nx / 2.0 + 0.3)
+        T0 = W.temperature_noise(nx, ny, p["T_melt"], 1e-3, 4)
+    a = lbm.Solver(p, phi0, T0)
+    a.set_launch("64x8", 1)
+    a.step(steps)
+    ref = a.save()
+    fa = a.fields(FIELDS)
+    for tile, xcd, mode in itertools.product(lbm.TWO_STEP_VARIANTS, lbm.XCD_MODES, ("cached", "streaming")):
+        print(f"{nx}x{ny} {tile} xcd={xcd} {mode}", flush=True)
+        b = lbm.Solver(p, phi0, T0)
+        b.set_launch(tile, xcd)
+        b.set_store_mode(mode)
+        b.step(1)
+        b.step(steps - 1)
+        assert b.step_count == steps
+        assert b.save() == ref, (tile, xcd, mode)
+        fb = b.fields(FIELDS)
+        for k in FIELDS:
+            assert np.array_equal(fa[k], fb[k]), (tile, xcd, mode, k)
+    h = lbm.Solver(dict(p, storage=lbm.STORAGE["fp16"]), phi0, T0)
+    for tile in lbm.TWO_STEP_VARIANTS:
+        with pytest.raises(lbm.LbmError) as e:
+            h.set_launch(tile, 0)
+        assert e.value.code == lbm.LBM_EINVAL
 
 
 def test_autotune_leaves_state_untouched():
