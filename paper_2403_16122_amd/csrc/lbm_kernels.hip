@@ -578,205 +578,6 @@ __device__ __forceinline__ int map_tile(int b, int mode, int band, int ntx, int 
   return b;
 }
 
-// One TX x TY tile (origin x0, y0) of the fused step; shared by the
-// single-grid kernel and the batched one.  MACRO_IN: the collide pass of
-// the unfused two-kernel step; phi - 1, rho and f_s^H of every node were
-// written by k_macro to the first three output-field planes, and the halo
-// is read from there instead of being rebuilt from pulled populations.
-template <int TX, int TY, bool FIELDS, class PT, bool MACRO_IN = false, bool STREAM = false>
-__device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, int x0, int y0) {
-  constexpr int NT = TX * TY;
-  constexpr int LX = TX + 4, LY = TY + 2;  // LDS column c <-> x0 + c - 2, row r <-> y0 + r - 1
-  constexpr int RX = LX + 2, RY = LY + 2;  // reference tile: one more cell on every side
-  __shared__ float s_phi[LY][LX];  // phi - 1 (stencils are blind to the constant)
-  __shared__ float s_rho[LY][LX];
-  __shared__ float s_fsH[LY][LX];
-  __shared__ float s_p[LY][LX];
-  __shared__ float s_S[LY][LX];
-  __shared__ float s_ref[RY][RX];  // phi of the previous step, reference of the stored g
-  constexpr bool NR = PopIO<PT>::kNodeRef;
-  __shared__ float s_th[NR ? RY : 1][NR ? RX : 1];  // reference T - T_m of the stored h
-
-  const void* __restrict__ A = io.A;
-  const int nx = P.nx, ny = P.ny;
-  const int t = threadIdx.x;
-  const int lx = t % TX, ly = t / TX;
-  const int x = x0 + lx, y = y0 + ly;
-  const int xw = wrapx(x, nx);
-  const bool yin = y < ny;
-  const bool active = yin && x < nx;
-
-  // ---- phase 0: issue every global load of the tile at once ---------------
-  // This node's pulled g, h, f and history values, the one halo cell this
-  // lane rebuilds, and the previous-step fields with halo for LDS.  A single
-  // memory round trip then feeds the whole step.
-  constexpr int NRING = 2 * LX + 4 * TY;
-  static_assert(NRING <= NT, "one halo cell per lane at most");
-  Macro m, mh;
-  float f[9], phiux = 0.0f, phiuy = 0.0f;
-  if (yin) load_node<PT>(A, io.fsH_in, P, xw, y, m);
-  if (active) {
-    const int xm = x == 0 ? nx - 1 : x - 1;
-    const int xp = x == nx - 1 ? 0 : x + 1;
-    pull9<1, PT>(A, P, x, y, xm, xp, f);
-    phiux = ld(io.phiu_in, (unsigned)(y * nx + x));
-    phiuy = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
-  }
-  int hr = 0, hc = 0;
-  bool halo = false;
-  if (!MACRO_IN && t < NRING) {
-    if (t < LX) {
-      hr = 0;
-      hc = t;
-    } else if (t < 2 * LX) {
-      hr = LY - 1;
-      hc = t - LX;
-    } else {
-      const int q = t - 2 * LX;
-      hr = 1 + (q >> 2);
-      const int s = q & 3;
-      hc = s < 2 ? s : TX + s;
-    }
-    const int gy = y0 + hr - 1;
-    halo = gy >= 0 && gy < ny;
-    if (halo) load_node<PT>(A, io.fsH_in, P, wrapx(x0 + hc - 2, nx), gy, mh);
-  }
-  // phi_ref with a two-cell halo (rows beyond a wall are never read; the
-  // clamp keeps the load in bounds), and the lagged p and S with one cell
-  // (rows beyond a wall copy the adjacent row)
-  for (int j = t; j < RX * RY; j += NT) {
-    const int r = j / RX, c = j - (j / RX) * RX;
-    const int gy = min(max(y0 + r - 2, 0), ny - 1);
-    float rv, tv;
-    RefIO<NR>::load(io.ref_in, (unsigned)(gy * nx + wrapx(x0 + c - 3, nx)), rv, tv);
-    s_ref[r][c] = rv;
-    if constexpr (NR) s_th[r][c] = tv;
-  }
-  for (int j = t; j < LX * LY; j += NT) {
-    const int r = j / LX, c = j - (j / LX) * LX;
-    const int gy = min(max(y0 + r - 1, 0), ny - 1);
-    const int kk = gy * nx + wrapx(x0 + c - 2, nx);
-    s_p[r][c] = ld(io.p_in, (unsigned)kk);
-    s_S[r][c] = ld(io.S_in, (unsigned)kk);
-    if constexpr (MACRO_IN) {
-      s_phi[r][c] = ld(io.fields, (unsigned)kk);
-      s_rho[r][c] = ld(io.fields, P.plane + (unsigned)kk);
-      s_fsH[r][c] = ld(io.fields, 2u * P.plane + (unsigned)kk);
-    }
-  }
-  __syncthreads();
-
-  // ---- phase 1: macroscopic quantities of time t into LDS ----------------
-  if (yin) {
-    const float rs = rebase_g<RX>(m.g, s_ref, P, y, lx + 2, ly + 1);
-    if constexpr (NR) m.th = rebase_h<RX>(m.h, s_th, P, y, lx + 2, ly + 1);
-    finish_macro<NR>(P, rs, m);
-    s_phi[ly + 1][lx + 2] = (m.r - 1.0f) + m.dl;
-    s_rho[ly + 1][lx + 2] = m.rho;
-    s_fsH[ly + 1][lx + 2] = m.fsH;
-  }
-  if (halo) {
-    const float rs = rebase_g<RX>(mh.g, s_ref, P, y0 + hr - 1, hc, hr);
-    if constexpr (NR) mh.th = rebase_h<RX>(mh.h, s_th, P, y0 + hr - 1, hc, hr);
-    finish_macro<NR>(P, rs, mh);
-    s_phi[hr][hc] = (mh.r - 1.0f) + mh.dl;
-    s_rho[hr][hc] = mh.rho;
-    s_fsH[hr][hc] = mh.fsH;
-  }
-  __syncthreads();
-
-  // ---- wall ghost rows: wetting condition, Eq. (39)-(41) -----------------
-  const bool has_bot = (y0 == 0), has_top = (ny <= y0 + TY);
-  if (has_bot || has_top) {
-    for (int j = t; j < 2 * LX; j += NT) {
-      const bool isb = j < LX;
-      const int c = isb ? j : j - LX;
-      if (c < 1 || c > LX - 2) continue;
-      int r, r0, r1;
-      float tv;
-      if (isb) {
-        if (!has_bot) continue;
-        r = 0;
-        r0 = 1;
-        r1 = 2;
-        tv = P.tan_b;
-      } else {
-        if (!has_top) continue;
-        r = ny - y0 + 1;
-        r0 = r - 1;
-        r1 = r - 2;
-        tv = P.tan_t;
-      }
-      const float pg = wetting_ghost(s_phi[r0][c - 1], s_phi[r0][c], s_phi[r0][c + 1],
-                                     s_phi[r1][c - 1], s_phi[r1][c + 1], tv);
-      const float pcg = clamp01(1.0f + pg);
-      s_phi[r][c] = pg;
-      s_rho[r][c] = mix3(pcg * s_fsH[r0][c], pcg, P.rho_s, P.rho_l, P.rho_g);
-    }
-    __syncthreads();
-  }
-  if (!active) return;  // no barrier below
-
-  // ---- phase 2: stencils (Eq. (38)), forces, flow macros, collisions -----
-  const int r = ly + 1, c = lx + 2;
-  const int k = y * nx + x;
-  Grads d;
-#define LBM_TILE_STENCIL(arr, ox, oy, lap)                                                       \
-  stencil(arr[r][c], arr[r][c + 1], arr[r][c - 1], arr[r + 1][c], arr[r - 1][c], arr[r + 1][c + 1], \
-          arr[r + 1][c - 1], arr[r - 1][c - 1], arr[r - 1][c + 1], ox, oy, lap)
-  LBM_TILE_STENCIL(s_phi, d.phx, d.phy, &d.lphi);
-  LBM_TILE_STENCIL(s_rho, d.rx, d.ry, nullptr);
-  LBM_TILE_STENCIL(s_p, d.px, d.py, nullptr);
-  LBM_TILE_STENCIL(s_S, d.Sx, d.Sy, nullptr);
-#undef LBM_TILE_STENCIL
-  update_node<FIELDS, PT, STREAM>(P, io, m, f, phiux, phiuy, d, k);
-}
-
-template <int TX, int TY, bool FIELDS, class PT, bool STREAM = false>
-__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) void k_step(
-    KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
-  const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
-  if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
-  step_tile<TX, TY, FIELDS, PT, false, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
-}
-
-// ---- two steps per launch (FP32) -----------------------------------------
-// The second step of a TX x TY tile reads first-step results on the tile
-// plus 3 columns and 2 rows on each side (its halo macros pull from one cell
-// further, and their reference phi one more).  The workgroup first runs the
-// step on that region E from global memory, keeping its results in LDS, then
-// runs the second step on the tile from LDS and writes it out: one read and
-// one write of the state per two steps, for ~1.3x the arithmetic (the
-// overlap of neighbouring regions is computed by both tiles).  Every node
-// goes through the same macro and update code as in k_step, so the results
-// are bitwise those of two single steps.
-
-// Pull-stream one lattice into E cell (ex, ey) of grid row y from
-// first-step results in LDS (plane j at eo[j * ES]), with pull9's wall rules.
-template <int LAT, int EX, int ES>
-__device__ __forceinline__ void pull9_lds(const float* __restrict__ eo, const KParams& P, int ex, int ey,
-                                          int y, float q[9]) {
-  const bool bot = (y == 0), top = (y == P.ny - 1);
-  const int e = ey * EX + ex;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const int cy = cyv(i), cx = cxv(i);
-    const bool wall = (cy > 0 && bot) || (cy < 0 && top);
-    const int idx = wall ? (LAT * 9 + opp(i)) * ES + e : (LAT * 9 + i) * ES + e - cy * EX - cx;
-    float v = eo[idx];
-    if (LAT == 2 && cy > 0) v = bot ? (P.hwall[i] - v) : v;
-    q[i] = v;
-  }
-}
-
-template <int EX, int ES>
-__device__ __forceinline__ void load_node_lds(const float* __restrict__ eo, const KParams& P, int ex, int ey,
-                                              int y, Macro& m) {
-  pull9_lds<0, EX, ES>(eo, P, ex, ey, y, m.g);
-  pull9_lds<2, EX, ES>(eo, P, ex, ey, y, m.h);
-  m.fprev = eo[LDS_FSH * ES + ey * EX + ex];
-}
-
 // Halo cell of a macro region LXR x LYR around an inner block of TXR x
 // TYR cells (two columns and one row on each side): lane q < 2 LXR + 4 TYR
 // takes the bottom row, the top row, then the side columns row by row.
@@ -841,6 +642,161 @@ __device__ __forceinline__ void tile_grads(const float (*sphi)[LXR], const float
   LBM_GRAD(sp, d.px, d.py, nullptr);
   LBM_GRAD(sS, d.Sx, d.Sy, nullptr);
 #undef LBM_GRAD
+}
+
+// One TX x TY tile (origin x0, y0) of the fused step; shared by the
+// single-grid kernel and the batched one.  MACRO_IN: the collide pass of
+// the unfused two-kernel step; phi - 1, rho and f_s^H of every node were
+// written by k_macro to the first three output-field planes, and the halo
+// is read from there instead of being rebuilt from pulled populations.
+template <int TX, int TY, bool FIELDS, class PT, bool MACRO_IN = false, bool STREAM = false>
+__device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, int x0, int y0) {
+  constexpr int NT = TX * TY;
+  constexpr int LX = TX + 4, LY = TY + 2;  // LDS column c <-> x0 + c - 2, row r <-> y0 + r - 1
+  constexpr int RX = LX + 2, RY = LY + 2;  // reference tile: one more cell on every side
+  __shared__ float s_phi[LY][LX];  // phi - 1 (stencils are blind to the constant)
+  __shared__ float s_rho[LY][LX];
+  __shared__ float s_fsH[LY][LX];
+  __shared__ float s_p[LY][LX];
+  __shared__ float s_S[LY][LX];
+  __shared__ float s_ref[RY][RX];  // phi of the previous step, reference of the stored g
+  constexpr bool NR = PopIO<PT>::kNodeRef;
+  __shared__ float s_th[NR ? RY : 1][NR ? RX : 1];  // reference T - T_m of the stored h
+
+  const void* __restrict__ A = io.A;
+  const int nx = P.nx, ny = P.ny;
+  const int t = threadIdx.x;
+  const int lx = t % TX, ly = t / TX;
+  const int x = x0 + lx, y = y0 + ly;
+  const int xw = wrapx(x, nx);
+  const bool yin = y < ny;
+  const bool active = yin && x < nx;
+
+  // ---- phase 0: issue every global load of the tile at once ---------------
+  // This node's pulled g, h, f and history values, the one halo cell this
+  // lane rebuilds, and the previous-step fields with halo for LDS.  A single
+  // memory round trip then feeds the whole step.
+  constexpr int NRING = 2 * LX + 4 * TY;
+  static_assert(NRING <= NT, "one halo cell per lane at most");
+  Macro m, mh;
+  float f[9], phiux = 0.0f, phiuy = 0.0f;
+  if (yin) load_node<PT>(A, io.fsH_in, P, xw, y, m);
+  if (active) {
+    const int xm = x == 0 ? nx - 1 : x - 1;
+    const int xp = x == nx - 1 ? 0 : x + 1;
+    pull9<1, PT>(A, P, x, y, xm, xp, f);
+    phiux = ld(io.phiu_in, (unsigned)(y * nx + x));
+    phiuy = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
+  }
+  int hr = 0, hc = 0;
+  bool halo = false;
+  if (!MACRO_IN && t < NRING) {
+    ring_cell<LX, LY, TX>(t, hr, hc);
+    const int gy = y0 + hr - 1;
+    halo = gy >= 0 && gy < ny;
+    if (halo) load_node<PT>(A, io.fsH_in, P, wrapx(x0 + hc - 2, nx), gy, mh);
+  }
+  // phi_ref with a two-cell halo (rows beyond a wall are never read; the
+  // clamp keeps the load in bounds), and the lagged p and S with one cell
+  // (rows beyond a wall copy the adjacent row)
+  for (int j = t; j < RX * RY; j += NT) {
+    const int r = j / RX, c = j - (j / RX) * RX;
+    const int gy = min(max(y0 + r - 2, 0), ny - 1);
+    float rv, tv;
+    RefIO<NR>::load(io.ref_in, (unsigned)(gy * nx + wrapx(x0 + c - 3, nx)), rv, tv);
+    s_ref[r][c] = rv;
+    if constexpr (NR) s_th[r][c] = tv;
+  }
+  for (int j = t; j < LX * LY; j += NT) {
+    const int r = j / LX, c = j - (j / LX) * LX;
+    const int gy = min(max(y0 + r - 1, 0), ny - 1);
+    const int kk = gy * nx + wrapx(x0 + c - 2, nx);
+    s_p[r][c] = ld(io.p_in, (unsigned)kk);
+    s_S[r][c] = ld(io.S_in, (unsigned)kk);
+    if constexpr (MACRO_IN) {
+      s_phi[r][c] = ld(io.fields, (unsigned)kk);
+      s_rho[r][c] = ld(io.fields, P.plane + (unsigned)kk);
+      s_fsH[r][c] = ld(io.fields, 2u * P.plane + (unsigned)kk);
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 1: macroscopic quantities of time t into LDS ----------------
+  if (yin) {
+    const float rs = rebase_g<RX>(m.g, s_ref, P, y, lx + 2, ly + 1);
+    if constexpr (NR) m.th = rebase_h<RX>(m.h, s_th, P, y, lx + 2, ly + 1);
+    finish_macro<NR>(P, rs, m);
+    s_phi[ly + 1][lx + 2] = (m.r - 1.0f) + m.dl;
+    s_rho[ly + 1][lx + 2] = m.rho;
+    s_fsH[ly + 1][lx + 2] = m.fsH;
+  }
+  if (halo) {
+    const float rs = rebase_g<RX>(mh.g, s_ref, P, y0 + hr - 1, hc, hr);
+    if constexpr (NR) mh.th = rebase_h<RX>(mh.h, s_th, P, y0 + hr - 1, hc, hr);
+    finish_macro<NR>(P, rs, mh);
+    s_phi[hr][hc] = (mh.r - 1.0f) + mh.dl;
+    s_rho[hr][hc] = mh.rho;
+    s_fsH[hr][hc] = mh.fsH;
+  }
+  __syncthreads();
+
+  // ---- wall ghost rows: wetting condition, Eq. (39)-(41) -----------------
+  const bool has_bot = (y0 == 0), has_top = (ny <= y0 + TY);
+  if (has_bot || has_top) {
+    ghost_rows<LX>(P, s_phi, s_rho, s_fsH, has_bot, 0, has_top, ny - y0 + 1, t, NT);
+    __syncthreads();
+  }
+  if (!active) return;  // no barrier below
+
+  // ---- phase 2: stencils (Eq. (38)), forces, flow macros, collisions -----
+  Grads d;
+  tile_grads<LX>(s_phi, s_rho, s_p, s_S, ly + 1, lx + 2, d);
+  update_node<FIELDS, PT, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x));
+}
+
+template <int TX, int TY, bool FIELDS, class PT, bool STREAM = false>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) void k_step(
+    KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
+  const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
+  if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
+  step_tile<TX, TY, FIELDS, PT, false, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
+}
+
+// ---- two steps per launch (FP32) -----------------------------------------
+// The second step of a TX x TY tile reads first-step results on the tile
+// plus 3 columns and 2 rows on each side (its halo macros pull from one cell
+// further, and their reference phi one more).  The workgroup first runs the
+// step on that region E from global memory, keeping its results in LDS, then
+// runs the second step on the tile from LDS and writes it out: one read and
+// one write of the state per two steps, for ~1.3x the arithmetic (the
+// overlap of neighbouring regions is computed by both tiles).  Every node
+// goes through the same macro and update code as in k_step, so the results
+// are bitwise those of two single steps.
+
+// Pull-stream one lattice into E cell (ex, ey) of grid row y from
+// first-step results in LDS (plane j at eo[j * ES]), with pull9's wall rules.
+template <int LAT, int EX, int ES>
+__device__ __forceinline__ void pull9_lds(const float* __restrict__ eo, const KParams& P, int ex, int ey,
+                                          int y, float q[9]) {
+  const bool bot = (y == 0), top = (y == P.ny - 1);
+  const int e = ey * EX + ex;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cy = cyv(i), cx = cxv(i);
+    const bool wall = (cy > 0 && bot) || (cy < 0 && top);
+    const int idx = wall ? (LAT * 9 + opp(i)) * ES + e : (LAT * 9 + i) * ES + e - cy * EX - cx;
+    float v = eo[idx];
+    if (LAT == 2 && cy > 0) v = bot ? (P.hwall[i] - v) : v;
+    q[i] = v;
+  }
+}
+
+template <int EX, int ES>
+__device__ __forceinline__ void load_node_lds(const float* __restrict__ eo, const KParams& P, int ex, int ey,
+                                              int y, Macro& m) {
+  pull9_lds<0, EX, ES>(eo, P, ex, ey, y, m.g);
+  pull9_lds<2, EX, ES>(eo, P, ex, ey, y, m.h);
+  m.fprev = eo[LDS_FSH * ES + ey * EX + ex];
 }
 
 template <int TX, int TY, bool STREAM = false>
