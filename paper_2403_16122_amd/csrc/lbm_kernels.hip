@@ -311,6 +311,63 @@ __device__ __forceinline__ void load_node(const void* __restrict__ A,
   m.fprev = ld(fsH_prev, (unsigned)(y * P.nx + x));
 }
 
+// The 16-bit formats hold pulled populations as loaded, two per register,
+// from the load to their first use after the tile's barrier, and convert
+// then (the same conversion, scale and wall rule as pull9, in the same
+// order): the loads in flight across the barrier take half the registers.
+template <class PT>
+struct Raw9 {
+  typedef PT v2 __attribute__((ext_vector_type(2)));
+  v2 p[5];
+};
+
+template <int LAT, class PT>
+__device__ __forceinline__ void pull9_raw(const void* __restrict__ A, const KParams& P, int x, int y, int xm,
+                                          int xp, Raw9<PT>& r) {
+  const unsigned pl = P.plane;
+  const unsigned nx = (unsigned)P.nx;
+  const bool bot = (y == 0), top = (y == P.ny - 1);
+  const unsigned rowc = (unsigned)y * nx;
+  const unsigned rowd = rowc - nx, rowu = rowc + nx;  // used only away from the walls
+  const unsigned k = rowc + (unsigned)x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cy = cyv(i), cx = cxv(i);
+    const bool wall = (cy > 0 && bot) || (cy < 0 && top);
+    const unsigned sx = (unsigned)(cx > 0 ? xm : (cx < 0 ? xp : x));
+    const unsigned sk = (cy > 0 ? rowd : (cy < 0 ? rowu : rowc)) + sx;
+    const unsigned idx = wall ? (unsigned)(LAT * 9 + opp(i)) * pl + k : (unsigned)(LAT * 9 + i) * pl + sk;
+    const PT v = *(const PT*)((const char*)A + (idx << 1));
+    if (i & 1)
+      r.p[i >> 1].y = v;
+    else
+      r.p[i >> 1].x = v;
+  }
+}
+
+template <int LAT, class PT>
+__device__ __forceinline__ void unpack9(const Raw9<PT>& r, const KParams& P, int y, float q[9]) {
+  const bool bot = (y == 0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    float v = (float)((i & 1) ? r.p[i >> 1].y : r.p[i >> 1].x);
+    if constexpr (PopIO<PT>::kScaled) v *= P.sc_ld[LAT];
+    if (LAT == 2 && cyv(i) > 0) v = bot ? (P.hwall[i] - v) : v;
+    q[i] = v;
+  }
+}
+
+template <class PT>
+__device__ __forceinline__ void load_node_raw(const void* __restrict__ A, const float* __restrict__ fsH_prev,
+                                              const KParams& P, int x, int y, Raw9<PT>& g, Raw9<PT>& h,
+                                              float& fprev) {
+  const int xm = x == 0 ? P.nx - 1 : x - 1;
+  const int xp = x == P.nx - 1 ? 0 : x + 1;
+  pull9_raw<0, PT>(A, P, x, y, xm, xp, g);
+  pull9_raw<2, PT>(A, P, x, y, xm, xp, h);
+  fprev = ld(fsH_prev, (unsigned)(y * P.nx + x));
+}
+
 // Node-local macroscopic quantities of time t (Eq. (29), (9), (19), (26), (1))
 // from the loaded inputs; m.g must already be rebased to reference rs and,
 // under NODEREF, m.h to m.th.
@@ -678,13 +735,23 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
   // memory round trip then feeds the whole step.
   constexpr int NRING = 2 * LX + 4 * TY;
   static_assert(NRING <= NT, "one halo cell per lane at most");
+  constexpr bool RAW = !std::is_same<PT, float>::value;  // 16-bit: hold the loads packed
   Macro m, mh;
   float f[9], phiux = 0.0f, phiuy = 0.0f;
-  if (yin) load_node<PT>(A, io.fsH_in, P, xw, y, m);
+  Raw9<PT> rg, rh, rf, rgh, rhh;
+  if (yin) {
+    if constexpr (RAW)
+      load_node_raw<PT>(A, io.fsH_in, P, xw, y, rg, rh, m.fprev);
+    else
+      load_node<PT>(A, io.fsH_in, P, xw, y, m);
+  }
   if (active) {
     const int xm = x == 0 ? nx - 1 : x - 1;
     const int xp = x == nx - 1 ? 0 : x + 1;
-    pull9<1, PT>(A, P, x, y, xm, xp, f);
+    if constexpr (RAW)
+      pull9_raw<1, PT>(A, P, x, y, xm, xp, rf);
+    else
+      pull9<1, PT>(A, P, x, y, xm, xp, f);
     phiux = ld(io.phiu_in, (unsigned)(y * nx + x));
     phiuy = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
   }
@@ -694,7 +761,12 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
     ring_cell<LX, LY, TX>(t, hr, hc);
     const int gy = y0 + hr - 1;
     halo = gy >= 0 && gy < ny;
-    if (halo) load_node<PT>(A, io.fsH_in, P, wrapx(x0 + hc - 2, nx), gy, mh);
+    if (halo) {
+      if constexpr (RAW)
+        load_node_raw<PT>(A, io.fsH_in, P, wrapx(x0 + hc - 2, nx), gy, rgh, rhh, mh.fprev);
+      else
+        load_node<PT>(A, io.fsH_in, P, wrapx(x0 + hc - 2, nx), gy, mh);
+    }
   }
   // phi_ref with a two-cell halo (rows beyond a wall are never read; the
   // clamp keeps the load in bounds), and the lagged p and S with one cell
@@ -723,6 +795,10 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
 
   // ---- phase 1: macroscopic quantities of time t into LDS ----------------
   if (yin) {
+    if constexpr (RAW) {
+      unpack9<0, PT>(rg, P, y, m.g);
+      unpack9<2, PT>(rh, P, y, m.h);
+    }
     const float rs = rebase_g<RX>(m.g, s_ref, P, y, lx + 2, ly + 1);
     if constexpr (NR) m.th = rebase_h<RX>(m.h, s_th, P, y, lx + 2, ly + 1);
     finish_macro<NR>(P, rs, m);
@@ -731,6 +807,10 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
     s_fsH[ly + 1][lx + 2] = m.fsH;
   }
   if (halo) {
+    if constexpr (RAW) {
+      unpack9<0, PT>(rgh, P, y0 + hr - 1, mh.g);
+      unpack9<2, PT>(rhh, P, y0 + hr - 1, mh.h);
+    }
     const float rs = rebase_g<RX>(mh.g, s_ref, P, y0 + hr - 1, hc, hr);
     if constexpr (NR) mh.th = rebase_h<RX>(mh.h, s_th, P, y0 + hr - 1, hc, hr);
     finish_macro<NR>(P, rs, mh);
@@ -751,6 +831,7 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
   // ---- phase 2: stencils (Eq. (38)), forces, flow macros, collisions -----
   Grads d;
   tile_grads<LX>(s_phi, s_rho, s_p, s_S, ly + 1, lx + 2, d);
+  if constexpr (RAW) unpack9<1, PT>(rf, P, y, f);
   update_node<FIELDS, PT, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x));
 }
 
