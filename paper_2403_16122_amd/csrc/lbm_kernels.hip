@@ -210,24 +210,32 @@ __device__ __forceinline__ void* pop_plane(void* B, unsigned j, unsigned pl) {
 // population (half-way rule); for h at the bottom wall by the
 // anti-bounce-back Dirichlet value -h_opp + 2 w_i cp_ref (T_w - T_m) in the
 // shifted variables.
-template <int LAT, class PT>
-__device__ __forceinline__ void pull9(const void* __restrict__ A, const KParams& P, int x, int y,
-                                      int xm, int xp, float q[9]) {
-  // 32-bit element indices: a scalar plane base plus one vector offset per load
+// Element index of the population of lattice LAT pulled into node (x, y)
+// along direction i: the neighbour's x - c_i, or, beyond a wall, the
+// node's own opposite population (32-bit indices: a scalar plane base plus
+// one vector offset per load).
+template <int LAT>
+__device__ __forceinline__ unsigned pull_index(const KParams& P, int i, int x, int y, int xm, int xp) {
   const unsigned pl = P.plane;
   const unsigned nx = (unsigned)P.nx;
   const bool bot = (y == 0), top = (y == P.ny - 1);
   const unsigned rowc = (unsigned)y * nx;
   const unsigned rowd = rowc - nx, rowu = rowc + nx;  // used only away from the walls
-  const unsigned k = rowc + (unsigned)x;
+  const int cy = cyv(i), cx = cxv(i);
+  const bool wall = (cy > 0 && bot) || (cy < 0 && top);
+  const unsigned sx = (unsigned)(cx > 0 ? xm : (cx < 0 ? xp : x));
+  const unsigned sk = (cy > 0 ? rowd : (cy < 0 ? rowu : rowc)) + sx;
+  return wall ? (unsigned)(LAT * 9 + opp(i)) * pl + rowc + (unsigned)x : (unsigned)(LAT * 9 + i) * pl + sk;
+}
+
+template <int LAT, class PT>
+__device__ __forceinline__ void pull9(const void* __restrict__ A, const KParams& P, int x, int y,
+                                      int xm, int xp, float q[9]) {
+  const bool bot = (y == 0);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const int cy = cyv(i), cx = cxv(i);
-    const bool wall = (cy > 0 && bot) || (cy < 0 && top);
-    const unsigned sx = (unsigned)(cx > 0 ? xm : (cx < 0 ? xp : x));
-    const unsigned sk = (cy > 0 ? rowd : (cy < 0 ? rowu : rowc)) + sx;
-    const unsigned idx = wall ? (unsigned)(LAT * 9 + opp(i)) * pl + k : (unsigned)(LAT * 9 + i) * pl + sk;
-    float v = pop_ld<PT, LAT>(A, idx, P);
+    const int cy = cyv(i);
+    float v = pop_ld<PT, LAT>(A, pull_index<LAT>(P, i, x, y, xm, xp), P);
     if (LAT == 2 && cy > 0) v = bot ? (P.hwall[i] - v) : v;
     q[i] = v;
   }
@@ -324,20 +332,9 @@ struct Raw9 {
 template <int LAT, class PT>
 __device__ __forceinline__ void pull9_raw(const void* __restrict__ A, const KParams& P, int x, int y, int xm,
                                           int xp, Raw9<PT>& r) {
-  const unsigned pl = P.plane;
-  const unsigned nx = (unsigned)P.nx;
-  const bool bot = (y == 0), top = (y == P.ny - 1);
-  const unsigned rowc = (unsigned)y * nx;
-  const unsigned rowd = rowc - nx, rowu = rowc + nx;  // used only away from the walls
-  const unsigned k = rowc + (unsigned)x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const int cy = cyv(i), cx = cxv(i);
-    const bool wall = (cy > 0 && bot) || (cy < 0 && top);
-    const unsigned sx = (unsigned)(cx > 0 ? xm : (cx < 0 ? xp : x));
-    const unsigned sk = (cy > 0 ? rowd : (cy < 0 ? rowu : rowc)) + sx;
-    const unsigned idx = wall ? (unsigned)(LAT * 9 + opp(i)) * pl + k : (unsigned)(LAT * 9 + i) * pl + sk;
-    const PT v = *(const PT*)((const char*)A + (idx << 1));
+    const PT v = *(const PT*)((const char*)A + (pull_index<LAT>(P, i, x, y, xm, xp) << 1));
     if (i & 1)
       r.p[i >> 1].y = v;
     else
