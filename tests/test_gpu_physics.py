@@ -12,6 +12,7 @@
   Pr = 7.25, Ste = 0.02, theta = 86.4 deg) against the oracle.
 """
 import math
+import pathlib
 
 import numpy as np
 import pytest
@@ -20,6 +21,7 @@ from scipy.optimize import brentq
 from paper_2403_16122_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+GOLDEN = pathlib.Path(__file__).parent / "golden"
 
 
 def _lbm():
@@ -140,7 +142,12 @@ def test_sessile512_freezes_with_the_area_expansion_of_its_density_ratio():
     change fixes the final condensed area: rho_l A_0 = rho_s A_f, so
     sum(clamp(phi)) grows by 1/gamma = 1.111 (the mass source of Eq. (19)
     is what makes it grow).  The frozen drop ends taller than it started and
-    with a tip; its shape is reported."""
+    with a tip, whose aspect ratio H/R (height over the wetted half-width)
+    is held to the values the paper prints for this angle and density ratio
+    (tests/golden/frozen_aspect_ratio.txt; the paper's own simulation 1.18,
+    the experiment 1.16).  The paper, after Marin et al., ties the tip to the
+    geometry of the expanding front rather than to its speed, so the values
+    are compared although this droplet's Ste and properties differ."""
     lbm = _lbm()
     p, phi0, T0, meta = W.workload("sessile512", seed=0)
     gamma = p["rho_s"] / p["rho_l"]
@@ -163,3 +170,10 @@ def test_sessile512_freezes_with_the_area_expansion_of_its_density_ratio():
     assert abs(ratio - 1.0 / gamma) < 0.02 / gamma
     assert shape["height"] > h_init
     assert 90.0 < shape["tip_angle_deg"] < 180.0
+    golden = dict(line.split() for line in open(GOLDEN / "frozen_aspect_ratio.txt") if line.strip() and line[0] != "#")
+    ar = shape["height"] / shape["base_radius"]
+    print(f"aspect ratio H/R {ar:.3f} (paper: {golden['lattice_boltzmann']} simulated, {golden['experiment']} measured)",
+          flush=True)
+    # measured 1.155 at R = 80 (1.117 in the oracle at R = 20: the tip sharpens with resolution)
+    for k in ("lattice_boltzmann", "experiment"):
+        assert abs(ar - float(golden[k])) <= 0.03 * float(golden[k]), (k, ar)
