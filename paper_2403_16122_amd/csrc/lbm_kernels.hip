@@ -1057,6 +1057,162 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
   update_node<false, float, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x));
 }
 
+// The same two steps with two lanes per tile node: every lane owns at most
+// one cell of each step (an E cell or a cell of the first step's macro ring;
+// a tile node or a halo cell of the second), so a workgroup runs 2 TX TY
+// lanes, four waves per SIMD, with the LDS of k_step2.
+template <int TX, int TY, bool STREAM = false>
+__global__ __launch_bounds__(2 * TX * TY) __attribute__((amdgpu_waves_per_eu(4))) void k_step2w(
+    KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
+  constexpr int NT = 2 * TX * TY, NTILE = TX * TY;
+  constexpr int EX = TX + 6, EY = TY + 4, ES = EX * EY;
+  constexpr int LXA = EX + 4, LYA = EY + 2, RXA = LXA + 2, RYA = LYA + 2;
+  constexpr int NRA = 2 * LXA + 4 * EY;
+  constexpr int LX = TX + 4, LY = TY + 2;
+  constexpr int NRB = 2 * LX + 4 * TY;
+  static_assert(ES + NRA <= NT && NTILE + NRB <= NT, "one cell per lane in each step");
+  static_assert(EX == LX + 2 && EY == LY + 2, "E doubles as the second step's reference tile");
+  __shared__ float s_eo[LDS_NOUT * ES];
+  __shared__ float s_work[5 * LYA * LXA + RYA * RXA];
+
+  const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
+  if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
+  const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+  const void* __restrict__ A = io.A;
+  const int nx = P.nx, ny = P.ny;
+  const int t = threadIdx.x;
+
+  // ===== step n -> n+1 on E, from global memory, results to LDS ===========
+  {
+    float(*sphi)[LXA] = reinterpret_cast<float(*)[LXA]>(s_work);
+    float(*srho)[LXA] = sphi + LYA;
+    float(*sfsH)[LXA] = srho + LYA;
+    float(*sp)[LXA] = sfsH + LYA;
+    float(*sS)[LXA] = sp + LYA;
+    float(*sref)[RXA] = reinterpret_cast<float(*)[RXA]>(s_work + 5 * LYA * LXA);
+    const int xa0 = x0 - 5, ya0 = y0 - 3;
+
+    Macro m;
+    float f[9], pux = 0.0f, puy = 0.0f;
+    int c = 0, r = 0;  // this lane's macro cell of the first step
+    bool on = false;   // an E cell inside the grid: macros and update
+    bool ring = false;  // a macro-ring cell inside the grid: macros only
+    if (t < ES) {
+      c = t % EX + 2;
+      r = t / EX + 1;
+      const int y = ya0 + r;
+      on = y >= 0 && y < ny;
+      if (on) {
+        const int x = wrapx(xa0 + c, nx);
+        load_node<float>(A, io.fsH_in, P, x, y, m);
+        const int xm = x == 0 ? nx - 1 : x - 1;
+        const int xp = x == nx - 1 ? 0 : x + 1;
+        pull9<1, float>(A, P, x, y, xm, xp, f);
+        pux = ld(io.phiu_in, (unsigned)(y * nx + x));
+        puy = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
+      }
+    } else if (t - ES < NRA) {
+      ring_cell<LXA, LYA, EX>(t - ES, r, c);
+      const int gy = ya0 + r;
+      ring = gy >= 0 && gy < ny;
+      if (ring) load_node<float>(A, io.fsH_in, P, wrapx(xa0 + c, nx), gy, m);
+    }
+    for (int j = t; j < RXA * RYA; j += NT) {
+      const int rr = j / RXA, cc = j - (j / RXA) * RXA;
+      const int gy = min(max(ya0 + rr - 1, 0), ny - 1);
+      float rv, tv;
+      RefIO<false>::load(io.ref_in, (unsigned)(gy * nx + wrapx(xa0 + cc - 1, nx)), rv, tv);
+      sref[rr][cc] = rv;
+    }
+    for (int j = t; j < LXA * LYA; j += NT) {
+      const int rr = j / LXA, cc = j - (j / LXA) * LXA;
+      const int gy = min(max(ya0 + rr, 0), ny - 1);
+      const int kk = gy * nx + wrapx(xa0 + cc, nx);
+      sp[rr][cc] = ld(io.p_in, (unsigned)kk);
+      sS[rr][cc] = ld(io.S_in, (unsigned)kk);
+    }
+    __syncthreads();
+
+    if (on || ring) {
+      const float rs = rebase_g<RXA>(m.g, sref, P, ya0 + r, c, r);
+      finish_macro<false>(P, rs, m);
+      sphi[r][c] = (m.r - 1.0f) + m.dl;
+      srho[r][c] = m.rho;
+      sfsH[r][c] = m.fsH;
+    }
+    __syncthreads();
+
+    const int rb = -1 - ya0, rt = ny - ya0;  // rows of y = -1 and y = ny
+    const bool gb = rb >= 0 && rb < LYA, gt = rt >= 0 && rt < LYA;
+    if (gb || gt) {
+      ghost_rows<LXA>(P, sphi, srho, sfsH, gb, rb, gt, rt, t, NT);
+      __syncthreads();
+    }
+
+    if (on) {
+      Grads d;
+      tile_grads<LXA>(sphi, srho, sp, sS, r, c, d);
+      update_node<false, float, false, ES>(P, io, m, f, pux, puy, d, 0u, s_eo + (r - 1) * EX + (c - 2));
+    }
+    __syncthreads();
+  }
+
+  // ===== step n+1 -> n+2 on the tile, from LDS, results to global =========
+  float(*sphi)[LX] = reinterpret_cast<float(*)[LX]>(s_work);
+  float(*srho)[LX] = sphi + LY;
+  float(*sfsH)[LX] = srho + LY;
+  float(*sp)[LX] = sfsH + LY;
+  float(*sS)[LX] = sp + LY;
+  const float(*sref)[EX] = reinterpret_cast<const float(*)[EX]>(s_eo + LDS_REF * ES);
+  Macro m;
+  float f[9], phiux = 0.0f, phiuy = 0.0f;
+  int c = 0, r = 0, y = 0;  // this lane's macro cell of the second step and its grid row
+  bool mac = false, active = false;
+  if (t < NTILE) {
+    const int lx = t % TX, ly = t / TX;
+    c = lx + 2;
+    r = ly + 1;
+    y = y0 + ly;
+    mac = y < ny;
+    active = mac && x0 + lx < nx;
+  } else if (t - NTILE < NRB) {
+    ring_cell<LX, LY, TX>(t - NTILE, r, c);
+    y = y0 + r - 1;
+    mac = y >= 0 && y < ny;
+  }
+  if (mac) load_node_lds<EX, ES>(s_eo, P, c + 1, r + 1, y, m);
+  if (active) {
+    const int e = (r + 1) * EX + c + 1;
+    pull9_lds<1, EX, ES>(s_eo, P, c + 1, r + 1, y, f);
+    phiux = s_eo[LDS_PHIUX * ES + e];
+    phiuy = s_eo[LDS_PHIUY * ES + e];
+  }
+  for (int j = t; j < LX * LY; j += NT) {
+    const int rr = j / LX, cc = j - (j / LX) * LX;
+    const int gy = min(max(y0 + rr - 1, 0), ny - 1);
+    const int e = (gy - y0 + 2) * EX + cc + 1;
+    sp[rr][cc] = s_eo[LDS_P * ES + e];
+    sS[rr][cc] = s_eo[LDS_S * ES + e];
+  }
+  if (mac) {
+    const float rs = rebase_g<EX>(m.g, sref, P, y, c, r);
+    finish_macro<false>(P, rs, m);
+    sphi[r][c] = (m.r - 1.0f) + m.dl;
+    srho[r][c] = m.rho;
+    sfsH[r][c] = m.fsH;
+  }
+  __syncthreads();
+  const bool has_bot = (y0 == 0), has_top = (ny <= y0 + TY);
+  if (has_bot || has_top) {
+    ghost_rows<LX>(P, sphi, srho, sfsH, has_bot, 0, has_top, ny - y0 + 1, t, NT);
+    __syncthreads();
+  }
+  if (!active) return;  // no barrier below
+  Grads d;
+  tile_grads<LX>(sphi, srho, sp, sS, r, c, d);
+  update_node<false, float, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x0 + c - 2));
+}
+
 // Unfused two-kernel step, kept to measure what fusion saves.  Pass 1
 // (k_macro) pulls g and h and writes phi - 1, rho and f_s^H of time t of
 // every node to the first three output-field planes; pass 2 (k_collide)
@@ -1440,6 +1596,7 @@ int launch_step_t(const KParams& P, const State& S, int cur, bool fields_only, i
     case 6:  // single steps (an odd remainder) and field output of the two-step variants
     case 7:
     case 8:
+    case 9:
     case 2:
       return launch_tile<64, 8, PT>(P, S, cur, fields_only, xcd_remap, st);
     case 3:
@@ -1482,9 +1639,31 @@ int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int
   return launch_step_t<float>(P, S, cur, fields_only, tile_variant, xcd_remap, st);
 }
 
+template <int TX, int TY>
+int launch_tile2w(const KParams& P, const State& S, int cur, int xcd, hipStream_t st) {
+  const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+  const int ntiles = ntx * nty;
+  int band = 0, grid = ntiles;
+  if (xcd == 1) {
+    band = (ntiles + 7) / 8;
+    grid = 8 * band;
+  } else if (xcd == 2) {
+    band = (ntx + 7) / 8;
+    grid = 8 * band * nty;
+  }
+  const StepIO io = make_io(S, cur);
+  if (P.stream_stores)
+    hipLaunchKernelGGL((k_step2w<TX, TY, true>), dim3(grid), dim3(2 * TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
+  else
+    hipLaunchKernelGGL((k_step2w<TX, TY, false>), dim3(grid), dim3(2 * TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_step2(const KParams& P, const State& S, int cur, int tile_variant, int xcd_remap, hipStream_t st) {
   if (P.storage != STORE_FP32) return -1;
   switch (tile_variant) {
+    case TWO_STEP_VARIANT + 3:
+      return launch_tile2w<32, 16>(P, S, cur, xcd_remap, st);
     case TWO_STEP_VARIANT:
       return launch_tile2<64, 8>(P, S, cur, xcd_remap, st);
     case TWO_STEP_VARIANT + 1:
