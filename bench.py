@@ -364,7 +364,8 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": ("k_step2 (two fused collide + pull-stream steps per launch)" if spl == 2
+            "kernel": (("k_step2w" if tile.endswith("w") else "k_step2")
+                       + " (two fused collide + pull-stream steps per launch)" if spl == 2
                        else "k_step (fused collide + pull-stream)"),
             "steps_per_launch": spl,
             "bytes_per_launch": bpn * N * spl,
