@@ -139,11 +139,12 @@ const char* lbm_last_error(void);
  * recomputed per tile.  5: the unfused two-kernel step on 64x8 tiles (a
  * macro pass writes phi, rho and f_s^H of every node, then the collide pass
  * reads its halo from there), bitwise equal to the fused step and kept to
- * measure what fusion saves; lbm_autotune does not consider it.  6, 7, 8, 9
+ * measure what fusion saves; lbm_autotune does not consider it.  6-10
  * (FP32 storage only, else LBM_EINVAL): two steps per launch on 64x8, 32x8,
- * 32x16 tiles, and 9 on 32x16 tiles with two lanes per tile node (one cell
- * of each step per lane, four waves per SIMD) -- each workgroup runs the
- * first step on its tile plus 3 columns and 2 rows
+ * 32x16 tiles, then on 32x16 tiles with two lanes per tile node (9: one
+ * cell of each step per lane, four waves per SIMD) and on 32x8 tiles with
+ * three (10: two workgroups per CU, six waves per SIMD) -- each workgroup
+ * runs the first step on its tile plus 3 columns and 2 rows
  * of halo from global memory, keeps those results in LDS and runs the
  * second step on the tile from there, so the state crosses HBM once per two
  * steps at ~1.3-1.5x the arithmetic; lbm_step issues pairs and a single
@@ -165,7 +166,7 @@ int lbm_set_store_mode(lbm_ctx* c, int32_t mode);
 
 /* Time every launch shape for `reps` launches and keep the fastest per step
  * (written to the optional out-pointers): tile variants 0-4, and under FP32
- * storage the two-step variants 6-9 at half their time per launch.  The
+ * storage the two-step variants 6-10 at half their time per launch.  The
  * state is not advanced: each timed launch recomputes the next step(s) from
  * the same buffers.  Synchronises. */
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_remap);

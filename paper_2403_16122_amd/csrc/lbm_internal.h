@@ -85,9 +85,9 @@ struct StepOff {
 
 enum { NFIELD = 10 };
 // tiles 64x4, 32x8, 64x8, 64x16, 128x4; 5: unfused two-kernel 64x8; 6, 7, 8:
-// two steps per launch on 64x8, 32x8, 32x16 tiles; 9: the same on 32x16 tiles
-// with two lanes per tile node (FP32 storage)
-enum { NTILE_VARIANTS = 10, TWO_STEP_VARIANT = 6, NTWO_STEP_VARIANTS = 4 };
+// two steps per launch on 64x8, 32x8, 32x16 tiles; 9, 10: the same on 32x16
+// and 32x8 tiles with two and three lanes per tile node (FP32 storage)
+enum { NTILE_VARIANTS = 11, TWO_STEP_VARIANT = 6, NTWO_STEP_VARIANTS = 5 };
 inline bool is_two_step(int tile_variant) {
   return tile_variant >= TWO_STEP_VARIANT && tile_variant < TWO_STEP_VARIANT + NTWO_STEP_VARIANTS;
 }

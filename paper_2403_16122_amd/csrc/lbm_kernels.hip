@@ -1057,14 +1057,15 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
   update_node<false, float, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x));
 }
 
-// The same two steps with two lanes per tile node: every lane owns at most
-// one cell of each step (an E cell or a cell of the first step's macro ring;
-// a tile node or a halo cell of the second), so a workgroup runs 2 TX TY
-// lanes, four waves per SIMD, with the LDS of k_step2.
-template <int TX, int TY, bool STREAM = false>
-__global__ __launch_bounds__(2 * TX * TY) __attribute__((amdgpu_waves_per_eu(4))) void k_step2w(
+// The same two steps with more lanes than tile nodes: every lane owns at
+// most one cell of each step (an E cell or a cell of the first step's macro
+// ring; a tile node or a halo cell of the second), with the LDS of k_step2.
+// NT lanes: 2 TX TY for 32x16 tiles (one workgroup, 4 waves per SIMD),
+// 3 TX TY for 32x8 tiles (two workgroups, 6 waves per SIMD).
+template <int TX, int TY, int NT, bool STREAM = false>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ? 4 : 6))) void k_step2w(
     KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
-  constexpr int NT = 2 * TX * TY, NTILE = TX * TY;
+  constexpr int NTILE = TX * TY;
   constexpr int EX = TX + 6, EY = TY + 4, ES = EX * EY;
   constexpr int LXA = EX + 4, LYA = EY + 2, RXA = LXA + 2, RYA = LYA + 2;
   constexpr int NRA = 2 * LXA + 4 * EY;
@@ -1597,6 +1598,7 @@ int launch_step_t(const KParams& P, const State& S, int cur, bool fields_only, i
     case 7:
     case 8:
     case 9:
+    case 10:
     case 2:
       return launch_tile<64, 8, PT>(P, S, cur, fields_only, xcd_remap, st);
     case 3:
@@ -1639,7 +1641,7 @@ int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int
   return launch_step_t<float>(P, S, cur, fields_only, tile_variant, xcd_remap, st);
 }
 
-template <int TX, int TY>
+template <int TX, int TY, int NT>
 int launch_tile2w(const KParams& P, const State& S, int cur, int xcd, hipStream_t st) {
   const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
   const int ntiles = ntx * nty;
@@ -1653,9 +1655,9 @@ int launch_tile2w(const KParams& P, const State& S, int cur, int xcd, hipStream_
   }
   const StepIO io = make_io(S, cur);
   if (P.stream_stores)
-    hipLaunchKernelGGL((k_step2w<TX, TY, true>), dim3(grid), dim3(2 * TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
+    hipLaunchKernelGGL((k_step2w<TX, TY, NT, true>), dim3(grid), dim3(NT), 0, st, P, io, ntx, ntiles, band, xcd);
   else
-    hipLaunchKernelGGL((k_step2w<TX, TY, false>), dim3(grid), dim3(2 * TX * TY), 0, st, P, io, ntx, ntiles, band, xcd);
+    hipLaunchKernelGGL((k_step2w<TX, TY, NT, false>), dim3(grid), dim3(NT), 0, st, P, io, ntx, ntiles, band, xcd);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1663,7 +1665,9 @@ int launch_step2(const KParams& P, const State& S, int cur, int tile_variant, in
   if (P.storage != STORE_FP32) return -1;
   switch (tile_variant) {
     case TWO_STEP_VARIANT + 3:
-      return launch_tile2w<32, 16>(P, S, cur, xcd_remap, st);
+      return launch_tile2w<32, 16, 1024>(P, S, cur, xcd_remap, st);
+    case TWO_STEP_VARIANT + 4:
+      return launch_tile2w<32, 8, 768>(P, S, cur, xcd_remap, st);
     case TWO_STEP_VARIANT:
       return launch_tile2<64, 8>(P, S, cur, xcd_remap, st);
     case TWO_STEP_VARIANT + 1:

@@ -20,10 +20,10 @@ FIELD_BITS = {"phi": 0, "T": 1, "ux": 2, "uy": 3, "p": 4, "fs": 5, "fl": 6, "rho
 TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4,
                  "unfused64x8": 5,  # two-kernel step, kept to measure the gain from fusion
                  "two64x8": 6, "two32x8": 7, "two32x16": 8,  # two steps per launch (FP32 storage)
-                 "two32x16w": 9}  # the same with two lanes per tile node
+                 "two32x16w": 9, "two32x8w": 10}  # the same with two and three lanes per tile node
 XCD_MODES = (0, 1, 2)  # row-major tiles; one row-major band per XCD; one column band per XCD
 TILE_NAMES = {v: k for k, v in TILE_VARIANTS.items()}
-TWO_STEP_VARIANTS = ("two64x8", "two32x8", "two32x16", "two32x16w")  # FP32 storage only (lbm_set_launch refuses them otherwise)
+TWO_STEP_VARIANTS = ("two64x8", "two32x8", "two32x16", "two32x16w", "two32x8w")  # FP32 storage only (lbm_set_launch refuses them otherwise)
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
 STORE_MODES = {"auto": 0, "cached": 1, "streaming": 2}  # lbm_set_store_mode  # LBM_STORE_FP32 / _FP16_SHIFT / _BF16_SHIFT
 
