@@ -389,11 +389,12 @@ def main():
         ptile, pxcd = pick_launch(ps, args)
         psecs, _ = time_steps(ps, args.probe_steps, 10)
         pl = psecs / args.probe_steps
+        pspl = 2 if ptile in lbm.TWO_STEP_VARIANTS else 1  # node-steps per launch
         pach = bpn * Np / pl / 1e9
         out["hbm_probe"] = {
             "workload": "probe4096: 4096x2048 sessile droplet R=640 (same physics), 2.3 GB working set",
             "steps": args.probe_steps, "MLUPS": round(Np * args.probe_steps / psecs / 1e6, 1),
-            "tile": ptile, "xcd_remap": pxcd,
+            "tile": ptile, "xcd_remap": pxcd, "steps_per_launch": pspl,
             "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("probe4096", args.storage, ptile, pxcd),
         }
@@ -411,7 +412,7 @@ def main():
         torch.cuda.synchronize()
         out["hbm_probe"]["plain_copy_GBps"] = round(2 * cn * 4 * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9, 1)
         if out["hbm_probe"]["traffic"]:
-            out["hbm_probe"]["traffic_GBps"] = round(out["hbm_probe"]["traffic"] / pl / 1e9, 1)
+            out["hbm_probe"]["traffic_GBps"] = round(out["hbm_probe"]["traffic"] / (pl * pspl) / 1e9, 1)
         del ca, cb
         torch.cuda.empty_cache()
         # the unfused two-kernel step on the same grid: what fusion saves
