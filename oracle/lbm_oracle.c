@@ -18,6 +18,11 @@
  * (39)-(41) wetting boundary.  Where the paper is silent or garbled the
  * reading taken is named inline; the full list lives with the design notes.
  *
+ * Parity unpinned: the -grad p and c_s^2 grad S terms of F~ (Eq. (33)).  No
+ * closed form in the tests reaches them (they need flow across a pressure or
+ * source gradient), so only this definition and parity with the GPU library
+ * fix them.
+ *
  * Plain loops; OpenMP splits rows of each pass (results do not depend on the
  * thread count: no reduction runs in parallel).
  */
