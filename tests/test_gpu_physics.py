@@ -10,6 +10,9 @@
   (Eq. (44)), with expansion and shrinkage.
 - The droplet setup of Sec. 4.2.1 (C_p,s/C_p,l = 0.5, k_s/k_l = 3.8,
   Pr = 7.25, Ste = 0.02, theta = 86.4 deg) against the oracle.
+- Channel flows under a body force: the pressure-level drift of Eq. (36)
+  against its closed form, and a liquid layer under a lighter gas against
+  the one-dimensional momentum balance, both also against the oracle.
 """
 import math
 import pathlib
@@ -177,3 +180,77 @@ def test_sessile512_freezes_with_the_area_expansion_of_its_density_ratio():
     # measured 1.155 at R = 80 (1.117 in the oracle at R = 20: the tip sharpens with resolution)
     for k in ("lattice_boltzmann", "experiment"):
         assert abs(ar - float(golden[k])) <= 0.03 * float(golden[k]), (k, ar)
+
+
+# Channel flows driven by a body force along the walls, tau_f = 1/2 + sqrt(3)/4
+# (no wall slip), FP32 storage; the closed forms are those of the oracle pins.
+_EXACT_WALL_NU = math.sqrt(3.0) / 12.0
+
+
+def test_channel_flow_pressure_drift_and_profile(oracle_mod):
+    """Eq. (36) with tau = tau_f moves the pressure level uniformly by
+    c_s^2 <F_0> / (2 tau_f (1 - w_0)) per step, F_0 = -w_0 u.F~ / c_s^2,
+    while the velocity keeps the exact parabola (oracle: 2.4e-7 and 7.9e-6)."""
+    lbm = _lbm()
+    nx, ny, g = 4, 32, 1e-5
+    cs2, w0, tau = 1.0 / 3.0, 4.0 / 9.0, 0.5 + math.sqrt(3.0) / 4.0
+    p = W.default_params(nx, ny, T_bottom=2.0, rho_s=1.0, mu_l=_EXACT_WALL_NU, gx=g)
+    s = lbm.Solver(p, np.ones(nx * ny), np.full(nx * ny, 2.0))
+    s.step(10000)
+    p1 = s.fields(["p"])["p"].astype(np.float64)
+    s.step(1000)
+    f = {k: v.astype(np.float64) for k, v in s.fields(["ux", "p", "rho"]).items()}
+    drift = (f["p"].mean() - p1.mean()) / 1000.0
+    rate = cs2 / (1.0 - w0) * (-w0 / cs2 * g * np.mean(f["rho"] * f["ux"])) / (2.0 * tau)
+    y = np.arange(ny)
+    exact = g / (2.0 * _EXACT_WALL_NU) * (y + 0.5) * (ny - 0.5 - y)
+    uerr = np.abs(f["ux"] - exact[:, None]).max() / exact.max()
+    o = oracle_mod.OracleSolver(p, np.ones(nx * ny), np.full(nx * ny, 2.0), threads=1)
+    o.step(11000)
+    fo = o.fields(["ux", "p"])
+    du = np.abs(f["ux"] - fo["ux"]).max() / exact.max()
+    dp = np.abs(f["p"] - fo["p"]).max() / np.abs(fo["p"]).max()
+    print(f"drift {drift:.6e} closed form {rate:.6e} rel {(drift - rate) / abs(rate):.2e}; "
+          f"|u - parabola| {uerr:.2e}; GPU vs oracle u {du:.2e} p {dp:.2e}", flush=True)
+    # measured in FP32: drift within 8.6e-4 of the closed form, parabola
+    # within 7.0e-6, oracle within 1.2e-5 (u) and 6.2e-5 (p)
+    assert abs(drift - rate) < 1e-2 * abs(rate)
+    assert uerr < 1e-4
+    assert du < 1e-4 and dp < 1e-3
+
+
+def test_layered_channel_flow_against_the_momentum_balance(oracle_mod):
+    """Liquid under a gas ten times lighter, equal nu, W = 4: the steady profile
+    against d/dy(mu du/dy) = -rho g built from the GPU's own rho(y), mu(y)
+    (oracle: 6.7 %, the diffuse interface's discretisation error), and
+    against the oracle node by node."""
+    lbm = _lbm()
+    nx, ny, g, rg, width = 4, 32, 1e-5, 0.1, 4.0
+    nu = _EXACT_WALL_NU
+    p = W.default_params(nx, ny, W=width, T_bottom=2.0, rho_s=1.0, rho_g=rg, mu_l=nu, mu_g=rg * nu, gx=g)
+    phi0 = W.flat_layer(nx, ny, ny / 2, width)
+    s = lbm.Solver(p, phi0, np.full(nx * ny, 2.0))
+    s.step(10000)
+    f = {k: v.astype(np.float64) for k, v in s.fields(["ux", "phi", "rho"]).items()}
+    u, phi, rho = f["ux"][:, 1], f["phi"][:, 1], f["rho"][:, 1]
+    pc = np.clip(phi, 0.0, 1.0)
+    mu = pc * nu + (1.0 - pc) * rg * nu
+    A = np.zeros((ny, ny))
+    for j in range(ny):
+        lo = 0.5 * (mu[j] + mu[j - 1]) if j > 0 else mu[0]
+        hi = 0.5 * (mu[j] + mu[j + 1]) if j < ny - 1 else mu[-1]
+        A[j, j] = -(lo + hi) - (lo if j == 0 else 0.0) - (hi if j == ny - 1 else 0.0)
+        if j > 0:
+            A[j, j - 1] = lo
+        if j < ny - 1:
+            A[j, j + 1] = hi
+    ref = np.linalg.solve(A, -rho * g)
+    err = np.abs(u - ref).max() / ref.max()
+    o = oracle_mod.OracleSolver(p, phi0, np.full(nx * ny, 2.0), threads=1)
+    o.step(10000)
+    uo = o.fields(["ux"])["ux"]
+    du = np.abs(f["ux"] - uo).max() / uo.max()
+    print(f"layered: |u - balance| {err:.3e}; GPU vs oracle {du:.2e}", flush=True)
+    # measured in FP32: 6.65e-2 (as the oracle) and 2.6e-5 from the oracle
+    assert err < 8e-2
+    assert du < 1e-3
