@@ -18,10 +18,9 @@
  * (39)-(41) wetting boundary.  Where the paper is silent or garbled the
  * reading taken is named inline; the full list lives with the design notes.
  *
- * Parity unpinned: the -grad p and c_s^2 grad S terms of F~ (Eq. (33)).  No
- * closed form in the tests reaches them (they need flow across a pressure or
- * source gradient), so only this definition and parity with the GPU library
- * fix them.
+ * Parity unpinned: the c_s^2 grad S term of F~ (Eq. (33)).  No closed form
+ * in the tests reaches it (it needs flow across a gradient of the mass
+ * source), so only this definition and parity with the GPU library fix it.
  *
  * Plain loops; OpenMP splits rows of each pass (results do not depend on the
  * thread count: no reduction runs in parallel).

@@ -12,7 +12,8 @@
   Pr = 7.25, Ste = 0.02, theta = 86.4 deg) against the oracle.
 - Channel flows under a body force: the pressure-level drift of Eq. (36)
   against its closed form, and a liquid layer under a lighter gas against
-  the one-dimensional momentum balance, both also against the oracle.
+  the one-dimensional momentum balance, and a channel under hydrostatic
+  gravity, all also against the oracle.
 """
 import math
 import pathlib
@@ -266,3 +267,30 @@ def test_layered_channel_flow_against_the_momentum_balance(oracle_mod, storage):
     # FP16 6.85e-2 and 1.8e-3; BF16 6.95e-2 and 4.3e-3
     assert err < 8e-2
     assert du < {"fp32": 1e-3, "fp16": 1e-2, "bf16": 2e-2}[storage]
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_channel_flow_under_hydrostatic_gravity(oracle_mod, storage):
+    """One phase under g_x along and g_y = -1e-3 across the walls: hydrostatic
+    pressure and the unchanged parabola, which needs the -grad(p) term of F~
+    (oracle: 9.1e-5 of the peak with it, 6.2e-3 without)."""
+    lbm = _lbm()
+    nx, ny, g, gy = 4, 32, 1e-5, -1e-3
+    p = W.default_params(nx, ny, T_bottom=2.0, rho_s=1.0, mu_l=_EXACT_WALL_NU, gx=g, gy=gy)
+    s = lbm.Solver(dict(p, storage=lbm.STORAGE[storage]), np.ones(nx * ny), np.full(nx * ny, 2.0))
+    s.step(10000)
+    f = {k: v.astype(np.float64) for k, v in s.fields(["ux", "p"]).items()}
+    y = np.arange(ny)
+    exact = g / (2.0 * _EXACT_WALL_NU) * (y + 0.5) * (ny - 0.5 - y)
+    uerr = np.abs(f["ux"] - exact[:, None]).max() / exact.max()
+    slope = np.polyfit(y, f["p"][:, 1], 1)[0]
+    o = oracle_mod.OracleSolver(p, np.ones(nx * ny), np.full(nx * ny, 2.0), threads=1)
+    o.step(10000)
+    du = np.abs(f["ux"] - o.fields(["ux"])["ux"]).max() / exact.max()
+    print(f"{storage} hydrostatic: |u - parabola| {uerr:.2e}; dp/dy {slope:.6e}; GPU vs oracle u {du:.2e}", flush=True)
+    # measured: FP32 9.3e-5 from the parabola, 1.8e-5 from the oracle, slope
+    # within 2.3e-4; FP16 2.7e-3 and 2.7e-3 (its storage noise, as in the
+    # channel without g_y), slope within 2.3e-5
+    assert abs(slope - gy) < 1e-3 * abs(gy)
+    tol = {"fp32": 5e-4, "fp16": 1e-2}[storage]
+    assert uerr < tol and du < tol
