@@ -297,6 +297,24 @@ int lbm_mlp_gradient(lbm_mlp* m, const float* d_x, const float* d_t, const float
 int lbm_mlp_train(lbm_mlp* m, const float* d_x, const float* d_t, const float* d_mask, int32_t n, const float* w3,
                   float lr, int32_t steps, double* host_loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward pass of lbm_mlp_forward without a handle and without any
+ * allocation.  d_params: device FP32 parameters of `ensemble` members in the
+ * layout of lbm_mlp_set_params (ensemble x lbm_mlp_param_count floats);
+ * d_x [n][5], d_y [ensemble][n][3] as for lbm_mlp_forward, all device
+ * memory the caller owns.  The BF16 copies the kernels read are packed into
+ * a static device buffer of the library (about 1.4 MB, held by every GPU it
+ * runs on until the process ends), so ensemble is limited to
+ * 1..LBM_MLP_NOALLOC_MAX_ENSEMBLE and n to 1..2^26 (else LBM_EINVAL).
+ * Asynchronous on hip_stream (NULL = default stream); outputs equal
+ * lbm_mlp_forward's with the same parameters bit for bit.  All calls on one
+ * GPU share the buffer: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialised by the caller. */
+#define LBM_MLP_NOALLOC_MAX_ENSEMBLE 16
+int lbm_mlp_forward_noalloc(const float* d_params, int32_t ensemble, const float* d_x, int32_t n, float* d_y,
+                            void* hip_stream);
+
 const char* lbm_mlp_last_error(void);
 void lbm_mlp_destroy(lbm_mlp* m);
 

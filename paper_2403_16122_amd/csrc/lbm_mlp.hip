@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -433,6 +434,49 @@ uint64_t splitmix64(uint64_t& s) {
   return z ^ (z >> 31);
 }
 
+// ---- Forward pass without allocation ---------------------------------------
+// lbm_mlp_forward_noalloc packs the caller's FP32 parameters into this
+// library-owned buffer (the BF16 copies the matrix cores read, then the
+// padded FP32 biases) and runs the forward kernel from there.  Each GPU the
+// library runs on holds its own copy until the process ends; host code uses
+// the per-device address from hipGetSymbolAddress, never the symbol itself.
+constexpr int NOALLOC_MAX_E = 16;
+constexpr int NOALLOC_MAX_N = 1 << 26;
+constexpr size_t NOALLOC_PACK_BYTES = (size_t)NOALLOC_MAX_E * NPACK * sizeof(__bf16);
+constexpr size_t NOALLOC_BYTES = NOALLOC_PACK_BYTES + (size_t)NOALLOC_MAX_E * NBIAS * sizeof(float);
+static_assert(NOALLOC_PACK_BYTES % 256 == 0, "the bias block must stay 256-byte aligned");
+static_assert(NOALLOC_MAX_E == LBM_MLP_NOALLOC_MAX_ENSEMBLE, "header limit");
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int scratch_on_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return mdev_error(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) {
+    g_mlp_error = "device ordinal beyond the library's table of scratch addresses";
+    return LBM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return mdev_error(e, "hipGetSymbolAddress(scratch)");
+    if (!p) {
+      g_mlp_error = "hipGetSymbolAddress(scratch) returned no address";
+      return LBM_EDEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
 }  // namespace
 
 struct lbm_mlp {
@@ -613,6 +657,38 @@ int lbm_mlp_forward(lbm_mlp* m, const float* d_x, int32_t n, float* d_y) {
   a.np = np_of(n);
   hipLaunchKernelGGL(k_mlp_rows<false>, dim3((n + SAMPLES_PER_BLOCK - 1) / SAMPLES_PER_BLOCK, m->E), dim3(256), 0,
                      m->stream, a);
+  MLP_CK(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm_mlp_forward_noalloc(const float* d_params, int32_t ensemble, const float* d_x, int32_t n, float* d_y,
+                            void* hip_stream) {
+  if (!d_params || !d_x || !d_y || n < 1) return LBM_EINVAL;
+  if (ensemble < 1 || ensemble > NOALLOC_MAX_E || n > NOALLOC_MAX_N) {
+    g_mlp_error = "lbm_mlp_forward_noalloc: ensemble must be 1.." + std::to_string(NOALLOC_MAX_E) +
+                  " and n at most " + std::to_string(NOALLOC_MAX_N) + " (the static buffer's limits)";
+    return LBM_EINVAL;
+  }
+  void* base = nullptr;
+  int rc = scratch_on_current_device(&base);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  __bf16* pack = (__bf16*)base;
+  float* bias = (float*)((char*)base + NOALLOC_PACK_BYTES);
+  // every packed value and bias of members 0..ensemble-1 is rewritten here,
+  // so nothing left by an earlier call is read
+  const int total = ensemble * NPACK;
+  hipLaunchKernelGGL(k_mlp_pack, dim3((total + 255) / 256), dim3(256), 0, st, d_params, pack, bias, (int)ensemble);
+  MLP_CK(hipGetLastError());
+  RowsArgs a{};
+  a.x = d_x;
+  a.y = d_y;
+  a.pack = pack;
+  a.bias = bias;
+  a.n = n;
+  a.np = np_of(n);
+  hipLaunchKernelGGL(k_mlp_rows<false>, dim3((n + SAMPLES_PER_BLOCK - 1) / SAMPLES_PER_BLOCK, ensemble), dim3(256), 0,
+                     st, a);
   MLP_CK(hipGetLastError());
   return LBM_OK;
 }

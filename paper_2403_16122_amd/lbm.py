@@ -37,7 +37,7 @@ EXPORTED = [
     "lbm_batch_autotune", "lbm_batch_set_store_mode", "lbm_batch_step", "lbm_batch_results", "lbm_batch_fields",
     "lbm_batch_last_error", "lbm_batch_destroy", "lbm_shape_of",
     "lbm_mlp_param_count", "lbm_mlp_create", "lbm_mlp_set_params", "lbm_mlp_get_params", "lbm_mlp_forward",
-    "lbm_mlp_gradient", "lbm_mlp_train", "lbm_mlp_last_error", "lbm_mlp_destroy",
+    "lbm_mlp_gradient", "lbm_mlp_train", "lbm_mlp_last_error", "lbm_mlp_destroy", "lbm_mlp_forward_noalloc",
 ]
 DROP_STATUS = {0: "queued", 1: "running", 2: "frozen", 3: "limit", 4: "nonfinite"}
 
@@ -137,6 +137,7 @@ def load_library():
     L.lbm_mlp_set_params.argtypes = [vp, fp, C.c_size_t]
     L.lbm_mlp_get_params.argtypes = [vp, fp, C.c_size_t]
     L.lbm_mlp_forward.argtypes = [vp, vp, C.c_int32, vp]
+    L.lbm_mlp_forward_noalloc.argtypes = [vp, C.c_int32, vp, C.c_int32, vp, vp]
     L.lbm_mlp_gradient.argtypes = [vp, vp, vp, vp, C.c_int32, fp, fp, dp]
     L.lbm_mlp_train.argtypes = [vp, vp, vp, vp, C.c_int32, fp, C.c_float, C.c_int32, dp]
     L.lbm_mlp_last_error.argtypes = []
@@ -481,3 +482,32 @@ class MLP:
                                          C.c_void_p(mask.data_ptr()), n, self._fp(w3), float(lr), int(steps),
                                          _dptr(loss)), "lbm_mlp_train")
         return loss
+
+
+MLP_NOALLOC_MAX_ENSEMBLE = 16  # LBM_MLP_NOALLOC_MAX_ENSEMBLE
+
+
+def mlp_forward_noalloc(params, x, y, stream=None):
+    """lbm_mlp_forward_noalloc: the network's forward pass from device FP32
+    parameters ``params`` [ensemble][param_count] for device inputs ``x``
+    [n][5] into the caller's device output ``y`` [ensemble][n][3] (all
+    contiguous float32 torch tensors on the current device).  The library
+    allocates nothing; calls overlapping on one GPU race."""
+    import torch
+
+    L = load_library()
+    P = int(L.lbm_mlp_param_count())
+    for name, t in (("params", params), ("x", x), ("y", y)):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    if params.dim() != 2 or params.shape[1] != P or x.dim() != 2 or x.shape[1] != 5:
+        raise ValueError("expected params [ensemble][param_count] and x [n][5]")
+    E, n = params.shape[0], x.shape[0]
+    if tuple(y.shape) != (E, n, 3):
+        raise ValueError(f"expected y of shape ({E}, {n}, 3)")
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    rc = L.lbm_mlp_forward_noalloc(C.c_void_p(params.data_ptr()), E, C.c_void_p(x.data_ptr()), n,
+                                   C.c_void_p(y.data_ptr()), C.c_void_p(st.cuda_stream))
+    if rc != LBM_OK:
+        raise LbmError(rc, "lbm_mlp_forward_noalloc", L.lbm_mlp_last_error().decode())
+    return y
