@@ -1,14 +1,19 @@
 """Throughput of the fused coupled-lattice step on one MI355X.
 
 A step is one time step of all three D2Q9 lattices (phase field, flow,
-enthalpy) over the whole grid; the default workload is the 512x256 sessile
-droplet (R = 80, theta = 90, rho_s/rho_l = 0.9, Ste = 0.1, Bond = 0.1, FP32
-populations).  Inputs are resident in HBM before the timed region.
+enthalpy) over the whole grid.  The headline workload is the largest
+single-GPU configuration: the 1024x512 droplet (R = 160) with gas bubbles,
+contact angle and bubble count from the seed, chi = 1, rho_s/rho_l = 0.9,
+Ste = 0.1, FP32 populations; the same droplet is also timed with FP16 and
+BF16 population storage.  Inputs are resident in HBM before the timed
+region.
 
-Prints one JSON line with MLUPS, the roofline of the step kernel (HBM
-bound, algorithmic 256 B per node update), the FP64 oracle timed on the host
-cores, and the same step kernel on a 4096x2048 grid whose 2.3 GB working
-set does not fit the 256 MB Infinity Cache.
+Prints one JSON line with MLUPS, the roofline of the dominant step kernel
+on a 4096x2048 grid whose 2.3 GB state does not fit the 256 MB Infinity
+Cache (algorithmic 256 B per node update; the HBM traffic rocprofv3
+measured for that launch beside it), the 512x256 droplet and its run to
+full solidification, the batched sweep, the surrogate network, and the
+FP64 oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -217,7 +222,7 @@ def host_io(lbm, params, phi0, T0, N, steps, step_secs):
 
 
 def to_frozen(lbm, params, phi0, T0, tile, xcd):
-    """The bench's droplet from its initial state until 1 % of its liquid is
+    """The 512x256 droplet from its initial state until 1 % of its liquid is
     left (diagnostics every 5000 steps): wall time, steps, and the frozen
     shape."""
     import torch
@@ -247,29 +252,73 @@ def to_frozen(lbm, params, phi0, T0, tile, xcd):
             "note": "from the initial state, launch as timed above; diagnostics every 5000 steps inside the wall time"}
 
 
-def oracle_rate(oracle, params, phi0, T0, budget_s: float, threads: int):
-    """MLUPS of the FP64 oracle over `budget_s` seconds of steps from the
-    initial state, and the number of steps taken."""
+def oracle_rate(oracle, params, phi0, T0, threads: int, budget_s: float = 0.0, steps: int = 0):
+    """MLUPS of the FP64 oracle from the initial state: `steps` steps, or
+    as many as fit in `budget_s` seconds (in chunks of 5)."""
     o = oracle.OracleSolver(params, phi0, T0, threads=threads)
     n = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        o.step(5)
-        n += 5
+    if steps > 0:
+        o.step(steps)
+        n = steps
+    else:
+        while time.perf_counter() - t0 < budget_s:
+            o.step(5)
+            n += 5
     dt = time.perf_counter() - t0
+    del o
     return params["nx"] * params["ny"] * n / dt / 1e6, n, dt
 
 
-def cpu_baseline(params, phi0, T0, budget_s: float):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(W, params, phi0, T0, workload: str, budget_s: float, gpu_rates: dict):
+    """The FP64 oracle on the host: the headline workload for ~budget_s
+    seconds on every host thread this process may use and for a third of it
+    on one thread, then the 128x64 case (all 2000 steps) and slices of the
+    512x256 and 4096x2048 cases, each with GPU MLUPS of the same workload
+    beside it.  The oracle is rebuilt from its source with -O3 -march=native
+    for this host (same bits as the in-tree build: FP64, no FMA
+    contraction)."""
+    import tempfile
+
     import oracle
 
-    cores = oracle.oracle.default_threads()
-    v, n, dt = oracle_rate(oracle, params, phi0, T0, budget_s, cores)
-    v1, n1, dt1 = oracle_rate(oracle, params, phi0, T0, budget_s / 3, 1)
-    return dict(value=round(v, 3), unit="MLUPS", cores=cores, kind="oracle",
-                sample=f"{n} steps of the same workload from its initial state ({dt:.1f} s, FP64, OpenMP rows)",
-                single_thread={"value": round(v1, 3), "unit": "MLUPS", "cores": 1,
-                               "sample": f"{n1} steps from the initial state ({dt1:.1f} s, FP64, one thread)"})
+    build = "gcc -O3 -march=native -fopenmp (built on this host)"
+    try:
+        oracle.oracle.use_library(oracle.oracle.build_native(tempfile.mkdtemp(prefix="lbm_oracle_")))
+    except Exception as e:  # a host without gcc: time the in-tree -O3 build instead
+        build = f"in-tree gcc -O3 build (native build failed: {e})"
+    cores = oracle.oracle.host_threads()
+    v, n, dt = oracle_rate(oracle, params, phi0, T0, cores, budget_s=budget_s)
+    v1, n1, dt1 = oracle_rate(oracle, params, phi0, T0, 1, budget_s=budget_s / 3)
+    out = dict(value=round(v, 3), unit="MLUPS", cores=cores, kind="oracle",
+               sample=f"{n} steps of {workload} from its initial state ({dt:.1f} s, FP64, OpenMP over rows)",
+               nproc=os.cpu_count(), affinity=len(os.sched_getaffinity(0)),
+               omp_num_threads=os.environ.get("OMP_NUM_THREADS"), cpu_model=cpu_model(), build=build,
+               single_thread={"value": round(v1, 3), "unit": "MLUPS", "cores": 1,
+                              "sample": f"{n1} steps from the initial state ({dt1:.1f} s)"},
+               gpu_MLUPS=gpu_rates.get(workload))
+    slices = {}
+    for name, steps, steps1 in (("sessile128", 2000, 2000), ("sessile512", 200, 40), ("probe4096", 10, 1)):
+        pp, pphi, pT, _ = W.workload(name, seed=0)
+        pp["storage"] = 0
+        r, _, t = oracle_rate(oracle, pp, pphi, pT, cores, steps=steps)
+        r1, _, t1 = oracle_rate(oracle, pp, pphi, pT, 1, steps=steps1)
+        slices[name] = {"steps": steps, "MLUPS": round(r, 3), "seconds": round(t, 2),
+                        "single_thread": {"steps": steps1, "MLUPS": round(r1, 3), "seconds": round(t1, 2)},
+                        "gpu_MLUPS": gpu_rates.get(name)}
+        note(f"oracle {name}: {r:.2f} MLUPS on {cores} threads, {r1:.2f} on one")
+    out["slices"] = slices
+    return out
 
 
 def note(msg: str):
@@ -277,19 +326,67 @@ def note(msg: str):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def describe(name: str, params: dict, meta: dict, storage: str) -> str:
+    if name == "bubbles1024":
+        rb = [b[2] for b in meta["bubbles"]]
+        return (f"bubbles1024: {params['nx']}x{params['ny']} droplet R={meta['R']:g} lu with {len(rb)} gas bubbles "
+                f"(r {min(rb):.1f}-{max(rb):.1f} lu), contact angle {meta['theta']:.1f} deg, chi=1, "
+                f"rho_s/rho_l {params['rho_s']:g}, Ste 0.1, W=4, M=0.1, rho_l/rho_g=1000, "
+                f"{storage.upper()} populations (planar 2-D, seed 0)")
+    if name in ("sessile512", "probe4096"):
+        return (f"{name}: {params['nx']}x{params['ny']} sessile droplet R={meta['R']:g} lu, theta {meta['theta']:g}, "
+                f"rho_s/rho_l {params['rho_s']:g}, Ste 0.1, Bond 0.1, W=4, M=0.1, rho_l/rho_g=1000, "
+                f"{storage.upper()} populations (planar 2-D)")
+    return f"{name}: {params['nx']}x{params['ny']}, {storage.upper()} populations"
+
+
+def kernel_name(tile: str) -> str:
+    import paper_2403_16122_amd.lbm as lbm
+
+    if tile in lbm.TWO_STEP_VARIANTS:
+        return ("k_step2w" if tile.endswith("w") else "k_step2") + " (two fused collide + pull-stream steps per launch)"
+    return "k_step (fused collide + pull-stream)"
+
+
+def timed_run(lbm, W, name: str, storage: str, steps: int, warmup: int, args):
+    """One workload in one storage format: autotuned launch, `steps` timed
+    steps after `warmup`; returns (record, seconds, tile, xcd)."""
+    import torch
+
+    params, phi0, T0, meta = W.workload(name, seed=0)
+    params["storage"] = lbm.STORAGE[storage]
+    N = params["nx"] * params["ny"]
+    s = lbm.Solver(params, phi0, T0)
+    tile, xcd = pick_launch(s, args)
+    torch.cuda.synchronize()
+    secs, wall = time_steps(s, steps, warmup)
+    d = s.diag()
+    if d["rc"] != 0:
+        print(f"bench.py: non-finite state after the timed steps of {name} {storage} ({d})", file=sys.stderr)
+        sys.exit(3)
+    del s
+    torch.cuda.empty_cache()
+    spl = 2 if tile in lbm.TWO_STEP_VARIANTS else 1
+    rec = {"workload": name, "storage": storage, "steps": steps, "MLUPS": round(N * steps / secs / 1e6, 1),
+           "us_per_step": round(secs / steps * 1e6, 3), "tile": tile, "xcd_remap": xcd, "steps_per_launch": spl,
+           "state_MB": round(lbm.workspace_bytes(params) / 2 ** 20, 1)}
+    note(f"{name} {storage}: {rec['MLUPS']} MLUPS ({tile}, order {xcd})")
+    return rec, secs, wall, (params, phi0, T0, meta)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--workload", default="sessile512")
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="bubbles1024")
     ap.add_argument("--tile", default="auto", help="auto (library autotuner) or a name of lbm.TILE_VARIANTS")
     ap.add_argument("--no-xcd", action="store_true", help="round-robin workgroup dispatch (xcd mode 0)")
     ap.add_argument("--xcd", type=int, default=None, help="workgroup-to-XCD mapping mode 0/1/2 (fixed tiles only)")
     ap.add_argument("--storage", default="fp32", choices=("fp32", "fp16", "bf16"),
-                    help="population storage format (compute is FP32 in every case)")
+                    help="population storage format of the headline (compute is FP32 in every case)")
     ap.add_argument("--no-storage-variants", dest="storage_variants", action="store_false",
-                    help="skip the FP16/BF16 storage runs on the 4096x2048 probe")
+                    help="skip the FP16/BF16 storage runs")
     ap.add_argument("--probe-steps", type=int, default=100, help="steps on the 4096x2048 grid (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle timing budget (0: skip)")
     ap.add_argument("--sweep-droplets", type=int, default=256, help="droplets in the batched sweep (0: skip)")
@@ -299,6 +396,8 @@ def main():
                     help="skip running the 512x256 droplet to full solidification")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
                     help="skip training and scoring the surrogate network")
+    ap.add_argument("--no-others", dest="others", action="store_false",
+                    help="headline workload only (no 128x64 and 512x256 rates)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -322,28 +421,13 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    params, phi0, T0, meta = W.workload(args.workload, seed=0)
-    params["storage"] = lbm.STORAGE[args.storage]
-    bpn = BYTES_PER_NODE[args.storage]
+    head, secs, wall, (params, phi0, T0, meta) = timed_run(lbm, W, args.workload, args.storage, args.steps,
+                                                            args.warmup, args)
     N = params["nx"] * params["ny"]
-    solver = lbm.Solver(params, phi0, T0)
-    tile, xcd = pick_launch(solver, args)
-    torch.cuda.synchronize()
-    secs, wall = time_steps(solver, args.steps, args.warmup)
-    d = solver.diag()
-    if d["rc"] != 0:
-        print(f"bench.py: non-finite state after the timed steps ({d})", file=sys.stderr)
-        sys.exit(3)
-    mlups = N * args.steps / secs / 1e6
-    # a two-step launch processes 2 N node-steps; achieved counts the
-    # algorithmic bytes of those node-steps over the launch's duration
-    spl = 2 if tile in lbm.TWO_STEP_VARIANTS else 1
-    launch_s = secs * spl / args.steps
-    achieved = bpn * N * spl / launch_s / 1e9
-    traffic = measured_traffic(args.workload, args.storage, tile, xcd)
+    gpu_rates = {args.workload: head["MLUPS"]}
     out = {
         "metric": METRIC,
-        "value": round(mlups, 2),
+        "value": round(N * args.steps / secs / 1e6, 2),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
@@ -355,51 +439,60 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {params['nx']}x{params['ny']} sessile droplet R={meta['R']:g} lu, "
-                        f"theta {meta['theta']:g}, rho_s/rho_l {params['rho_s']:g}, Ste 0.1, Bond 0.1, "
-                        f"W=4, M=0.1, rho_l/rho_g=1000, {args.storage.upper()} populations (planar 2-D)",
-            "nx": params["nx"], "ny": params["ny"], "tile": tile, "xcd_remap": xcd, "storage": args.storage,
-            "parallelism": "single GPU",
-        },
-        "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": (("k_step2w" if tile.endswith("w") else "k_step2")
-                       + " (two fused collide + pull-stream steps per launch)" if spl == 2
-                       else "k_step (fused collide + pull-stream)"),
-            "steps_per_launch": spl,
-            "bytes_per_launch": bpn * N * spl,
-            "note": ("working set fits the 256 MB Infinity Cache at this size; see hbm_probe"
-                     + ("; bytes_per_launch counts 256 B per node-step for the launch's 2 N node-steps, while "
-                        "the launch itself reads and writes the state once" if spl == 2 else "")),
+            "workload": describe(args.workload, params, meta, args.storage),
+            "nx": params["nx"], "ny": params["ny"], "tile": head["tile"], "xcd_remap": head["xcd_remap"],
+            "storage": args.storage, "state_MB": head["state_MB"], "parallelism": "single GPU",
         },
         "wall_s": round(wall, 3),
     }
-    del solver
+    # the headline droplet in every population storage format (compute FP32)
+    formats = {args.storage: head}
+    if args.storage_variants:
+        for st in ("fp32", "fp16", "bf16"):
+            if st not in formats:
+                formats[st] = timed_run(lbm, W, args.workload, st, args.steps, args.warmup, args)[0]
+    out["storage_formats"] = formats
     out["host_io"] = host_io(lbm, params, phi0, T0, N, args.steps, secs)
-    if args.to_frozen and args.workload == "sessile512" and args.storage == "fp32":
-        out["to_frozen"] = to_frozen(lbm, params, phi0, T0, tile, xcd)
     torch.cuda.empty_cache()
-    note(f"{args.workload}: {out['value']} MLUPS ({tile}, order {xcd})")
+    if args.others:
+        # the 128x64 parity case and the 512x256 droplet (cache-resident sizes)
+        for name in ("sessile128", "sessile512"):
+            if name == args.workload:
+                continue
+            rec, _, _, (pp, pphi, pT, _m) = timed_run(lbm, W, name, "fp32", max(args.steps, 200), args.warmup, args)
+            gpu_rates[name] = rec["MLUPS"]
+            out.setdefault("other_workloads", {})[name] = rec
+            if name == "sessile512" and args.to_frozen:
+                out["to_frozen"] = to_frozen(lbm, pp, pphi, pT, rec["tile"], rec["xcd_remap"])
+            torch.cuda.empty_cache()
     if args.probe_steps > 0:
-        pp, pphi, pT, _ = W.workload("probe4096", seed=0)
-        pp["storage"] = params["storage"]
+        # the roofline: the dominant step kernel on a state beyond the Infinity Cache
+        prec, psecs, _, (pp, pphi, pT, _m) = timed_run(lbm, W, "probe4096", "fp32", args.probe_steps, 10, args)
+        gpu_rates["probe4096"] = prec["MLUPS"]
         Np = pp["nx"] * pp["ny"]
-        ps = lbm.Solver(pp, pphi, pT)
-        ptile, pxcd = pick_launch(ps, args)
-        psecs, _ = time_steps(ps, args.probe_steps, 10)
-        pl = psecs / args.probe_steps
-        pspl = 2 if ptile in lbm.TWO_STEP_VARIANTS else 1  # node-steps per launch
-        pach = bpn * Np / pl / 1e9
-        out["hbm_probe"] = {
-            "workload": "probe4096: 4096x2048 sessile droplet R=640 (same physics), 2.3 GB working set",
-            "steps": args.probe_steps, "MLUPS": round(Np * args.probe_steps / psecs / 1e6, 1),
-            "tile": ptile, "xcd_remap": pxcd, "steps_per_launch": pspl,
-            "achieved": round(pach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(pach / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("probe4096", args.storage, ptile, pxcd),
+        ptile, pxcd, pspl = prec["tile"], prec["xcd_remap"], prec["steps_per_launch"]
+        launch_s = psecs * pspl / args.probe_steps  # average duration of one launch (HIP events on its stream)
+        alg = BYTES_PER_NODE["fp32"] * Np * pspl    # 256 B per node update x node updates per launch
+        achieved = alg / launch_s / 1e9
+        traffic = measured_traffic("probe4096", "fp32", ptile, pxcd)
+        out["roofline"] = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kernel_name(ptile), "workload": describe("probe4096", pp, _m, "fp32"),
+            "tile": ptile, "xcd_remap": pxcd, "steps_per_launch": pspl, "launch_us": round(launch_s * 1e6, 2),
+            "bytes_per_launch": alg,
+            "note": ("achieved counts the algorithmic 256 B per node update for every node update the launch "
+                     "performs; measured on the 4096x2048 grid, whose 2.3 GB state exceeds the 256 MB Infinity "
+                     "Cache (the headline grid's does not)"
+                     + ("; a two-step launch reads and writes the state once, so this is an effective rate: "
+                        "hbm_traffic gives what the launch moves" if pspl == 2 else "")),
         }
+        if traffic:
+            out["roofline"]["hbm_traffic"] = {
+                "bytes_per_launch": traffic, "GBps": round(traffic / launch_s / 1e9, 1),
+                "frac": round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                "note": "rocprofv3 FETCH_SIZE + WRITE_SIZE of this launch shape, calibrated on a plain copy"}
         # practical bandwidth beside the nominal peak: a 2 GiB device copy
-        # (read + write) and the step's measured traffic per second
         cn = (2 << 30) // 4
         ca = torch.ones(cn, dtype=torch.float32, device="cuda")
         cb = torch.empty_like(ca)
@@ -410,42 +503,33 @@ def main():
             cb.copy_(ca)
         c1.record()
         torch.cuda.synchronize()
-        out["hbm_probe"]["plain_copy_GBps"] = round(2 * cn * 4 * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9, 1)
-        if out["hbm_probe"]["traffic"]:
-            out["hbm_probe"]["traffic_GBps"] = round(out["hbm_probe"]["traffic"] / (pl * pspl) / 1e9, 1)
+        out["roofline"]["plain_copy_GBps"] = round(2 * cn * 4 * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9, 1)
         del ca, cb
         torch.cuda.empty_cache()
+        probe = {"fp32": prec}
         # the unfused two-kernel step on the same grid: what fusion saves
+        ps = lbm.Solver(dict(pp, storage=0), pphi, pT)
         ps.set_launch("unfused64x8", pxcd)
         usecs, _ = time_steps(ps, args.probe_steps, 10)
-        ubpn = UNFUSED_BYTES_PER_NODE[args.storage]
-        out["hbm_probe"]["unfused"] = {
-            "launch": f"unfused64x8, order {pxcd}", "MLUPS": round(Np * args.probe_steps / usecs / 1e6, 1),
-            "bytes_per_node": ubpn, "achieved": round(ubpn * Np / (usecs / args.probe_steps) / 1e9, 1),
-            "fused_speedup": round(usecs / psecs, 3),
-        }
         del ps
         torch.cuda.empty_cache()
-        note(f"probe4096: {out['hbm_probe']['MLUPS']} MLUPS ({ptile}, order {pxcd})")
-        # the same probe with 16-bit population storage (FP32 compute)
-        if args.storage == "fp32" and args.storage_variants:
-            out["storage_variants"] = {}
+        ubpn = UNFUSED_BYTES_PER_NODE["fp32"]
+        probe["unfused_fp32"] = {
+            "launch": f"unfused64x8, order {pxcd}", "MLUPS": round(Np * args.probe_steps / usecs / 1e6, 1),
+            "bytes_per_node": ubpn, "achieved": round(ubpn * Np / (usecs / args.probe_steps) / 1e9, 1),
+            "fused_speedup": round(usecs / psecs, 3)}
+        if args.storage_variants:
             for st in ("fp16", "bf16"):
-                pp["storage"] = lbm.STORAGE[st]
-                vs = lbm.Solver(pp, pphi, pT)
-                vtile, vxcd = pick_launch(vs, args)
-                vsecs, _ = time_steps(vs, args.probe_steps, 10)
-                vl = vsecs / args.probe_steps
-                vach = BYTES_PER_NODE[st] * Np / vl / 1e9
-                out["storage_variants"][st] = {
-                    "workload": "probe4096", "MLUPS": round(Np * args.probe_steps / vsecs / 1e6, 1),
-                    "tile": vtile, "xcd_remap": vxcd, "bytes_per_node": BYTES_PER_NODE[st],
-                    "achieved": round(vach, 1), "unit": "GB/s", "frac": round(vach / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic("probe4096", st, vtile, vxcd),
-                }
-                del vs
-                torch.cuda.empty_cache()
-                note(f"probe4096 {st}: {out['storage_variants'][st]['MLUPS']} MLUPS ({vtile}, order {vxcd})")
+                vrec, vsecs, _, _ = timed_run(lbm, W, "probe4096", st, args.probe_steps, 10, args)
+                vl = vsecs * vrec["steps_per_launch"] / args.probe_steps
+                vach = BYTES_PER_NODE[st] * Np * vrec["steps_per_launch"] / vl / 1e9
+                vtr = measured_traffic("probe4096", st, vrec["tile"], vrec["xcd_remap"])
+                vrec.update({"bytes_per_node": BYTES_PER_NODE[st], "achieved": round(vach, 1), "unit": "GB/s",
+                             "frac": round(vach / HBM_PEAK_GBS, 4), "traffic": vtr})
+                if vtr:
+                    vrec["traffic_GBps"] = round(vtr / vl / 1e9, 1)
+                probe[st] = vrec
+        out["probe4096"] = probe
     if args.sweep_droplets > 0:
         out["sweep"] = sweep_bench(lbm, W, args.sweep_droplets, args.sweep_plain, args.sweep_time_limit)
         torch.cuda.empty_cache()
@@ -453,7 +537,7 @@ def main():
         out["surrogate"] = surrogate_bench(out.get("sweep"))
         note("surrogate done")
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(params, phi0, T0, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(W, params, phi0, T0, args.workload, args.cpu_seconds, gpu_rates)
     print(json.dumps(out), flush=True)
 
 

@@ -39,22 +39,56 @@ class _Diag(C.Structure):
     ]
 
 
+# FP64 throughout, no fast-math and no FMA contraction, so every build of the
+# same source (any -O level, any -march) gives the same bits.
+_CFLAGS = ["-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-std=c11", "-D_DEFAULT_SOURCE", "-Wall", "-Wextra"]
+
+
 def build_oracle(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, no fast-math, OpenMP over rows)."""
+    """Compile the oracle in-tree with gcc -O3 (portable: the library travels
+    with the tree to other hosts)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-std=c11",
-               "-D_DEFAULT_SOURCE", "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        cmd = ["gcc", "-O3"] + _CFLAGS + ["-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
 
 
+def build_native(out_dir: str) -> str:
+    """The same source built with gcc -O3 -march=native into out_dir, for
+    timing the oracle on the host it runs on."""
+    out = os.path.join(out_dir, "liblbm_oracle_native.so")
+    subprocess.run(["gcc", "-O3", "-march=native"] + _CFLAGS + ["-o", out, _SRC, "-lm"], check=True)
+    return out
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (before the
+    first solver is made)."""
+    global _LIB, _lib
+    _LIB = path
+    _lib = None
+
+
 _lib = None
 
 
+def host_threads() -> int:
+    """Host threads this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
 def default_threads() -> int:
-    """Rows are split over at most 16 host threads."""
-    return max(1, min(16, os.cpu_count() or 1))
+    """Rows are split over at most 16 host threads by default."""
+    return max(1, min(16, host_threads()))
 
 
 def lib_path() -> str:
