@@ -139,11 +139,13 @@ const char* lbm_last_error(void);
  * recomputed per tile.  5: the unfused two-kernel step on 64x8 tiles (a
  * macro pass writes phi, rho and f_s^H of every node, then the collide pass
  * reads its halo from there), bitwise equal to the fused step and kept to
- * measure what fusion saves; lbm_autotune does not consider it.  6-10
- * (FP32 storage only, else LBM_EINVAL): two steps per launch on 64x8, 32x8,
- * 32x16 tiles, then on 32x16 tiles with two lanes per tile node (9: one
+ * measure what fusion saves; lbm_autotune does not consider it.  6-10:
+ * two steps per launch on 64x8, 32x8, 32x16 tiles (6-8: FP32 storage only,
+ * else LBM_EINVAL), then on 32x16 tiles with two lanes per tile node (9: one
  * cell of each step per lane, four waves per SIMD) and on 32x8 tiles with
- * three (10: two workgroups per CU, six waves per SIMD) -- each workgroup
+ * three (10: two workgroups per CU, six waves per SIMD; 9 and 10 in every
+ * storage format, the first step's 16-bit populations kept in LDS exactly
+ * as a single step stores them) -- each workgroup
  * runs the first step on its tile plus 3 columns and 2 rows
  * of halo from global memory, keeps those results in LDS and runs the
  * second step on the tile from there, so the state crosses HBM once per two
@@ -165,8 +167,9 @@ int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap);
 int lbm_set_store_mode(lbm_ctx* c, int32_t mode);
 
 /* Time every launch shape for `reps` launches and keep the fastest per step
- * (written to the optional out-pointers): tile variants 0-4, and under FP32
- * storage the two-step variants 6-10 at half their time per launch.  The
+ * (written to the optional out-pointers): tile variants 0-4 and the
+ * two-step variants the storage format admits (6-10 under FP32, 9-10
+ * otherwise) at half their time per launch.  The
  * state is not advanced: each timed launch recomputes the next step(s) from
  * the same buffers.  Synchronises. */
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_remap);
@@ -225,9 +228,13 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
 int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, double freeze_frac,
                         int32_t use_graph);
 
-/* Tile shape (tile_variant 0..4 of lbm_set_launch) and whether each
- * droplet's tiles are kept on one XCD (xcd_group 1, default) or laid out
- * droplet after droplet (0); results are bitwise identical either way. */
+/* Tile shape (tile_variant 0..4 of lbm_set_launch, or the two-step variants
+ * 9 and 10 when the sampling interval is a multiple of 4; LBM_EINVAL
+ * otherwise) and whether each droplet's tiles are kept on one XCD
+ * (xcd_group 1, default) or laid out droplet after droplet (0); results are
+ * bitwise identical either way.  lbm_batch_autotune times the same set
+ * (per step).  With a two-step variant set, lbm_batch_configure refuses a
+ * sampling interval that is not a multiple of 4. */
 int lbm_batch_set_launch(lbm_batch* b, int32_t tile_variant, int32_t xcd_group);
 int lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* tile_variant, int32_t* xcd_group);
 /* Store mode of the batched step, as lbm_set_store_mode, except that mode 0

@@ -196,6 +196,12 @@ struct lbm_ctx {
 
 namespace {
 
+// Two steps per launch on one lane per node (variants 6-8) are built for FP32
+// storage only; every other variant for every format.
+bool variant_allowed(int v, int storage) {
+  return !lbmk::is_two_step(v) || storage == LBM_STORE_FP32 || lbmk::is_two_step_any_storage(v);
+}
+
 size_t part_bytes() { return (size_t)(lbmk::RED_BLOCKS + 1) * lbmk::RED_NVAL * sizeof(double); }
 
 size_t ws_size(const lbm_params* p) {
@@ -334,6 +340,7 @@ int lbm_step(lbm_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
   for (int32_t s = 0; s < nsteps;) {
     if (lbmk::is_two_step(c->tile_variant) && nsteps - s >= 2) {
+      c->K.seed = (unsigned)c->step;  // steps n and n + 1 seed 16-bit stochastic rounding
       if (lbmk::launch_step2(c->K, c->S, c->cur, c->tile_variant, c->xcd, c->stream))
         return dev_error(hipGetLastError(), "two-step kernel launch");
       c->cur ^= 1;
@@ -485,7 +492,7 @@ int lbm_set_launch(lbm_ctx* c, int32_t tile_variant, int32_t xcd_remap) {
   if (!c || tile_variant < 0 || tile_variant >= lbmk::NTILE_VARIANTS || xcd_remap < 0 ||
       xcd_remap >= lbmk::NXCD_MODES)
     return LBM_EINVAL;
-  if (lbmk::is_two_step(tile_variant) && c->P.storage != LBM_STORE_FP32) return LBM_EINVAL;
+  if (!variant_allowed(tile_variant, c->P.storage)) return LBM_EINVAL;
   c->tile_variant = tile_variant;
   c->xcd = xcd_remap;
   return LBM_OK;
@@ -514,10 +521,11 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* tile_variant, int32_t* xcd_r
   hipEvent_t e0 = ev.a, e1 = ev.b;
   float best = 1e30f;
   int bv = c->tile_variant, bx = c->xcd;
-  const int nv = c->P.storage == LBM_STORE_FP32 ? lbmk::NTILE_VARIANTS : lbmk::NTUNED_VARIANTS;
-  for (int v = 0; v < nv; ++v) {
+  c->K.seed = (unsigned)c->step;
+  for (int v = 0; v < lbmk::NTILE_VARIANTS; ++v) {
     const bool two = lbmk::is_two_step(v);
     if (v >= lbmk::NTUNED_VARIANTS && !two) continue;  // the unfused reference step
+    if (!variant_allowed(v, c->P.storage)) continue;
     for (int x = 0; x < lbmk::NXCD_MODES; ++x) {
       auto launch = [&]() {
         return two ? lbmk::launch_step2(c->K, c->S, c->cur, v, x, c->stream)

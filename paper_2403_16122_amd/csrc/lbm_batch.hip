@@ -214,7 +214,8 @@ int upload_map(lbm_batch* b) {
 int enqueue_chunk(lbm_batch* b, hipStream_t st) {
   // step numbers at the start of the interval (read from pinned memory when the copy runs)
   LBMB_CK(hipMemcpyAsync(b->d_steps(), b->h_steps, sizeof(unsigned) * b->slots, hipMemcpyHostToDevice, st));
-  for (int s = 0; s < b->sample_every; ++s)
+  const int per = lbmk::is_two_step_any_storage(b->tile_variant) ? 2 : 1;  // steps per launch
+  for (int s = 0; s < b->sample_every; s += per)
     if (lbmk::launch_batch(b->storage, b->tile_variant, false, b->nt, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(),
                            b->d_steps(), b->nblocks, s, st))
       return bdev_error(hipGetLastError(), "batch step launch");
@@ -517,6 +518,10 @@ int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, d
                         int32_t use_graph) {
   if (!b || sample_every < 2 || (sample_every & 1) || max_steps < 0 || !(freeze_frac > 0.0 && freeze_frac < 1.0))
     return LBM_EINVAL;
+  if (lbmk::is_two_step_any_storage(b->tile_variant) && sample_every % 4) {
+    g_batch_error = "two steps per launch need a sampling interval that is a multiple of 4";
+    return LBM_EINVAL;
+  }
   b->sample_every = sample_every;
   b->max_steps = max_steps;
   b->freeze_frac = freeze_frac;
@@ -525,9 +530,15 @@ int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, d
   return LBM_OK;
 }
 
+// Batch launch shapes: the single-step tiles 0-4 and, with a sampling
+// interval that is a multiple of 4, the two-step variants 9 and 10.
+static bool batch_variant_ok(const lbm_batch* b, int v) {
+  if (v >= 0 && v < lbmk::NBATCH_VARIANTS) return true;
+  return lbmk::is_two_step_any_storage(v) && b->sample_every % 4 == 0;
+}
+
 int lbm_batch_set_launch(lbm_batch* b, int32_t tile_variant, int32_t xcd_group) {
-  if (!b || tile_variant < 0 || tile_variant >= lbmk::NBATCH_VARIANTS || xcd_group < 0 || xcd_group > 1)
-    return LBM_EINVAL;
+  if (!b || !batch_variant_ok(b, tile_variant) || xcd_group < 0 || xcd_group > 1) return LBM_EINVAL;
   b->tile_variant = tile_variant;
   b->xcd_group = xcd_group;
   return upload_map(b);
@@ -561,7 +572,9 @@ int lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* tile_variant, int32_
   LBMB_CK(hipEventCreate(&ev.c));
   float best = 1e30f;
   int bv = b->tile_variant, bx = b->xcd_group;
-  for (int v = 0; v < lbmk::NBATCH_VARIANTS; ++v)
+  for (int v = 0; v < lbmk::NTILE_VARIANTS; ++v) {
+    if (!batch_variant_ok(b, v)) continue;
+    const float per_launch = lbmk::is_two_step_any_storage(v) ? 2.0f : 1.0f;  // steps per launch
     for (int x = 0; x <= 1; ++x) {
       b->tile_variant = v;
       b->xcd_group = x;
@@ -579,12 +592,14 @@ int lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* tile_variant, int32_
       LBMB_CK(hipEventSynchronize(ev.c));
       float ms = 0.0f;
       LBMB_CK(hipEventElapsedTime(&ms, ev.a, ev.c));
+      ms /= per_launch;  // compare time per step
       if (ms < best) {
         best = ms;
         bv = v;
         bx = x;
       }
     }
+  }
   b->tile_variant = bv;
   b->xcd_group = bx;
   if (tile_variant) *tile_variant = bv;

@@ -86,12 +86,18 @@ struct StepOff {
 enum { NFIELD = 10 };
 // tiles 64x4, 32x8, 64x8, 64x16, 128x4; 5: unfused two-kernel 64x8; 6, 7, 8:
 // two steps per launch on 64x8, 32x8, 32x16 tiles; 9, 10: the same on 32x16
-// and 32x8 tiles with two and three lanes per tile node (FP32 storage)
+// and 32x8 tiles with two and three lanes per tile node (these two in every
+// storage format; 6-8 FP32 only)
 enum { NTILE_VARIANTS = 11, TWO_STEP_VARIANT = 6, NTWO_STEP_VARIANTS = 5 };
 inline bool is_two_step(int tile_variant) {
   return tile_variant >= TWO_STEP_VARIANT && tile_variant < TWO_STEP_VARIANT + NTWO_STEP_VARIANTS;
 }
-enum { NTUNED_VARIANTS = 5 };  // single-step shapes the autotuner times (plus the two-step ones in FP32)
+// Two-step variants with more lanes than tile nodes (32x16 / 1024 lanes and
+// 32x8 / 768 lanes): built for every storage format and for batches.
+inline bool is_two_step_any_storage(int tile_variant) {
+  return tile_variant == TWO_STEP_VARIANT + 3 || tile_variant == TWO_STEP_VARIANT + 4;
+}
+enum { NTUNED_VARIANTS = 5 };  // single-step shapes the autotuner times (plus the two-step ones)
 enum { NXCD_MODES = 3 };      // workgroup -> tile orders (map_tile)
 enum { RED_NVAL = 8 };
 constexpr int RED_BLOCKS = 512;
@@ -105,8 +111,9 @@ int launch_init(const KParams& P, const IParams& I, const State& S, int cur, con
                 const double* d_T0, hipStream_t st);
 int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int tile_variant,
                 int xcd_remap, hipStream_t st);
-// Two steps n -> n+2 in one launch (FP32 storage only): reads buffer cur,
-// writes buffer cur^1, like one step.
+// Two steps n -> n+2 in one launch (variants 6-8 FP32 storage only, 9-10
+// every format; steps P.seed and P.seed + 1): reads buffer cur, writes
+// buffer cur^1, like one step.
 int launch_step2(const KParams& P, const State& S, int cur, int tile_variant, int xcd_remap, hipStream_t st);
 // The 9 populations of `lattice` as FP32 (shifted variables) into the first
 // nine field planes.
@@ -136,7 +143,10 @@ void tile_shape(int tile_variant, int* tx, int* ty);
 // pass (s = 0), for every tile listed in d_tmap (nblocks entries:
 // slot << 16 | tile, ~0u = none), with the per-slot constants d_ptab[slot],
 // buffer sets d_otab[2 slot + (s & 1)] (offsets from d_base) and step
-// numbers d_steps[slot] + s (seeds of the stochastic rounding).
+// numbers d_steps[slot] + s (seeds of the stochastic rounding).  Tile
+// variants 0-4 (single steps), and 9-10 (steps s and s + 1 in one launch,
+// s even, buffer set (s / 2) & 1; their fields pass runs single-step tiles
+// of the same shape).
 int launch_batch(int storage, int tile_variant, bool fields_only, bool stream_stores, char* d_base,
                  const KParams* d_ptab,
                  const StepOff* d_otab, const unsigned* d_tmap, const unsigned* d_steps, int nblocks, int s,

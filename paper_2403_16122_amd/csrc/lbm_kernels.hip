@@ -100,6 +100,26 @@ __device__ __forceinline__ unsigned sr_node(unsigned k, unsigned seed) {
 }
 // word of population j (0..26) of a node from its hash
 __device__ __forceinline__ constexpr unsigned sr_pop(int j) { return 0x9e3779b9u * (unsigned)(j + 1); }
+// One stored value: FP32 as is; 16-bit formats rounded stochastically with
+// random word rnd (v_cvt_sr_f16_f32 / v_cvt_sr_bf16_f32).
+template <class PT>
+__device__ __forceinline__ PT cvt_store(float v, unsigned rnd);
+template <>
+__device__ __forceinline__ float cvt_store<float>(float v, unsigned) {
+  return v;
+}
+template <>
+__device__ __forceinline__ _Float16 cvt_store<_Float16>(float v, unsigned rnd) {
+  half2v h = {0, 0};
+  h = __builtin_amdgcn_cvt_sr_f16_f32(h, v, rnd, false);
+  return h.x;
+}
+template <>
+__device__ __forceinline__ __bf16 cvt_store<__bf16>(float v, unsigned rnd) {
+  bf162v h = {0, 0};
+  h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, rnd, false);
+  return h.x;
+}
 template <class PT>
 struct PopIO;
 // kNodeRef: the 16-bit formats keep h relative to the writing node's own
@@ -126,9 +146,7 @@ struct PopIO<_Float16> {
   }
   template <bool NT>
   static __device__ __forceinline__ void put(void* b, unsigned idx, float v, unsigned rnd) {
-    half2v h = {0, 0};
-    h = __builtin_amdgcn_cvt_sr_f16_f32(h, v, rnd, false);
-    st_as<NT, _Float16>((char*)b + (idx << 1), h.x);
+    st_as<NT, _Float16>((char*)b + (idx << 1), cvt_store<_Float16>(v, rnd));
   }
 };
 template <>
@@ -140,9 +158,7 @@ struct PopIO<__bf16> {
   }
   template <bool NT>
   static __device__ __forceinline__ void put(void* b, unsigned idx, float v, unsigned rnd) {
-    bf162v h = {0, 0};
-    h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, rnd, false);
-    st_as<NT, __bf16>((char*)b + (idx << 1), h.x);
+    st_as<NT, __bf16>((char*)b + (idx << 1), cvt_store<__bf16>(v, rnd));
   }
 };
 // Node references.  FP32 storage keeps phi_ref, the reference of the stored
@@ -198,6 +214,13 @@ template <class PT, int LAT, bool NT = false>
 __device__ __forceinline__ void pop_st(void* B, unsigned idx, float v, const KParams& P, unsigned rnd) {
   if constexpr (PopIO<PT>::kScaled) v *= P.sc_st[LAT];
   PopIO<PT>::template put<NT>(B, idx, v, rnd);
+}
+// The same value into an LDS array of the storage type (two steps per
+// launch keep the first step's populations as stored, bit for bit).
+template <class PT, int LAT>
+__device__ __forceinline__ void pop_lds_st(PT* dst, float v, const KParams& P, unsigned rnd) {
+  if constexpr (PopIO<PT>::kScaled) v *= P.sc_st[LAT];
+  *dst = cvt_store<PT>(v, rnd);
 }
 // Plane `j` of a population buffer.
 template <class PT>
@@ -447,15 +470,22 @@ __device__ __forceinline__ float wetting_ghost(float a0m, float a0c, float a0p, 
 // Everything after the stencils for one node k: interface terms (Eq. (3),
 // (12), (13)), forces (Eq. (11)), flow macros (Eq. (34)-(36)) and the three
 // BGK collisions with their stores, or the output fields when FIELDS.
-// LS > 0 (FP32 only): the node's 33 results go to LDS instead, plane j at
-// lo[j * LS] (populations 0-26 as in the global layout, then phi_ref,
-// (phi u)_x, (phi u)_y, f_s^H, p, S), for a second step in the same launch.
-enum { LDS_REF = 27, LDS_PHIUX = 28, LDS_PHIUY = 29, LDS_FSH = 30, LDS_P = 31, LDS_S = 32, LDS_NOUT = 33 };
+// LS > 0: the node's results go to LDS instead, for a second step in the
+// same launch: the 27 populations as stored (storage type, same rounding)
+// at lop[j * LS] in the global plane order, and the references, (phi u),
+// f_s^H, p and S as FP32 at loa[AUX_* * LS].  dseed: the step's offset
+// from P.seed (stochastic rounding of 16-bit storage).
+enum { AUX_REF = 0, AUX_PHIUX = 1, AUX_PHIUY = 2, AUX_FSH = 3, AUX_P = 4, AUX_S = 5, AUX_TH = 6 };
+template <class PT>
+constexpr int aux_planes() {
+  return PopIO<PT>::kNodeRef ? 7 : 6;
+}
 template <bool FIELDS, class PT, bool STREAM = false, int LS = 0>
 __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, const Macro& m,
                                             const float f[9], float phiux, float phiuy,
-                                            const Grads& d, unsigned k, float* lo = nullptr) {
-  static_assert(LS == 0 || (!FIELDS && std::is_same<PT, float>::value), "LDS results: FP32 step only");
+                                            const Grads& d, unsigned k, PT* lop = nullptr, float* loa = nullptr,
+                                            unsigned dseed = 0) {
+  static_assert(LS == 0 || !FIELDS, "LDS results: time steps only");
   const float phi = m.phi, rho = m.rho;
   const float om = (1.0f - m.r) - m.dl;  // 1 - phi without cancellation in either bulk
   // interface terms (Eq. (3), (12), (13))
@@ -516,7 +546,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
   const unsigned pl = P.plane;
   void* __restrict__ B = io.B;
   float r_new, th_new;  // references the stored g and h take this step
-  const unsigned rb = PopIO<PT>::kNodeRef ? sr_node(k, P.seed) : 0u;  // stochastic-rounding hash
+  const unsigned rb = PopIO<PT>::kNodeRef ? sr_node(k, P.seed + dseed) : 0u;  // stochastic-rounding hash
   // flow collision (Eq. (30)-(33))
   {
     const float itau = rcp(tauf), sf = 1.0f - 0.5f * itau;
@@ -532,7 +562,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float Fi = wt(i) * (Ssrc + 3.0f * (cx * Gx + cy * Gy) + 9.0f * cu * cF - 3.0f * uFt);
       const float fn = f[i] - (f[i] - feq) * itau + sf * Fi;
       if constexpr (LS > 0)
-        lo[(9 + i) * LS] = fn;
+        pop_lds_st<PT, 1>(lop + (9 + i) * LS, fn, P, rb ^ sr_pop(9 + i));
       else
         pop_st<PT, 1, STREAM>(Bf, i * pl + k, fn, P, rb ^ sr_pop(9 + i));
     }
@@ -557,14 +587,15 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       const float Gi = wt(i) * (cx * ax + cy * ay + pm);
       const float gn = gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi;
       if constexpr (LS > 0)
-        lo[i * LS] = gn;
+        pop_lds_st<PT, 0>(lop + i * LS, gn, P, rb ^ sr_pop(i));
       else
         pop_st<PT, 0, STREAM>(B, i * pl + k, gn, P, rb ^ sr_pop(i));
     }
     if constexpr (LS > 0) {
-      lo[LDS_REF * LS] = r_new;
-      lo[LDS_PHIUX * LS] = pux;
-      lo[LDS_PHIUY * LS] = puy;
+      loa[AUX_REF * LS] = r_new;
+      if constexpr (PopIO<PT>::kNodeRef) loa[AUX_TH * LS] = th_new;
+      loa[AUX_PHIUX * LS] = pux;
+      loa[AUX_PHIUY * LS] = puy;
     } else {
       RefIO<PopIO<PT>::kNodeRef>::template store<STREAM>(io.ref_out, k, r_new, th_new);
       st<STREAM>(io.phiu_out, k, pux);
@@ -589,7 +620,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       float hn = m.h[i] - (m.h[i] - heq) * itau;
       if (NR) hn += wt(i) * cmove;
       if constexpr (LS > 0)
-        lo[(18 + i) * LS] = hn;
+        pop_lds_st<PT, 2>(lop + (18 + i) * LS, hn, P, rb ^ sr_pop(18 + i));
       else
         pop_st<PT, 2, STREAM>(Bh, i * pl + k, hn, P, rb ^ sr_pop(18 + i));
       hs += m.h[i];
@@ -600,14 +631,14 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
     float h0 = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
     if (NR) h0 += W0 * cmove;
     if constexpr (LS > 0)
-      lo[18 * LS] = h0;
+      pop_lds_st<PT, 2>(lop + 18 * LS, h0, P, rb ^ sr_pop(18));
     else
       pop_st<PT, 2, STREAM>(Bh, k, h0, P, rb ^ sr_pop(18));
   }
   if constexpr (LS > 0) {
-    lo[LDS_FSH * LS] = m.fsH;
-    lo[LDS_P * LS] = p;
-    lo[LDS_S * LS] = Ssrc;
+    loa[AUX_FSH * LS] = m.fsH;
+    loa[AUX_P * LS] = p;
+    loa[AUX_S * LS] = Ssrc;
   } else {
     st<STREAM>(io.fsH_out, k, m.fsH);
     st<STREAM>(io.p_out, k, p);
@@ -852,10 +883,11 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
 // are bitwise those of two single steps.
 
 // Pull-stream one lattice into E cell (ex, ey) of grid row y from
-// first-step results in LDS (plane j at eo[j * ES]), with pull9's wall rules.
-template <int LAT, int EX, int ES>
-__device__ __forceinline__ void pull9_lds(const float* __restrict__ eo, const KParams& P, int ex, int ey,
-                                          int y, float q[9]) {
+// first-step results in LDS (plane j at ep[j * ES], the storage type), with
+// pop_ld's conversion and pull9's wall rules.
+template <int LAT, int EX, int ES, class PT>
+__device__ __forceinline__ void pull9_lds(const PT* __restrict__ ep, const KParams& P, int ex, int ey, int y,
+                                          float q[9]) {
   const bool bot = (y == 0), top = (y == P.ny - 1);
   const int e = ey * EX + ex;
 #pragma unroll
@@ -863,18 +895,19 @@ __device__ __forceinline__ void pull9_lds(const float* __restrict__ eo, const KP
     const int cy = cyv(i), cx = cxv(i);
     const bool wall = (cy > 0 && bot) || (cy < 0 && top);
     const int idx = wall ? (LAT * 9 + opp(i)) * ES + e : (LAT * 9 + i) * ES + e - cy * EX - cx;
-    float v = eo[idx];
+    float v = (float)ep[idx];
+    if constexpr (PopIO<PT>::kScaled) v *= P.sc_ld[LAT];
     if (LAT == 2 && cy > 0) v = bot ? (P.hwall[i] - v) : v;
     q[i] = v;
   }
 }
 
-template <int EX, int ES>
-__device__ __forceinline__ void load_node_lds(const float* __restrict__ eo, const KParams& P, int ex, int ey,
-                                              int y, Macro& m) {
-  pull9_lds<0, EX, ES>(eo, P, ex, ey, y, m.g);
-  pull9_lds<2, EX, ES>(eo, P, ex, ey, y, m.h);
-  m.fprev = eo[LDS_FSH * ES + ey * EX + ex];
+template <int EX, int ES, class PT>
+__device__ __forceinline__ void load_node_lds(const PT* __restrict__ ep, const float* __restrict__ ea,
+                                              const KParams& P, int ex, int ey, int y, Macro& m) {
+  pull9_lds<0, EX, ES>(ep, P, ex, ey, y, m.g);
+  pull9_lds<2, EX, ES>(ep, P, ex, ey, y, m.h);
+  m.fprev = ea[AUX_FSH * ES + ey * EX + ex];
 }
 
 template <int TX, int TY, bool STREAM = false>
@@ -890,7 +923,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
   constexpr int NRB = 2 * LX + 4 * TY;
   static_assert(ES <= 2 * NT && NRA <= NT && NRB <= NT, "lane assignment");
   static_assert(EX == LX + 2 && EY == LY + 2, "E doubles as the second step's reference tile");
-  __shared__ float s_eo[LDS_NOUT * ES];
+  __shared__ float s_ep[27 * ES];  // first-step populations
+  __shared__ float s_ea[6 * ES];   // and references, (phi u), f_s^H, p, S
   __shared__ float s_work[5 * LYA * LXA + RYA * RXA];
 
   const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
@@ -990,8 +1024,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
       if (!on[s]) continue;
       Grads d;
       tile_grads<LXA>(sphi, srho, sp, sS, ey[s] + 1, ex[s] + 2, d);
-      update_node<false, float, false, ES>(P, io, m[s], f[s], pux[s], puy[s], d, 0u,
-                                           s_eo + ey[s] * EX + ex[s]);
+      const int e = ey[s] * EX + ex[s];
+      update_node<false, float, false, ES>(P, io, m[s], f[s], pux[s], puy[s], d, 0u, s_ep + e, s_ea + e);
     }
     __syncthreads();
   }
@@ -1002,19 +1036,19 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
   float(*sfsH)[LX] = srho + LY;
   float(*sp)[LX] = sfsH + LY;
   float(*sS)[LX] = sp + LY;
-  const float(*sref)[EX] = reinterpret_cast<const float(*)[EX]>(s_eo + LDS_REF * ES);
+  const float(*sref)[EX] = reinterpret_cast<const float(*)[EX]>(s_ea + AUX_REF * ES);
   const int lx = t % TX, ly = t / TX;
   const int x = x0 + lx, y = y0 + ly;
   const bool yin = y < ny;
   const bool active = yin && x < nx;
   Macro m, mh;
   float f[9], phiux = 0.0f, phiuy = 0.0f;
-  if (yin) load_node_lds<EX, ES>(s_eo, P, lx + 3, ly + 2, y, m);
+  if (yin) load_node_lds<EX, ES>(s_ep, s_ea, P, lx + 3, ly + 2, y, m);
   if (active) {
     const int e = (ly + 2) * EX + lx + 3;
-    pull9_lds<1, EX, ES>(s_eo, P, lx + 3, ly + 2, y, f);
-    phiux = s_eo[LDS_PHIUX * ES + e];
-    phiuy = s_eo[LDS_PHIUY * ES + e];
+    pull9_lds<1, EX, ES>(s_ep, P, lx + 3, ly + 2, y, f);
+    phiux = s_ea[AUX_PHIUX * ES + e];
+    phiuy = s_ea[AUX_PHIUY * ES + e];
   }
   int hr = 0, hc = 0;
   bool halo = false;
@@ -1022,14 +1056,14 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
     ring_cell<LX, LY, TX>(t, hr, hc);
     const int gy = y0 + hr - 1;
     halo = gy >= 0 && gy < ny;
-    if (halo) load_node_lds<EX, ES>(s_eo, P, hc + 1, hr + 1, gy, mh);
+    if (halo) load_node_lds<EX, ES>(s_ep, s_ea, P, hc + 1, hr + 1, gy, mh);
   }
   for (int j = t; j < LX * LY; j += NT) {
     const int r = j / LX, c = j - (j / LX) * LX;
     const int gy = min(max(y0 + r - 1, 0), ny - 1);
     const int e = (gy - y0 + 2) * EX + c + 1;
-    sp[r][c] = s_eo[LDS_P * ES + e];
-    sS[r][c] = s_eo[LDS_S * ES + e];
+    sp[r][c] = s_ea[AUX_P * ES + e];
+    sS[r][c] = s_ea[AUX_S * ES + e];
   }
   if (yin) {
     const float rs = rebase_g<EX>(m.g, sref, P, y, lx + 2, ly + 1);
@@ -1059,26 +1093,33 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
 
 // The same two steps with more lanes than tile nodes: every lane owns at
 // most one cell of each step (an E cell or a cell of the first step's macro
-// ring; a tile node or a halo cell of the second), with the LDS of k_step2.
-// NT lanes: 2 TX TY for 32x16 tiles (one workgroup, 4 waves per SIMD),
-// 3 TX TY for 32x8 tiles (two workgroups, 6 waves per SIMD).
-template <int TX, int TY, int NT, bool STREAM = false>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ? 4 : 6))) void k_step2w(
-    KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
+// ring; a tile node or a halo cell of the second).  NT lanes: 2 TX TY for
+// 32x16 tiles (one workgroup, 4 waves per SIMD), 3 TX TY for 32x8 tiles
+// (two workgroups, 6 waves per SIMD).  Any storage format: the first
+// step's populations stay in LDS as stored (16-bit values rounded exactly
+// as a single step rounds them, with that step's random words), so the
+// second step reads what it would read from memory, and both steps are
+// bitwise those of single steps.  The first step runs with the step number
+// P.seed, the second with P.seed + 1.  Shared by the single-grid and the
+// batched kernels.
+template <int TX, int TY, int NT, class PT, bool STREAM>
+__device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, int x0, int y0) {
   constexpr int NTILE = TX * TY;
-  constexpr int EX = TX + 6, EY = TY + 4, ES = EX * EY;
+  constexpr int EX = TX + 6, EY = TY + 4, ES = EX * EY;  // E: cell (ex, ey) <-> (x0 - 3 + ex, y0 - 2 + ey)
+  // first step: macro cells (c, r) <-> (x0 - 5 + c, y0 - 3 + r); reference tiles one more cell around
   constexpr int LXA = EX + 4, LYA = EY + 2, RXA = LXA + 2, RYA = LYA + 2;
-  constexpr int NRA = 2 * LXA + 4 * EY;
+  constexpr int NRA = 2 * LXA + 4 * EY;  // macro cells of the first step outside E
+  // second step: the single-step layout, macro cells (c, r) <-> (x0 - 2 + c, y0 - 1 + r)
   constexpr int LX = TX + 4, LY = TY + 2;
   constexpr int NRB = 2 * LX + 4 * TY;
+  constexpr bool NR = PopIO<PT>::kNodeRef;
   static_assert(ES + NRA <= NT && NTILE + NRB <= NT, "one cell per lane in each step");
   static_assert(EX == LX + 2 && EY == LY + 2, "E doubles as the second step's reference tile");
-  __shared__ float s_eo[LDS_NOUT * ES];
-  __shared__ float s_work[5 * LYA * LXA + RYA * RXA];
+  static_assert((27 * ES * sizeof(PT)) % 4 == 0, "FP32 planes after the populations");
+  __shared__ PT s_ep[27 * ES];                 // first-step populations, as stored
+  __shared__ float s_ea[aux_planes<PT>() * ES];  // references, (phi u), f_s^H, p, S
+  __shared__ float s_work[5 * LYA * LXA + (NR ? 2 : 1) * RYA * RXA];
 
-  const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
-  if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
-  const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
   const void* __restrict__ A = io.A;
   const int nx = P.nx, ny = P.ny;
   const int t = threadIdx.x;
@@ -1091,13 +1132,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     float(*sp)[LXA] = sfsH + LYA;
     float(*sS)[LXA] = sp + LYA;
     float(*sref)[RXA] = reinterpret_cast<float(*)[RXA]>(s_work + 5 * LYA * LXA);
+    float(*sth)[RXA] = sref + RYA;  // node-reference storage only
     const int xa0 = x0 - 5, ya0 = y0 - 3;
 
     Macro m;
     float f[9], pux = 0.0f, puy = 0.0f;
-    int c = 0, r = 0;  // this lane's macro cell of the first step
-    bool on = false;   // an E cell inside the grid: macros and update
+    int c = 0, r = 0;   // this lane's macro cell of the first step
+    bool on = false;    // an E cell inside the grid: macros and update
     bool ring = false;  // a macro-ring cell inside the grid: macros only
+    unsigned k = 0;     // its node index
     if (t < ES) {
       c = t % EX + 2;
       r = t / EX + 1;
@@ -1105,25 +1148,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       on = y >= 0 && y < ny;
       if (on) {
         const int x = wrapx(xa0 + c, nx);
-        load_node<float>(A, io.fsH_in, P, x, y, m);
+        k = (unsigned)(y * nx + x);
+        load_node<PT>(A, io.fsH_in, P, x, y, m);
         const int xm = x == 0 ? nx - 1 : x - 1;
         const int xp = x == nx - 1 ? 0 : x + 1;
-        pull9<1, float>(A, P, x, y, xm, xp, f);
-        pux = ld(io.phiu_in, (unsigned)(y * nx + x));
-        puy = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
+        pull9<1, PT>(A, P, x, y, xm, xp, f);
+        pux = ld(io.phiu_in, k);
+        puy = ld(io.phiu_in, P.plane + k);
       }
     } else if (t - ES < NRA) {
       ring_cell<LXA, LYA, EX>(t - ES, r, c);
       const int gy = ya0 + r;
       ring = gy >= 0 && gy < ny;
-      if (ring) load_node<float>(A, io.fsH_in, P, wrapx(xa0 + c, nx), gy, m);
+      if (ring) load_node<PT>(A, io.fsH_in, P, wrapx(xa0 + c, nx), gy, m);
     }
     for (int j = t; j < RXA * RYA; j += NT) {
       const int rr = j / RXA, cc = j - (j / RXA) * RXA;
       const int gy = min(max(ya0 + rr - 1, 0), ny - 1);
       float rv, tv;
-      RefIO<false>::load(io.ref_in, (unsigned)(gy * nx + wrapx(xa0 + cc - 1, nx)), rv, tv);
+      RefIO<NR>::load(io.ref_in, (unsigned)(gy * nx + wrapx(xa0 + cc - 1, nx)), rv, tv);
       sref[rr][cc] = rv;
+      if constexpr (NR) sth[rr][cc] = tv;
     }
     for (int j = t; j < LXA * LYA; j += NT) {
       const int rr = j / LXA, cc = j - (j / LXA) * LXA;
@@ -1136,7 +1181,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
 
     if (on || ring) {
       const float rs = rebase_g<RXA>(m.g, sref, P, ya0 + r, c, r);
-      finish_macro<false>(P, rs, m);
+      if constexpr (NR) m.th = rebase_h<RXA>(m.h, sth, P, ya0 + r, c, r);
+      finish_macro<NR>(P, rs, m);
       sphi[r][c] = (m.r - 1.0f) + m.dl;
       srho[r][c] = m.rho;
       sfsH[r][c] = m.fsH;
@@ -1153,7 +1199,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     if (on) {
       Grads d;
       tile_grads<LXA>(sphi, srho, sp, sS, r, c, d);
-      update_node<false, float, false, ES>(P, io, m, f, pux, puy, d, 0u, s_eo + (r - 1) * EX + (c - 2));
+      const int e = (r - 1) * EX + (c - 2);
+      update_node<false, PT, false, ES>(P, io, m, f, pux, puy, d, k, s_ep + e, s_ea + e, 0u);
     }
     __syncthreads();
   }
@@ -1164,7 +1211,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   float(*sfsH)[LX] = srho + LY;
   float(*sp)[LX] = sfsH + LY;
   float(*sS)[LX] = sp + LY;
-  const float(*sref)[EX] = reinterpret_cast<const float(*)[EX]>(s_eo + LDS_REF * ES);
+  const float(*sref)[EX] = reinterpret_cast<const float(*)[EX]>(s_ea + AUX_REF * ES);
+  const float(*sth)[EX] = reinterpret_cast<const float(*)[EX]>(s_ea + AUX_TH * ES);  // node-reference storage
   Macro m;
   float f[9], phiux = 0.0f, phiuy = 0.0f;
   int c = 0, r = 0, y = 0;  // this lane's macro cell of the second step and its grid row
@@ -1181,23 +1229,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     y = y0 + r - 1;
     mac = y >= 0 && y < ny;
   }
-  if (mac) load_node_lds<EX, ES>(s_eo, P, c + 1, r + 1, y, m);
+  if (mac) load_node_lds<EX, ES>(s_ep, s_ea, P, c + 1, r + 1, y, m);
   if (active) {
     const int e = (r + 1) * EX + c + 1;
-    pull9_lds<1, EX, ES>(s_eo, P, c + 1, r + 1, y, f);
-    phiux = s_eo[LDS_PHIUX * ES + e];
-    phiuy = s_eo[LDS_PHIUY * ES + e];
+    pull9_lds<1, EX, ES>(s_ep, P, c + 1, r + 1, y, f);
+    phiux = s_ea[AUX_PHIUX * ES + e];
+    phiuy = s_ea[AUX_PHIUY * ES + e];
   }
   for (int j = t; j < LX * LY; j += NT) {
     const int rr = j / LX, cc = j - (j / LX) * LX;
     const int gy = min(max(y0 + rr - 1, 0), ny - 1);
     const int e = (gy - y0 + 2) * EX + cc + 1;
-    sp[rr][cc] = s_eo[LDS_P * ES + e];
-    sS[rr][cc] = s_eo[LDS_S * ES + e];
+    sp[rr][cc] = s_ea[AUX_P * ES + e];
+    sS[rr][cc] = s_ea[AUX_S * ES + e];
   }
   if (mac) {
     const float rs = rebase_g<EX>(m.g, sref, P, y, c, r);
-    finish_macro<false>(P, rs, m);
+    if constexpr (NR) m.th = rebase_h<EX>(m.h, sth, P, y, c, r);
+    finish_macro<NR>(P, rs, m);
     sphi[r][c] = (m.r - 1.0f) + m.dl;
     srho[r][c] = m.rho;
     sfsH[r][c] = m.fsH;
@@ -1211,7 +1260,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   if (!active) return;  // no barrier below
   Grads d;
   tile_grads<LX>(sphi, srho, sp, sS, r, c, d);
-  update_node<false, float, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x0 + c - 2));
+  update_node<false, PT, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x0 + c - 2), nullptr, nullptr,
+                                 1u);
+}
+
+template <int TX, int TY, int NT, class PT, bool STREAM = false>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ? 4 : 6))) void k_step2w(
+    KParams P, StepIO io, int ntx, int ntiles, int band, int mode) {
+  const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
+  if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
+  step2w_tile<TX, TY, NT, PT, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
 }
 
 // Unfused two-kernel step, kept to measure what fusion saves.  Pass 1
@@ -1286,6 +1344,26 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
   const StepIO io = io_of(base, otab[2 * slot + par]);
   const int ntx = (P.nx + TX - 1) / TX;
   step_tile<TX, TY, FIELDS, PT, false, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
+}
+
+// Two steps s, s + 1 (s even) of many grids in one launch, on the tiles of
+// step2w_tile: workgroup b runs tile tmap[b] of slot tmap[b] >> 16.  The
+// launch reads buffer set par = (s / 2) & 1 and writes the other one, so an
+// interval whose step count is a multiple of 4 ends in the buffer a run of
+// single steps ends in.
+template <int TX, int TY, int NT, class PT, bool STREAM = false>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ? 4 : 6))) void k_batch2w(
+    char* __restrict__ base, const KParams* __restrict__ ptab, const StepOff* __restrict__ otab,
+    const unsigned* __restrict__ tmap, const unsigned* __restrict__ steps, int s) {
+  const unsigned e = tmap[blockIdx.x];
+  if (e == ~0u) return;
+  const int slot = (int)(e >> 16), tile = (int)(e & 0xffffu);
+  const int par = (s >> 1) & 1;
+  KParams P = ptab[slot];
+  P.seed = steps[slot] + (unsigned)s;  // the grid's own step number (the second step adds one)
+  const StepIO io = io_of(base, otab[2 * slot + par]);
+  const int ntx = (P.nx + TX - 1) / TX;
+  step2w_tile<TX, TY, NT, PT, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
 }
 
 // Initial state (no time-stepping yet): u = 0, p = 0, liquid fraction 1,
@@ -1641,7 +1719,7 @@ int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int
   return launch_step_t<float>(P, S, cur, fields_only, tile_variant, xcd_remap, st);
 }
 
-template <int TX, int TY, int NT>
+template <int TX, int TY, int NT, class PT>
 int launch_tile2w(const KParams& P, const State& S, int cur, int xcd, hipStream_t st) {
   const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
   const int ntiles = ntx * nty;
@@ -1655,19 +1733,30 @@ int launch_tile2w(const KParams& P, const State& S, int cur, int xcd, hipStream_
   }
   const StepIO io = make_io(S, cur);
   if (P.stream_stores)
-    hipLaunchKernelGGL((k_step2w<TX, TY, NT, true>), dim3(grid), dim3(NT), 0, st, P, io, ntx, ntiles, band, xcd);
+    hipLaunchKernelGGL((k_step2w<TX, TY, NT, PT, true>), dim3(grid), dim3(NT), 0, st, P, io, ntx, ntiles, band,
+                       xcd);
   else
-    hipLaunchKernelGGL((k_step2w<TX, TY, NT, false>), dim3(grid), dim3(NT), 0, st, P, io, ntx, ntiles, band, xcd);
+    hipLaunchKernelGGL((k_step2w<TX, TY, NT, PT, false>), dim3(grid), dim3(NT), 0, st, P, io, ntx, ntiles, band,
+                       xcd);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <class PT>
+int launch_step2w_t(const KParams& P, const State& S, int cur, int tile_variant, int xcd_remap, hipStream_t st) {
+  if (tile_variant == TWO_STEP_VARIANT + 3) return launch_tile2w<32, 16, 1024, PT>(P, S, cur, xcd_remap, st);
+  return launch_tile2w<32, 8, 768, PT>(P, S, cur, xcd_remap, st);
+}
+
 int launch_step2(const KParams& P, const State& S, int cur, int tile_variant, int xcd_remap, hipStream_t st) {
-  if (P.storage != STORE_FP32) return -1;
+  if (P.storage != STORE_FP32) {
+    if (!is_two_step_any_storage(tile_variant)) return -1;
+    if (P.storage == STORE_FP16) return launch_step2w_t<_Float16>(P, S, cur, tile_variant, xcd_remap, st);
+    return launch_step2w_t<__bf16>(P, S, cur, tile_variant, xcd_remap, st);
+  }
   switch (tile_variant) {
     case TWO_STEP_VARIANT + 3:
-      return launch_tile2w<32, 16, 1024>(P, S, cur, xcd_remap, st);
     case TWO_STEP_VARIANT + 4:
-      return launch_tile2w<32, 8, 768>(P, S, cur, xcd_remap, st);
+      return launch_step2w_t<float>(P, S, cur, tile_variant, xcd_remap, st);
     case TWO_STEP_VARIANT:
       return launch_tile2<64, 8>(P, S, cur, xcd_remap, st);
     case TWO_STEP_VARIANT + 1:
@@ -1695,6 +1784,16 @@ int launch_expand(const KParams& P, const State& S, int cur, int lattice, hipStr
 
 void tile_shape(int tile_variant, int* tx, int* ty) {
   static const int T[NBATCH_VARIANTS][2] = {{64, 4}, {32, 8}, {64, 8}, {64, 16}, {128, 4}};
+  if (tile_variant == TWO_STEP_VARIANT + 3) {  // two steps per launch, 32x16 tiles
+    *tx = 32;
+    *ty = 16;
+    return;
+  }
+  if (tile_variant == TWO_STEP_VARIANT + 4) {  // two steps per launch, 32x8 tiles
+    *tx = 32;
+    *ty = 8;
+    return;
+  }
   const int v = tile_variant >= 0 && tile_variant < NBATCH_VARIANTS ? tile_variant : 0;
   *tx = T[v][0];
   *ty = T[v][1];
@@ -1715,9 +1814,28 @@ int launch_batch_t(bool fields_only, bool nt, char* base, const KParams* ptab, c
                        steps, s);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+template <int TX, int TY, int NT, class PT>
+int launch_batch2_t(bool nt, char* base, const KParams* ptab, const StepOff* otab, const unsigned* tmap,
+                    const unsigned* steps, int nblocks, int s, hipStream_t st) {
+  if (nt)
+    hipLaunchKernelGGL((k_batch2w<TX, TY, NT, PT, true>), dim3(nblocks), dim3(NT), 0, st, base, ptab, otab, tmap,
+                       steps, s);
+  else
+    hipLaunchKernelGGL((k_batch2w<TX, TY, NT, PT, false>), dim3(nblocks), dim3(NT), 0, st, base, ptab, otab, tmap,
+                       steps, s);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 template <class PT>
 int launch_batch_v(int variant, bool fields_only, bool nt, char* base, const KParams* ptab, const StepOff* otab,
                    const unsigned* tmap, const unsigned* steps, int nblocks, int s, hipStream_t st) {
+  if (variant == TWO_STEP_VARIANT + 3) {  // fields pass on the same 32x16 tiles
+    if (fields_only) return launch_batch_t<32, 16, PT>(true, false, base, ptab, otab, tmap, steps, nblocks, s, st);
+    return launch_batch2_t<32, 16, 1024, PT>(nt, base, ptab, otab, tmap, steps, nblocks, s, st);
+  }
+  if (variant == TWO_STEP_VARIANT + 4) {
+    if (fields_only) return launch_batch_t<32, 8, PT>(true, false, base, ptab, otab, tmap, steps, nblocks, s, st);
+    return launch_batch2_t<32, 8, 768, PT>(nt, base, ptab, otab, tmap, steps, nblocks, s, st);
+  }
   switch (variant) {
     case 0:
       return launch_batch_t<64, 4, PT>(fields_only, nt, base, ptab, otab, tmap, steps, nblocks, s, st);

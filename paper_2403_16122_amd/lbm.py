@@ -23,7 +23,8 @@ TILE_VARIANTS = {"64x4": 0, "32x8": 1, "64x8": 2, "64x16": 3, "128x4": 4,
                  "two32x16w": 9, "two32x8w": 10}  # the same with two and three lanes per tile node
 XCD_MODES = (0, 1, 2)  # row-major tiles; one row-major band per XCD; one column band per XCD
 TILE_NAMES = {v: k for k, v in TILE_VARIANTS.items()}
-TWO_STEP_VARIANTS = ("two64x8", "two32x8", "two32x16", "two32x16w", "two32x8w")  # FP32 storage only (lbm_set_launch refuses them otherwise)
+TWO_STEP_VARIANTS = ("two64x8", "two32x8", "two32x16", "two32x16w", "two32x8w")
+TWO_STEP_ANY_STORAGE = ("two32x16w", "two32x8w")  # the others: FP32 storage only (lbm_set_launch refuses them)
 STORAGE = {"fp32": 0, "fp16": 1, "bf16": 2}
 STORE_MODES = {"auto": 0, "cached": 1, "streaming": 2}  # lbm_set_store_mode  # LBM_STORE_FP32 / _FP16_SHIFT / _BF16_SHIFT
 

@@ -59,6 +59,33 @@ def test_batch_equals_single_solver_bitwise(storage, tile, xcd):
     assert all(r["steps"] == 200 for r in b.results())
 
 
+@pytest.mark.parametrize("storage,tile,xcd", [(0, "two32x8w", 1), (1, "two32x8w", 0), (1, "two32x16w", 1),
+                                          (2, "two32x16w", 0)])
+def test_two_step_batch_equals_single_steps_bitwise(storage, tile, xcd):
+    """Two steps per launch in the batch (intervals of a multiple of 4
+    steps) give every droplet exactly the single solver's single-step
+    state, in every storage format; an interval that is not a multiple of 4
+    is refused while such a launch is set."""
+    lbm = _lbm()
+    drops = small_sweep(5, seed=4, storage=storage)
+    print(f"two-step batch of {len(drops)} storage={storage} tile={tile} xcd={xcd}", flush=True)
+    b = make_batch(lbm, drops)
+    b.configure(sample_every=52, use_graph=True)
+    b.set_launch(tile, xcd)
+    with pytest.raises(lbm.LbmError):
+        b.configure(sample_every=50)
+    b.step(208)
+    names = ("phi", "T", "ux", "uy", "p", "fl")
+    for i, d in enumerate(drops):
+        s = lbm.Solver(d["params"], d["phi0"], d["T0"])
+        s.set_launch("64x8", 1)
+        s.step(208)
+        fs, fb = s.fields(names), b.fields(i, names)
+        for k in names:
+            assert np.array_equal(fs[k], fb[k]), (i, k, np.abs(fs[k] - fb[k]).max())
+    assert all(r["steps"] == 208 for r in b.results())
+
+
 def test_graph_replays_equal_individual_launches():
     lbm = _lbm()
     drops = small_sweep(4, seed=5, storage=1)

@@ -244,9 +244,49 @@ def test_two_step_launch_equals_single_steps(nx, ny, steps):
             assert np.array_equal(fa[k], fb[k]), (tile, xcd, mode, k)
     h = lbm.Solver(dict(p, storage=lbm.STORAGE["fp16"]), phi0, T0)
     for tile in lbm.TWO_STEP_VARIANTS:
+        if tile in lbm.TWO_STEP_ANY_STORAGE:
+            h.set_launch(tile, 0)
+            continue
         with pytest.raises(lbm.LbmError) as e:
             h.set_launch(tile, 0)
         assert e.value.code == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+@pytest.mark.parametrize("nx,ny,steps", [(3, 3, 9), (70, 13, 15), (130, 19, 8), (512, 256, 21)])
+def test_two_step_launch_equals_single_steps_16bit(storage, nx, ny, steps):
+    """16-bit storage: the two-step kernels keep the first step's
+    populations in LDS as stored (rounded stochastically with that step's
+    random words), so they reproduce single steps bit for bit as well:
+    whole checkpoint after an odd remainder, every workgroup order, cached
+    and streaming stores."""
+    lbm = _gpu()
+    if (nx, ny) == (512, 256):
+        p, phi0, T0, _ = W.workload("sessile512", seed=0)
+    else:
+        p = W.default_params(nx, ny, rho_s=0.88, theta_bottom_deg=65.0, theta_top_deg=115.0,
+                             gx=2e-6, gy=-5e-6, cp_s=0.7, k_s=0.2, cp_g=0.9, k_g=0.05)
+        R = max(2.0, min(nx, ny, 40) / 2.5)
+        phi0 = W.sessile_droplet(nx, ny, R, 90.0, 4.0, x0=nx / 2.0 + 0.3)
+        T0 = W.temperature_noise(nx, ny, p["T_melt"], 1e-3, 4)
+    p = dict(p, storage=lbm.STORAGE[storage])
+    a = lbm.Solver(p, phi0, T0)
+    a.set_launch("64x8", 1)
+    a.step(steps)
+    ref = a.save()
+    fa = a.fields(FIELDS)
+    for tile, xcd, mode in itertools.product(lbm.TWO_STEP_ANY_STORAGE, lbm.XCD_MODES, ("cached", "streaming")):
+        print(f"{storage} {nx}x{ny} {tile} xcd={xcd} {mode}", flush=True)
+        b = lbm.Solver(p, phi0, T0)
+        b.set_launch(tile, xcd)
+        b.set_store_mode(mode)
+        b.step(1)
+        b.step(steps - 1)
+        assert b.step_count == steps
+        assert b.save() == ref, (storage, tile, xcd, mode)
+        fb = b.fields(FIELDS)
+        for k in FIELDS:
+            assert np.array_equal(fa[k], fb[k]), (storage, tile, xcd, mode, k)
 
 
 def test_autotune_leaves_state_untouched():
