@@ -67,12 +67,14 @@ typedef struct {
   double gx, gy;                  /* gravity: body force rho*g */
   double bq_beta, bq_rho0, bq_Tref; /* optional Boussinesq force -rho0 beta (T - Tref) g (Sec. 4.3) */
   int32_t st_solid_mask;          /* 0: F_s = mu grad(phi) (Eq. (11)); 1: (1 - f_s) mu grad(phi) */
-  int32_t storage;                /* LBM_STORE_FP32 */
+  int32_t storage;                /* LBM_STORE_FP32, LBM_STORE_FP16_SHIFT or LBM_STORE_BF16_SHIFT:
+                                     the format of the stored populations; compute is FP32 */
 } lbm_params;
 
 typedef struct {
   int64_t step;
-  double sum_phi, sum_phic, sum_solid, sum_liquid, sum_H, max_u, h_c;
+  double sum_phi, sum_phic, sum_solid, sum_liquid, sum_H, max_u;
+  double h_c;  /* solid height on the centre column (the front height H_c of Sec. 4.2.1) */
   int32_t nonfinite;
 } lbm_diag_t;
 
@@ -98,12 +100,26 @@ int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
 int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_workspace,
              size_t ws_bytes, void* hip_stream, lbm_ctx** out);
 
-/* Enqueue nsteps >= 0 time steps on the context's stream (asynchronous). */
+/* Enqueue nsteps >= 0 time steps on the context's stream (asynchronous).
+ * One step is the update of Sec. 3 in this order: pull-streaming with the
+ * wall rules of Sec. 4.1, the enthalpy rule Eq. (9) on H = sum h_i
+ * (Eq. (29)), the mass source Eq. (19), the order parameter Eq. (26), the
+ * mixture properties Eq. (1), the wetting ghost rows Eq. (39)-(41), the
+ * stencils Eq. (38), the chemical potential and interface terms
+ * Eq. (3), (12)-(13), the forces Eq. (11) (with the Boussinesq term and
+ * solid mask of Sec. 4.3), the velocity and fluid-solid force Eq. (34)-(35),
+ * the forcing Eq. (33), the pressure Eq. (36), and the collisions Eq. (21)
+ * with (24)-(25), (37), Eq. (30)-(32) and Eq. (27)-(28).  LBM_EINVAL for a
+ * negative count; launch failures give LBM_EDEVICE. */
 int lbm_step(lbm_ctx* c, int32_t nsteps);
 
-/* Macroscopic fields at the current time level (phi, T, u, p, f_s, f_l,
- * rho, H, mdot as the next step would compute them).  host_out[j] receives
- * the j-th set bit of field_mask, nx*ny doubles.  Synchronises. */
+/* Macroscopic fields at the current time level as the next step would
+ * compute them: phi (Eq. (26)), T and f_l (Eq. (9)), u (Eq. (34)-(35), with
+ * the fluid-solid force), p (Eq. (36)), f_s = clamp(phi) (1 - f_l), rho
+ * (Eq. (1)), H (Eq. (29)) and mdot (Eq. (19)) -- the quantities of the
+ * paper's Figs. 4-11.  host_out[j] receives the j-th set bit of field_mask
+ * (caller-owned, nx*ny doubles each, row-major).  LBM_EINVAL for an unknown
+ * bit or a NULL output.  Synchronises. */
 int lbm_fields(lbm_ctx* c, uint32_t field_mask, double* const* host_out);
 
 /* Same fields as FP32 into device buffers (nx*ny floats each), enqueued on
@@ -113,9 +129,13 @@ int lbm_fields(lbm_ctx* c, uint32_t field_mask, double* const* host_out);
  * value). */
 int lbm_fields_device(lbm_ctx* c, uint32_t field_mask, float* const* d_out);
 
-/* FP64 sums over the grid: sum phi, sum clamp(phi), solid and liquid
- * volume, sum H, max |u|, solid height on the centre column; returns
- * LBM_ENONFINITE if a field is NaN/Inf.  Synchronises. */
+/* FP64 sums over the grid (wave reductions in FP64 of the FP32 fields, in
+ * a fixed order): sum phi (conserved exactly without freezing, Sec. 3.1),
+ * sum clamp(phi), solid volume sum f_s and liquid volume sum clamp(phi) f_l
+ * (the volume change of Eq. (44)), sum H (Eq. (29)), max |u|, and the solid
+ * height on the centre column, sum of f_s over the column x = nx/2 (the
+ * front height H_c of Sec. 4.2.1).  Returns LBM_ENONFINITE if a field is
+ * NaN/Inf (the sums are still written).  Synchronises. */
 int lbm_diag(lbm_ctx* c, lbm_diag_t* out);
 
 /* Post-collision populations of lattice 0 = g, 1 = f, 2 = h (9*nx*ny
@@ -230,11 +250,15 @@ int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, d
 
 /* Tile shape (tile_variant 0..4 of lbm_set_launch, or the two-step variants
  * 9 and 10 when the sampling interval is a multiple of 4; LBM_EINVAL
- * otherwise) and whether each droplet's tiles are kept on one XCD
- * (xcd_group 1, default) or laid out droplet after droplet (0); results are
- * bitwise identical either way.  lbm_batch_autotune times the same set
- * (per step).  With a two-step variant set, lbm_batch_configure refuses a
- * sampling interval that is not a multiple of 4. */
+ * otherwise) and how tiles are dealt to the 8 XCDs: each droplet's tiles
+ * kept on one XCD (xcd_group 1, default), laid out droplet after droplet
+ * (0), or the tiles of all droplets cut into 8 contiguous equal lists, one
+ * per XCD (2: balanced however few droplets remain); results are bitwise
+ * identical either way.  lbm_batch_autotune times the same set (per step)
+ * and keeps the fastest; after it, lbm_batch_step repeats the tuning each
+ * time the resident set has halved (the last droplets of a sweep favour
+ * other launches).  With a two-step variant set, lbm_batch_configure
+ * refuses a sampling interval that is not a multiple of 4. */
 int lbm_batch_set_launch(lbm_batch* b, int32_t tile_variant, int32_t xcd_group);
 int lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* tile_variant, int32_t* xcd_group);
 /* Store mode of the batched step, as lbm_set_store_mode, except that mode 0

@@ -121,6 +121,8 @@ struct lbm_batch {
   int64_t max_steps;
   double freeze_frac;
   int tile_variant, xcd_group;
+  int tune_reps;     // repetitions of the last lbm_batch_autotune (0: never tuned)
+  int tuned_active;  // resident droplets at that tuning
   int store_mode;  // 0 and 1 cached, 2 streaming stores
   bool nt;         // the step kernels stream their stores
   bool use_graph;
@@ -154,7 +156,11 @@ lbmk::StepOff offsets(const lbm_batch* b, const lbmk::State& S, int par) {
 // xcd_group 1: droplets are dealt to the 8 XCDs by node count (largest
 // first to the least loaded), and workgroup b, which the hardware places on
 // XCD b mod 8, takes the (b / 8)-th tile of XCD (b mod 8)'s list, so all
-// tiles of a droplet share one L2.
+// tiles of a droplet share one L2.  xcd_group 2: the tiles of all resident
+// droplets, droplet after droplet and row by row, cut into 8 contiguous
+// lists of equal length, one per XCD: every XCD gets the same work however
+// few droplets are left (with group 1 a lone droplet runs on one XCD), and
+// a tile's halo neighbours are still mostly in its own XCD's list.
 std::vector<unsigned> build_tmap(const lbm_batch* b) {
   int tx, ty;
   lbmk::tile_shape(b->tile_variant, &tx, &ty);
@@ -163,10 +169,14 @@ std::vector<unsigned> build_tmap(const lbm_batch* b) {
     const lbm_params& P = b->drops[b->slot_drop[s]].P;
     return ((P.nx + tx - 1) / tx) * ((P.ny + ty - 1) / ty);
   };
-  if (b->xcd_group == 0) {
+  if (b->xcd_group == 0 || b->xcd_group == 2) {
     for (int s : b->active)
       for (int t = 0, nt = tiles_of(s); t < nt; ++t) out.push_back(((unsigned)s << 16) | (unsigned)t);
-    return out;
+    if (b->xcd_group == 0) return out;
+    const size_t len = (out.size() + 7) / 8;  // list length per XCD
+    std::vector<unsigned> dealt(8 * len, ~0u);
+    for (size_t i = 0; i < out.size(); ++i) dealt[8 * (i % len) + i / len] = out[i];
+    return dealt;
   }
   std::vector<int> order(b->active);
   std::sort(order.begin(), order.end(), [&](int a, int c) { return tiles_of(a) > tiles_of(c); });
@@ -459,6 +469,8 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
   b->freeze_frac = 0.01;
   b->tile_variant = 0;
   b->xcd_group = 1;
+  b->tune_reps = 0;
+  b->tuned_active = 0;
   b->store_mode = 0;
   b->nt = false;
   b->use_graph = true;
@@ -538,7 +550,7 @@ static bool batch_variant_ok(const lbm_batch* b, int v) {
 }
 
 int lbm_batch_set_launch(lbm_batch* b, int32_t tile_variant, int32_t xcd_group) {
-  if (!b || !batch_variant_ok(b, tile_variant) || xcd_group < 0 || xcd_group > 1) return LBM_EINVAL;
+  if (!b || !batch_variant_ok(b, tile_variant) || xcd_group < 0 || xcd_group > 2) return LBM_EINVAL;
   b->tile_variant = tile_variant;
   b->xcd_group = xcd_group;
   return upload_map(b);
@@ -575,7 +587,7 @@ int lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* tile_variant, int32_
   for (int v = 0; v < lbmk::NTILE_VARIANTS; ++v) {
     if (!batch_variant_ok(b, v)) continue;
     const float per_launch = lbmk::is_two_step_any_storage(v) ? 2.0f : 1.0f;  // steps per launch
-    for (int x = 0; x <= 1; ++x) {
+    for (int x = 0; x <= 2; ++x) {
       b->tile_variant = v;
       b->xcd_group = x;
       int rc = upload_map(b);
@@ -602,6 +614,8 @@ int lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* tile_variant, int32_
   }
   b->tile_variant = bv;
   b->xcd_group = bx;
+  b->tune_reps = reps;
+  b->tuned_active = (int)b->active.size();
   if (tile_variant) *tile_variant = bv;
   if (xcd_group) *xcd_group = bx;
   return upload_map(b);
@@ -637,6 +651,12 @@ int lbm_batch_step(lbm_batch* b, int64_t nsteps, int32_t until_frozen) {
       if (b->slot_drop[s] >= 0) b->active.push_back(s);
     rc = upload_map(b);
     if (rc) return rc;
+    // the tail of a sweep, with few droplets left, favours other launches:
+    // re-tune once the resident set has halved since the last tuning
+    if (b->tune_reps > 0 && !b->active.empty() && 2 * (int)b->active.size() <= b->tuned_active) {
+      rc = lbm_batch_autotune(b, b->tune_reps, nullptr, nullptr);
+      if (rc) return rc;
+    }
   }
   return LBM_OK;
 }

@@ -4,10 +4,21 @@ An ensemble of small networks (``lbm.MLP``: BF16 matrix-core kernels) maps
 a droplet's parameters (R, theta, Ste, gamma = rho_s/rho_l, bubble count) to
 its freezing time t* (Fourier number, Eq. (42)), final height/R and tip
 angle, trained on droplets the batched solver ran to freezing
-(``sweep_data``).  The ensemble's spread of log t*, scaled on a held-back
-calibration tenth of the training droplets so that it bounds 95 % of their
-relative errors, is the predicted error of the mean: where it exceeds
-``fallback_rel`` (2 %), the droplet is run by the solver instead.
+(``sweep_data``).
+
+Whether a prediction can be trusted is decided by an error model, a second
+small ensemble of the same networks trained on out-of-fold errors: the
+training droplets are split into folds, the surrogate is refitted without
+each fold and its relative t* error on that fold recorded, and the error
+network learns log|error| from the five inputs.  Its output, scaled on a
+held-back calibration tenth of the training droplets (never seen by either
+network) so that it bounds 95 % of their errors, is the predicted error of a
+droplet; where it exceeds ``fallback_rel`` (2 %), the droplet is run by the
+solver instead.  (The spread of the ensemble does not rank the errors: most
+of them come from the bubbles' sizes and places, which the five inputs do
+not describe, and the error model learns where that matters -- bubble-free
+droplets carry a few tenths of a percent, droplets with several bubbles a
+few percent.)
 """
 from __future__ import annotations
 
@@ -33,6 +44,27 @@ def targets(d: Dict[str, np.ndarray]):
     return np.where(mask > 0, y, 0.0), mask
 
 
+SCHEDULE = ((6000, 3e-3), (6000, 1e-3), (4000, 3e-4))  # Adam steps, learning rate
+ERR_SCHEDULE = ((1500, 3e-3), (1500, 1e-3))
+ERR_FLOOR = 1e-4  # log of the error is taken of |error| + this floor
+
+
+def _fit_net(lbm, x: np.ndarray, y: np.ndarray, mask: np.ndarray, ensemble: int, seed: int, schedule):
+    """A network ensemble trained full-batch on normalised x, y (masked)."""
+    net = lbm.MLP(ensemble=ensemble, seed=seed, max_batch=max(len(x), 1))
+    for steps, lr in schedule:
+        net.train(x.astype(np.float32), y.astype(np.float32), mask.astype(np.float32), steps=steps, lr=lr)
+    return net
+
+
+def _spearman(a: np.ndarray, b: np.ndarray) -> float:
+    ra = np.argsort(np.argsort(a)).astype(np.float64)
+    rb = np.argsort(np.argsort(b)).astype(np.float64)
+    ra -= ra.mean()
+    rb -= rb.mean()
+    return float(np.sum(ra * rb) / np.sqrt(np.sum(ra * ra) * np.sum(rb * rb)))
+
+
 @dataclass
 class Surrogate:
     ensemble: int = 8
@@ -40,18 +72,33 @@ class Surrogate:
     fallback_rel: float = 0.02
     calib_frac: float = 0.1
     coverage: float = 0.95
-    spread_scale: float = 1.0
+    folds: int = 4          # out-of-fold refits that give the error model its targets
+    err_ensemble: int = 4
+    err_scale: float = 1.0  # calibration factor of the error model
     net: object = None
+    err_net: object = None
     xm: np.ndarray = field(default=None)
     xs: np.ndarray = field(default=None)
     ym: np.ndarray = field(default=None)
     ys: np.ndarray = field(default=None)
+    em: float = 0.0
+    es: float = 1.0
+    calib_spearman: float = float("nan")
     train_seconds: float = 0.0
 
-    def fit(self, data: Dict[str, np.ndarray], schedule=((6000, 3e-3), (6000, 1e-3), (4000, 3e-4))):
+    def _xn(self, x_raw):
+        return ((np.asarray(x_raw, dtype=np.float64) - self.xm) / self.xs).astype(np.float32)
+
+    def fit(self, data: Dict[str, np.ndarray], schedule=SCHEDULE):
         """Full-batch Adam on the frozen droplets of `data` (16000 steps:
         on 16k droplets a quarter of that leaves the held-out error 13 %
-        higher)."""
+        higher), then the error model: `folds` refits without one fold each
+        give every training droplet an out-of-fold relative t* error, an
+        ensemble learns log(|error| + 1e-4) from the inputs, and its scale is
+        set on the calibration droplets so that the predicted error bounds
+        `coverage` of their actual errors."""
+        import torch
+
         from paper_2403_16122_amd import lbm
 
         keep = np.asarray(data["frozen"], dtype=bool) & np.isfinite(data["t_star"])
@@ -60,43 +107,61 @@ class Surrogate:
         rng.shuffle(idx)
         ncal = int(round(self.calib_frac * len(idx)))
         cal, fit = np.sort(idx[:ncal]), np.sort(idx[ncal:])
-        x = features(data)[fit]
-        y, mask = targets({k: np.asarray(v)[fit] if np.ndim(v) else v for k, v in data.items()})
+        X = features(data)
+        Y, M = targets(data)
+        x, y, mask = X[fit], Y[fit], M[fit]
         self.xm, self.xs = x.mean(axis=0), x.std(axis=0) + 1e-12
         self.ym = np.array([np.sum(y[:, j] * mask[:, j]) / mask[:, j].sum() for j in range(3)])
         self.ys = np.array([np.sqrt(np.sum(((y[:, j] - self.ym[j]) * mask[:, j]) ** 2) / mask[:, j].sum())
                             for j in range(3)]) + 1e-12
-        xn = ((x - self.xm) / self.xs).astype(np.float32)
-        yn = (((y - self.ym) / self.ys) * mask).astype(np.float32)
-        self.net = lbm.MLP(ensemble=self.ensemble, seed=self.seed, max_batch=max(len(xn), 1))
-        import torch
+
+        def norm_y(yy, mm):
+            return ((yy - self.ym) / self.ys) * mm
 
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        loss = None
-        for steps, lr in schedule:
-            loss = self.net.train(xn, yn, mask.astype(np.float32), steps=steps, lr=lr)
+        self.net = _fit_net(lbm, self._xn(x), norm_y(y, mask), mask, self.ensemble, self.seed, schedule)
+        # out-of-fold errors of log t* on the fit droplets
+        oof = np.zeros(len(fit))
+        parts = np.array_split(np.random.default_rng(self.seed + 1).permutation(len(fit)), self.folds)
+        for f, held in enumerate(parts):
+            rest = np.sort(np.concatenate([parts[g] for g in range(self.folds) if g != f]))
+            net_f = _fit_net(lbm, self._xn(x[rest]), norm_y(y[rest], mask[rest]), mask[rest], self.ensemble,
+                             self.seed + 100 + f, schedule)
+            out = net_f.forward(self._xn(x[held])).cpu().numpy().astype(np.float64).mean(axis=0)
+            oof[held] = out[:, 0] * self.ys[0] + self.ym[0] - y[held, 0]
+            del net_f
+        le = np.log(np.abs(oof) + ERR_FLOOR)
+        self.em, self.es = float(le.mean()), float(le.std() + 1e-12)
+        et = np.zeros((len(fit), 3))
+        et[:, 0] = (le - self.em) / self.es
+        em = np.zeros((len(fit), 3))
+        em[:, 0] = 1.0
+        self.err_net = _fit_net(lbm, self._xn(x), et, em, self.err_ensemble, self.seed + 7, ERR_SCHEDULE)
         torch.cuda.synchronize()
         self.train_seconds = time.perf_counter() - t0
-        if ncal > 0:  # scale the spread to bound `coverage` of the calibration errors
-            self.spread_scale = 1.0
-            p = self.predict(features(data)[cal])
-            ratio = np.abs(np.log(p["t_star"] / np.asarray(data["t_star"])[cal])) / np.maximum(p["rel_spread"], 1e-12)
-            self.spread_scale = float(np.quantile(ratio, self.coverage))
-        return loss
+        if ncal > 0:  # scale the error model to bound `coverage` of the calibration errors
+            self.err_scale = 1.0
+            p = self.predict(X[cal])
+            actual = np.abs(np.log(p["t_star"] / np.asarray(data["t_star"])[cal]))
+            self.err_scale = float(np.quantile(actual / p["pred_rel_err"], self.coverage))
+            self.calib_spearman = _spearman(p["pred_rel_err"], actual)
+        return oof
 
     def predict_members(self, x_raw: np.ndarray):
         """Per-member outputs in the targets' units: (E, n, 3)."""
-        xn = ((np.asarray(x_raw, dtype=np.float64) - self.xm) / self.xs).astype(np.float32)
-        y = self.net.forward(xn).cpu().numpy().astype(np.float64)
+        y = self.net.forward(self._xn(x_raw)).cpu().numpy().astype(np.float64)
         return y * self.ys + self.ym
 
     def predict(self, x_raw: np.ndarray):
-        """Ensemble mean of (t*, height/R, tip angle) and the relative spread of t*."""
+        """Ensemble mean of (t*, height/R, tip angle), the relative spread of
+        t* over the ensemble, and the error model's predicted relative t*
+        error (scaled to bound `coverage` of the calibration errors)."""
         m = self.predict_members(x_raw)
         mean = m.mean(axis=0)
         spread = m[:, :, 0].std(axis=0)  # std of log t* = relative spread of t*
-        err = self.spread_scale * spread  # predicted relative error of t*
+        e = self.err_net.forward(self._xn(x_raw)).cpu().numpy().astype(np.float64)[:, :, 0].mean(axis=0)
+        err = self.err_scale * np.exp(e * self.es + self.em)
         return dict(t_star=np.exp(mean[:, 0]), height_R=mean[:, 1], tip_angle=100.0 * mean[:, 2],
                     rel_spread=spread, pred_rel_err=err, fallback=err > self.fallback_rel)
 
@@ -120,14 +185,21 @@ def evaluate(sur: Surrogate, test: Dict[str, np.ndarray]) -> Dict[str, float]:
     fb = p["fallback"]
     rel_fb = np.where(fb, 0.0, rel)
     ok = np.isfinite(ta)
+    acc = ~fb
     return dict(n=int(keep.sum()), t_star_rel_err_median=float(np.median(rel)), t_star_rel_err_p90=float(np.quantile(rel, 0.9)),
                 t_star_rel_err_max=float(rel.max()), height_R_abs_err_median=float(np.median(np.abs(p["height_R"] - hr))),
                 tip_angle_abs_err_median=float(np.median(np.abs(p["tip_angle"][ok] - ta[ok]))) if ok.any() else float("nan"),
                 fallback_fraction=float(fb.mean()), with_fallback_t_star_rel_err_median=float(np.median(rel_fb)),
                 with_fallback_t_star_rel_err_p90=float(np.quantile(rel_fb, 0.9)),
-                accepted_t_star_rel_err_max=float(rel[~fb].max()) if (~fb).any() else float("nan"),
-                accepted_t_star_rel_err_p95=float(np.quantile(rel[~fb], 0.95)) if (~fb).any() else float("nan"),
-                spread_scale=sur.spread_scale,
+                acceptance=float(acc.mean()),
+                accepted_t_star_rel_err_max=float(rel[acc].max()) if acc.any() else float("nan"),
+                accepted_t_star_rel_err_p95=float(np.quantile(rel[acc], 0.95)) if acc.any() else float("nan"),
+                accepted_t_star_rel_err_median=float(np.median(rel[acc])) if acc.any() else float("nan"),
+                accepted_frac_above_threshold=float((rel[acc] > sur.fallback_rel).mean()) if acc.any() else float("nan"),
+                error_model_spearman=_spearman(p["pred_rel_err"], rel),
+                error_model_spearman_calibration=sur.calib_spearman,
+                spread_spearman=_spearman(p["rel_spread"], rel),
+                err_scale=sur.err_scale,
                 inference_seconds=infer)
 
 

@@ -39,7 +39,8 @@ def make_batch(lbm, drops, slots=None):
                      radii=[d["R"] for d in drops], slots=slots)
 
 
-@pytest.mark.parametrize("storage,tile,xcd", [(0, "64x4", 1), (1, "64x8", 0), (2, "128x4", 1)])
+@pytest.mark.parametrize("storage,tile,xcd", [(0, "64x4", 1), (1, "64x8", 0), (2, "128x4", 1), (1, "64x8", 2),
+                                          (0, "32x8", 2)])
 def test_batch_equals_single_solver_bitwise(storage, tile, xcd):
     lbm = _lbm()
     drops = small_sweep(5, seed=3, storage=storage)
