@@ -115,7 +115,7 @@ def plain_until_frozen(lbm, d, every: int, max_steps: int):
     return tf, steps[-1], secs
 
 
-def run_sweep(lbm, W, n: int, storage: str, time_limit: float):
+def run_sweep(lbm, W, n: int, storage: str, time_limit: float, chunk: int = 50000):
     """The batched sweep in one storage format: every droplet run until 1 %
     of its liquid is left; returns (results, seconds, node_steps, launch)."""
     import torch
@@ -129,7 +129,7 @@ def run_sweep(lbm, W, n: int, storage: str, time_limit: float):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     while True:
-        b.step(50000, until_frozen=True)
+        b.step(chunk, until_frozen=True)
         res = b.results()
         done = sum(r["status"] != "running" and r["status"] != "queued" for r in res)
         print(f"sweep {storage}: {done}/{n} droplets finished after {time.perf_counter() - t0:.1f} s", file=sys.stderr,
@@ -143,7 +143,7 @@ def run_sweep(lbm, W, n: int, storage: str, time_limit: float):
     return drops, res, secs, node_steps, (tile, grp)
 
 
-def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float):
+def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float, reference: bool = True, chunk: int = 50000):
     """The batched sweep: n droplets (R ~ U(16,64), theta ~ U(60,150),
     Ste ~ U(0.05,0.3), gamma ~ U(0.85,1.1), 0-8 bubbles, grid 4R x 3R, FP16
     storage) all run until frozen as one queue; the same queue in FP32
@@ -153,7 +153,7 @@ def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float):
     import numpy as np
 
     every, max_steps = 200, 2_000_000
-    drops, res, secs, node_steps, (tile, grp) = run_sweep(lbm, W, n, "fp16", time_limit)
+    drops, res, secs, node_steps, (tile, grp) = run_sweep(lbm, W, n, "fp16", time_limit, chunk)
     frozen = [r for r in res if r["status"] == "frozen"]
     out = {
         "workload": f"{n} droplets, R~U(16,64), theta~U(60,150), Ste~U(0.05,0.3), gamma~U(0.85,1.1), 0-8 bubbles, "
@@ -162,6 +162,8 @@ def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float):
         "node_steps": int(node_steps), "MLUPS": round(node_steps / secs / 1e6, 1), "tile": tile, "xcd_group": grp,
         "t_freeze_steps": [round(float(q), 1) for q in np.nanpercentile([r["t_freeze"] for r in res], [0, 50, 100])],
     }
+    if not reference:
+        return out
     _, res32, secs32, ns32, (tile32, grp32) = run_sweep(lbm, W, n, "fp32", time_limit)
     tf16 = np.array([r["t_freeze"] for r in res])
     tf32 = np.array([r["t_freeze"] for r in res32])
@@ -423,6 +425,10 @@ def main():
     ap.add_argument("--sweep-droplets", type=int, default=256, help="droplets in the batched sweep (0: skip)")
     ap.add_argument("--sweep-plain", type=int, default=16, help="droplets of the sweep re-run one at a time in FP32")
     ap.add_argument("--sweep-time-limit", type=float, default=240.0)
+    ap.add_argument("--sweep-chunk", type=int, default=50000,
+                    help="steps between the sweep's progress checks (time limit and finished count)")
+    ap.add_argument("--no-sweep-reference", dest="sweep_reference", action="store_false",
+                    help="skip the FP32-storage run of the sweep (and the plain re-runs)")
     ap.add_argument("--no-to-frozen", dest="to_frozen", action="store_false",
                     help="skip running the 512x256 droplet to full solidification")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
@@ -562,7 +568,8 @@ def main():
                 probe[st] = vrec
         out["probe4096"] = probe
     if args.sweep_droplets > 0:
-        out["sweep"] = sweep_bench(lbm, W, args.sweep_droplets, args.sweep_plain, args.sweep_time_limit)
+        out["sweep"] = sweep_bench(lbm, W, args.sweep_droplets, args.sweep_plain, args.sweep_time_limit,
+                                   args.sweep_reference, args.sweep_chunk)
         torch.cuda.empty_cache()
     if args.surrogate:
         out["surrogate"] = surrogate_bench(out.get("sweep"))
