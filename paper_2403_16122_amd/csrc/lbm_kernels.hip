@@ -233,12 +233,17 @@ __device__ __forceinline__ void* pop_plane(void* B, unsigned j, unsigned pl) {
 // population (half-way rule); for h at the bottom wall by the
 // anti-bounce-back Dirichlet value -h_opp + 2 w_i cp_ref (T_w - T_m) in the
 // shifted variables.
-// Element index of the population of lattice LAT pulled into node (x, y)
-// along direction i: the neighbour's x - c_i, or, beyond a wall, the
-// node's own opposite population (32-bit indices: a scalar plane base plus
-// one vector offset per load).
-template <int LAT>
-__device__ __forceinline__ unsigned pull_index(const KParams& P, int i, int x, int y, int xm, int xp) {
+//
+// Addressing: direction i of lattice LAT is read relative to the plane
+// pbase(i) = min(i, opp(i)) of that lattice, a base address that is the same
+// for every lane (kept in scalar registers), plus a 32-bit byte offset that
+// depends only on the node and the direction: a neighbour's population at
+// (i - pbase(i)) planes + its index, or, beyond a wall, the node's own
+// opposite population at (opp(i) - pbase(i)) planes + the node's index --
+// both non-negative.  The offsets are therefore shared by g, f and h.
+__device__ __forceinline__ constexpr int pbase(int i) { return i < opp(i) ? i : opp(i); }
+
+__device__ __forceinline__ unsigned pull_off(const KParams& P, int i, int x, int y, int xm, int xp) {
   const unsigned pl = P.plane;
   const unsigned nx = (unsigned)P.nx;
   const bool bot = (y == 0), top = (y == P.ny - 1);
@@ -248,7 +253,15 @@ __device__ __forceinline__ unsigned pull_index(const KParams& P, int i, int x, i
   const bool wall = (cy > 0 && bot) || (cy < 0 && top);
   const unsigned sx = (unsigned)(cx > 0 ? xm : (cx < 0 ? xp : x));
   const unsigned sk = (cy > 0 ? rowd : (cy < 0 ? rowu : rowc)) + sx;
-  return wall ? (unsigned)(LAT * 9 + opp(i)) * pl + rowc + (unsigned)x : (unsigned)(LAT * 9 + i) * pl + sk;
+  return wall ? (unsigned)(opp(i) - pbase(i)) * pl + rowc + (unsigned)x : (unsigned)(i - pbase(i)) * pl + sk;
+}
+
+// The stored value of direction i of lattice LAT pulled from element offset
+// `off` (pull_off) of its base plane.
+template <int LAT, class PT>
+__device__ __forceinline__ PT pull_raw(const void* __restrict__ A, const KParams& P, int i, unsigned off) {
+  const char* base = (const char*)A + (size_t)(LAT * 9 + pbase(i)) * P.plane * sizeof(PT);
+  return *(const PT*)(base + (off * (unsigned)sizeof(PT)));
 }
 
 template <int LAT, class PT>
@@ -258,7 +271,8 @@ __device__ __forceinline__ void pull9(const void* __restrict__ A, const KParams&
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int cy = cyv(i);
-    float v = pop_ld<PT, LAT>(A, pull_index<LAT>(P, i, x, y, xm, xp), P);
+    float v = (float)pull_raw<LAT, PT>(A, P, i, pull_off(P, i, x, y, xm, xp));
+    if constexpr (PopIO<PT>::kScaled) v *= P.sc_ld[LAT];
     if (LAT == 2 && cy > 0) v = bot ? (P.hwall[i] - v) : v;
     q[i] = v;
   }
@@ -357,7 +371,7 @@ __device__ __forceinline__ void pull9_raw(const void* __restrict__ A, const KPar
                                           int xp, Raw9<PT>& r) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const PT v = *(const PT*)((const char*)A + (pull_index<LAT>(P, i, x, y, xm, xp) << 1));
+    const PT v = pull_raw<LAT, PT>(A, P, i, pull_off(P, i, x, y, xm, xp));
     if (i & 1)
       r.p[i >> 1].y = v;
     else
