@@ -373,6 +373,35 @@ def test_one_step_from_identical_state(oracle_mod, name, steps):
         assert np.abs(fg[k] - fo[k]).max() < tol, k
 
 
+@pytest.mark.parametrize("name,steps", [("bubbles1024", 100), ("probe4096", 20)])
+def test_full_size_from_identical_state_in_the_benchmarked_launch(oracle_mod, name, steps):
+    """The benchmark's two workloads at full size (the 1024x512 headline and
+    the 4096x2048 roofline grid), in the launch the library's autotuner
+    picks there (two steps per launch on both): from the very same state,
+    the GPU's after `steps` steps loaded into the oracle, two steps of each
+    agree at every node to FP32 rounding of the populations and fields."""
+    lbm = _gpu()
+    p, phi0, T0, _ = W.workload(name, seed=0)
+    g = lbm.Solver(p, phi0, T0)
+    tile, xcd = g.autotune(reps=3)
+    print(f"{name}: launch {tile}/{xcd}", flush=True)
+    g.step(steps)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    o.load(gpu_state_as_oracle_checkpoint(g.save(), p))
+    g.step(2)
+    o.step(2)
+    for lat, tol in (("g", 1e-6), ("f", 1e-7), ("h", 1e-6)):
+        d = float(np.abs(g.pops(lat) - o.pops(lat)).max())
+        print(f"{name}@{steps}+2 ({tile}) pops {lat}: {d:.2e}", flush=True)
+        assert d < tol, (lat, d)
+    fg, fo = g.fields(FIELDS), o.fields(FIELDS)
+    umax = max(np.abs(fo["ux"]).max(), np.abs(fo["uy"]).max())
+    for k, tol in (("phi", 2e-6), ("T", 2e-6), ("ux", 2e-4 * umax), ("uy", 2e-4 * umax), ("p", 2e-8)):
+        d = float(np.abs(fg[k] - fo[k]).max())
+        print(f"{name}@{steps}+2 {k}: {d:.2e} (bound {tol:.1e})", flush=True)
+        assert d < tol, k
+
+
 def test_nonfinite_is_reported():
     lbm = _gpu()
     p, phi0, T0, _ = W.workload("sessile128", seed=0)
