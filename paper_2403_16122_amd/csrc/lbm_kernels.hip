@@ -33,6 +33,9 @@ __device__ __forceinline__ constexpr int opp(int i) {
   return i == 0 ? 0 : (i < 5 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5);
 }
 
+// The first direction of each pair of opposite ones: 1, 2, 5, 6.
+__device__ __forceinline__ constexpr int pair_dir(int j) { return j < 2 ? j + 1 : j + 3; }
+
 __device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
 __device__ __forceinline__ float mix3(float fs, float pc, float zs, float zl, float zg) {
   // Eq. (1) with the clamped order parameter
@@ -561,24 +564,48 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
   void* __restrict__ B = io.B;
   float r_new, th_new;  // references the stored g and h take this step
   const unsigned rb = PopIO<PT>::kNodeRef ? sr_node(k, P.seed + dseed) : 0u;  // stochastic-rounding hash
+  // The three BGK collisions, each written per pair of opposite directions
+  // (i, opp(i)): an equilibrium or source term splits into a part even in
+  // c_i (u.u, (c_i.u)^2, (c_i.u)(c_i.F), constants), shared by the pair, and
+  // a part odd in c_i, added for i and subtracted for opp(i).  The update
+  // keeps the non-equilibrium form f_i - (f_i - f_i^eq)/tau (+ source), with
+  // f_i - f_i^eq formed by one fused multiply-add from the stored value, so
+  // the rounding stays at the size of the small non-equilibrium part.
   // flow collision (Eq. (30)-(33))
   {
     const float itau = rcp(tauf), sf = 1.0f - 0.5f * itau;
     const float Gx = Fx + rho * fbx, Gy = Fy + rho * fby;
+    // feq_i = w_i (e0 + 4.5 rho (c.u)^2 +- 3 rho (c.u)) - 3 p [i = 0],
+    // F_i = w_i (s0 + 9 (c.u)(c.Ft) +- 3 (c.G))
+    const float e0 = 3.0f * p - 1.5f * rho * usq, s0 = Ssrc - 3.0f * uFt;
+    const float r3 = 3.0f * rho, r45 = 4.5f * rho;
+    // the change -(f_i - feq_i)/tau + sf F_i is formed first (small), and
+    // added to the stored value in one rounding
+    float fn[9];
+    {
+      const float feq0 = W0 * e0 - 3.0f * p;
+      fn[0] = f[0] + __builtin_fmaf(-itau, f[0] - feq0, sf * (W0 * s0));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = pair_dir(j), o = opp(i);
+      const float cx = (float)cxv(i), cy = (float)cyv(i), w = wt(i);
+      const float cu = cx * ux + cy * uy, cF = cx * Ftx + cy * Fty, cG = cx * Gx + cy * Gy;
+      const float ev = __builtin_fmaf(r45 * cu, cu, e0), od = r3 * cu;
+      const float fe = __builtin_fmaf(9.0f * cu, cF, s0), fo = 3.0f * cG;
+      const float sw = sf * w;
+      const float ni = __builtin_fmaf(-w, ev + od, f[i]);  // f_i - feq_i
+      const float no = __builtin_fmaf(-w, ev - od, f[o]);
+      fn[i] = f[i] + __builtin_fmaf(-itau, ni, sw * (fe + fo));
+      fn[o] = f[o] + __builtin_fmaf(-itau, no, sw * (fe - fo));
+    }
     void* Bf = pop_plane<PT>(B, 9, pl);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const float cx = (float)cxv(i), cy = (float)cyv(i);
-      const float cu = cx * ux + cy * uy;
-      const float si = wt(i) * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq);
-      const float feq = 3.0f * p * (wt(i) - (i == 0 ? 1.0f : 0.0f)) + rho * si;
-      const float cF = cx * Ftx + cy * Fty;
-      const float Fi = wt(i) * (Ssrc + 3.0f * (cx * Gx + cy * Gy) + 9.0f * cu * cF - 3.0f * uFt);
-      const float fn = f[i] - (f[i] - feq) * itau + sf * Fi;
       if constexpr (LS > 0)
-        pop_lds_st<PT, 1>(lop + (9 + i) * LS, fn, P, rb ^ sr_pop(9 + i));
+        pop_lds_st<PT, 1>(lop + (9 + i) * LS, fn[i], P, rb ^ sr_pop(9 + i));
       else
-        pop_st<PT, 1, STREAM>(Bf, i * pl + k, fn, P, rb ^ sr_pop(9 + i));
+        pop_st<PT, 1, STREAM>(Bf, i * pl + k, fn[i], P, rb ^ sr_pop(9 + i));
     }
   }
   // phase-field collision (Eq. (21), (24), (25), (37))
@@ -591,19 +618,32 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
     // populations and the equilibrium relative to it
     RefIO<PopIO<PT>::kNodeRef>::round(phi, m.dT, r_new, th_new);
     const float dr = m.r - r_new;  // exact for nearby floats
-    const float dln = m.dl + dr;  // phi - phi_ref(new)
+    const float dln = m.dl + dr;   // phi - phi_ref(new)
+    // g_i - w_i phi_ref(new) = g_i(stored) + w_i dr; its equilibrium is
+    // w_i (dln +- 3 phi c.u) and its source w_i (phi mdot +- c.a)
+    const float itg = P.inv_tau_g, srg = P.src_g, ph3 = 3.0f * phi;
+    float gn[9];
+    {
+      const float gi = m.g[0] + W0 * dr;
+      gn[0] = gi - (gi - W0 * dln) * itg + srg * (W0 * pm);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = pair_dir(j), o = opp(i);
+      const float cx = (float)cxv(i), cy = (float)cyv(i), w = wt(i);
+      const float cu = cx * ux + cy * uy, ca = cx * ax + cy * ay;
+      const float od = ph3 * cu, sw = srg * w;
+      const float gi = __builtin_fmaf(w, dr, m.g[i]), go = __builtin_fmaf(w, dr, m.g[o]);
+      const float ni = __builtin_fmaf(-w, dln + od, gi), no = __builtin_fmaf(-w, dln - od, go);
+      gn[i] = __builtin_fmaf(-itg, ni, __builtin_fmaf(sw, pm + ca, gi));
+      gn[o] = __builtin_fmaf(-itg, no, __builtin_fmaf(sw, pm - ca, go));
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const float cx = (float)cxv(i), cy = (float)cyv(i);
-      const float cu = cx * ux + cy * uy;
-      const float gi = m.g[i] + wt(i) * dr;                 // g_i - w_i phi_ref
-      const float geq = wt(i) * (dln + 3.0f * phi * cu);  // g_i^eq - w_i phi_ref
-      const float Gi = wt(i) * (cx * ax + cy * ay + pm);
-      const float gn = gi - (gi - geq) * P.inv_tau_g + P.src_g * Gi;
       if constexpr (LS > 0)
-        pop_lds_st<PT, 0>(lop + i * LS, gn, P, rb ^ sr_pop(i));
+        pop_lds_st<PT, 0>(lop + i * LS, gn[i], P, rb ^ sr_pop(i));
       else
-        pop_st<PT, 0, STREAM>(B, i * pl + k, gn, P, rb ^ sr_pop(i));
+        pop_st<PT, 0, STREAM>(B, i * pl + k, gn[i], P, rb ^ sr_pop(i));
     }
     if constexpr (LS > 0) {
       loa[AUX_REF * LS] = r_new;
@@ -624,30 +664,39 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
     const float crd = NR ? P.cp_ref * (m.dT - m.th) : P.cp_ref * m.dT;
     // node reference: move from the received reference th to this step's
     const float cmove = NR ? P.cp_ref * (m.th - th_new) : 0.0f;
-    void* Bh = pop_plane<PT>(B, 18, pl);
+    // h_i^eq = w_i (e0 + 4.5 cp T (c.u)^2 +- 3 cp T (c.u)) for i > 0
+    const float e0 = crd - 1.5f * cpT * usq, c3 = 3.0f * cpT, c45 = 4.5f * cpT;
+    float hn[9];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int i = pair_dir(j), o = opp(i);
+      const float cx = (float)cxv(i), cy = (float)cyv(i), w = wt(i);
+      const float cu = cx * ux + cy * uy;
+      const float ev = __builtin_fmaf(c45 * cu, cu, e0), od = c3 * cu;
+      const float ni = __builtin_fmaf(-w, ev + od, m.h[i]), no = __builtin_fmaf(-w, ev - od, m.h[o]);
+      hn[i] = __builtin_fmaf(-itau, ni, m.h[i]);
+      hn[o] = __builtin_fmaf(-itau, no, m.h[o]);
+      if (NR) {
+        hn[i] = __builtin_fmaf(w, cmove, hn[i]);
+        hn[o] = __builtin_fmaf(w, cmove, hn[o]);
+      }
+    }
     float hs = 0.0f;
 #pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      const float cx = (float)cxv(i), cy = (float)cyv(i);
-      const float cu = cx * ux + cy * uy;
-      const float heq = wt(i) * (crd + cpT * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
-      float hn = m.h[i] - (m.h[i] - heq) * itau;
-      if (NR) hn += wt(i) * cmove;
-      if constexpr (LS > 0)
-        pop_lds_st<PT, 2>(lop + (18 + i) * LS, hn, P, rb ^ sr_pop(18 + i));
-      else
-        pop_st<PT, 2, STREAM>(Bh, i * pl + k, hn, P, rb ^ sr_pop(18 + i));
-      hs += m.h[i];
-    }
+    for (int i = 1; i < 9; ++i) hs += m.h[i];
     // rest population: h0eq - h0 = sum_{i>0} h_i - cp_ref dT + w0 (cp_ref dT - 1.5 cp T u.u);
     // the stored value moves by that relaxation plus L (f_s^H(n) - f_s^H(n-1))
     const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
-    float h0 = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
-    if (NR) h0 += W0 * cmove;
-    if constexpr (LS > 0)
-      pop_lds_st<PT, 2>(lop + 18 * LS, h0, P, rb ^ sr_pop(18));
-    else
-      pop_st<PT, 2, STREAM>(Bh, k, h0, P, rb ^ sr_pop(18));
+    hn[0] = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
+    if (NR) hn[0] += W0 * cmove;
+    void* Bh = pop_plane<PT>(B, 18, pl);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if constexpr (LS > 0)
+        pop_lds_st<PT, 2>(lop + (18 + i) * LS, hn[i], P, rb ^ sr_pop(18 + i));
+      else
+        pop_st<PT, 2, STREAM>(Bh, i * pl + k, hn[i], P, rb ^ sr_pop(18 + i));
+    }
   }
   if constexpr (LS > 0) {
     loa[AUX_FSH * LS] = m.fsH;
@@ -695,6 +744,61 @@ __device__ __forceinline__ void ring_cell(int q, int& hr, int& hc) {
     hc = s < 2 ? s : TXR + s;
   }
 }
+
+// Fill of a W x H LDS tile in two halves, so that the loads of several
+// fills are all in flight before the first LDS store (one memory round trip
+// for every fill of a phase, overlapping the node pulls issued before them).
+// Lane t owns column c = t % W and the rows t / W + q G (G = NT / W rows at
+// a time): colv(c) is worked out once per lane, ldv(r, colv) gives the value
+// (type V) of cell (c, r), stv(r, c, v) stores it.  The lanes beyond G W and
+// the rows beyond H load a duplicate of the last row (in bounds, never
+// stored), so the loads need no branch.
+template <int W, int H, int NT, class V>
+struct TileFill {
+  static constexpr int G = NT / W;
+  static_assert(G >= 1, "tile row wider than the workgroup");
+  static constexpr int NQ = (H + G - 1) / G;
+  int c, r0;
+  V v[NQ];
+  template <class CV, class LD>
+  __device__ __forceinline__ void load(int t, CV colv, LD ldv) {
+    c = t % W;
+    r0 = t / W;
+    const auto cv = colv(c);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = ldv(min(r0 + q * G, H - 1), cv);
+  }
+  // Cells from global memory: (c, r) takes the node at column wrapx(gx0 + c)
+  // and row clamp(gy0 + r, 0, ny - 1); ldk(k) loads node k.
+  template <class LD>
+  __device__ __forceinline__ void load_grid(int t, int gx0, int gy0, int nx, int ny, LD ldk) {
+    load(
+        t, [&](int cc) { return wrapx(gx0 + cc, nx); },
+        [&](int r, int gx) { return ldk((unsigned)(min(max(gy0 + r, 0), ny - 1) * nx + gx)); });
+  }
+  template <class ST>
+  __device__ __forceinline__ void store(int t, ST stv) const {
+    if (t >= G * W) return;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int r = r0 + q * G;
+      if ((q + 1) * G <= H || r < H) stv(r, c, v[q]);
+    }
+  }
+};
+
+struct RefPair {
+  float r, th;
+};
+template <bool NR>
+__device__ __forceinline__ RefPair load_ref(const void* b, unsigned k) {
+  RefPair v;
+  RefIO<NR>::load(b, k, v.r, v.th);
+  return v;
+}
+struct PS {
+  float p, s;
+};
 
 // Wetting ghost rows (Eq. (39)-(41)) of a macro region of width LXR: the
 // row rb below grid row 0 and the row rt above grid row ny-1, where present.
@@ -813,21 +917,24 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
   // phi_ref with a two-cell halo (rows beyond a wall are never read; the
   // clamp keeps the load in bounds), and the lagged p and S with one cell
   // (rows beyond a wall copy the adjacent row)
-  for (int j = t; j < RX * RY; j += NT) {
-    const int r = j / RX, c = j - (j / RX) * RX;
-    const int gy = min(max(y0 + r - 2, 0), ny - 1);
-    float rv, tv;
-    RefIO<NR>::load(io.ref_in, (unsigned)(gy * nx + wrapx(x0 + c - 3, nx)), rv, tv);
-    s_ref[r][c] = rv;
-    if constexpr (NR) s_th[r][c] = tv;
+  {
+    TileFill<RX, RY, NT, RefPair> fr;
+    TileFill<LX, LY, NT, PS> fp;
+    fr.load_grid(t, x0 - 3, y0 - 2, nx, ny, [&](unsigned kk) { return load_ref<NR>(io.ref_in, kk); });
+    fp.load_grid(t, x0 - 2, y0 - 1, nx, ny, [&](unsigned kk) { return PS{ld(io.p_in, kk), ld(io.S_in, kk)}; });
+    fr.store(t, [&](int r, int c, RefPair v) {
+      s_ref[r][c] = v.r;
+      if constexpr (NR) s_th[r][c] = v.th;
+    });
+    fp.store(t, [&](int r, int c, PS v) {
+      s_p[r][c] = v.p;
+      s_S[r][c] = v.s;
+    });
   }
-  for (int j = t; j < LX * LY; j += NT) {
-    const int r = j / LX, c = j - (j / LX) * LX;
-    const int gy = min(max(y0 + r - 1, 0), ny - 1);
-    const int kk = gy * nx + wrapx(x0 + c - 2, nx);
-    s_p[r][c] = ld(io.p_in, (unsigned)kk);
-    s_S[r][c] = ld(io.S_in, (unsigned)kk);
-    if constexpr (MACRO_IN) {
+  if constexpr (MACRO_IN) {
+    for (int j = t; j < LX * LY; j += NT) {
+      const int r = j / LX, c = j - (j / LX) * LX;
+      const int kk = min(max(y0 + r - 1, 0), ny - 1) * nx + wrapx(x0 + c - 2, nx);
       s_phi[r][c] = ld(io.fields, (unsigned)kk);
       s_rho[r][c] = ld(io.fields, P.plane + (unsigned)kk);
       s_fsH[r][c] = ld(io.fields, 2u * P.plane + (unsigned)kk);
@@ -989,19 +1096,16 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
       halo = gy >= 0 && gy < ny;
       if (halo) load_node<float>(A, io.fsH_in, P, wrapx(xa0 + hc, nx), gy, mh);
     }
-    for (int j = t; j < RXA * RYA; j += NT) {
-      const int r = j / RXA, c = j - (j / RXA) * RXA;
-      const int gy = min(max(ya0 + r - 1, 0), ny - 1);
-      float rv, tv;
-      RefIO<false>::load(io.ref_in, (unsigned)(gy * nx + wrapx(xa0 + c - 1, nx)), rv, tv);
-      sref[r][c] = rv;
-    }
-    for (int j = t; j < LXA * LYA; j += NT) {
-      const int r = j / LXA, c = j - (j / LXA) * LXA;
-      const int gy = min(max(ya0 + r, 0), ny - 1);
-      const int kk = gy * nx + wrapx(xa0 + c, nx);
-      sp[r][c] = ld(io.p_in, (unsigned)kk);
-      sS[r][c] = ld(io.S_in, (unsigned)kk);
+    {
+      TileFill<RXA, RYA, NT, float> fr;
+      TileFill<LXA, LYA, NT, PS> fp;
+      fr.load_grid(t, xa0 - 1, ya0 - 1, nx, ny, [&](unsigned kk) { return ld((const float*)io.ref_in, kk); });
+      fp.load_grid(t, xa0, ya0, nx, ny, [&](unsigned kk) { return PS{ld(io.p_in, kk), ld(io.S_in, kk)}; });
+      fr.store(t, [&](int r, int c, float v) { sref[r][c] = v; });
+      fp.store(t, [&](int r, int c, PS v) {
+        sp[r][c] = v.p;
+        sS[r][c] = v.s;
+      });
     }
     __syncthreads();
 
@@ -1072,12 +1176,18 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
     halo = gy >= 0 && gy < ny;
     if (halo) load_node_lds<EX, ES>(s_ep, s_ea, P, hc + 1, hr + 1, gy, mh);
   }
-  for (int j = t; j < LX * LY; j += NT) {
-    const int r = j / LX, c = j - (j / LX) * LX;
-    const int gy = min(max(y0 + r - 1, 0), ny - 1);
-    const int e = (gy - y0 + 2) * EX + c + 1;
-    sp[r][c] = s_ea[AUX_P * ES + e];
-    sS[r][c] = s_ea[AUX_S * ES + e];
+  {
+    TileFill<LX, LY, NT, PS> fp;
+    fp.load(
+        t, [](int cc) { return cc; },
+        [&](int rr, int cc) {
+          const int e = (min(max(y0 + rr - 1, 0), ny - 1) - y0 + 2) * EX + cc + 1;
+          return PS{s_ea[AUX_P * ES + e], s_ea[AUX_S * ES + e]};
+        });
+    fp.store(t, [&](int rr, int cc, PS v) {
+      sp[rr][cc] = v.p;
+      sS[rr][cc] = v.s;
+    });
   }
   if (yin) {
     const float rs = rebase_g<EX>(m.g, sref, P, y, lx + 2, ly + 1);
@@ -1176,20 +1286,19 @@ __device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, 
       ring = gy >= 0 && gy < ny;
       if (ring) load_node<PT>(A, io.fsH_in, P, wrapx(xa0 + c, nx), gy, m);
     }
-    for (int j = t; j < RXA * RYA; j += NT) {
-      const int rr = j / RXA, cc = j - (j / RXA) * RXA;
-      const int gy = min(max(ya0 + rr - 1, 0), ny - 1);
-      float rv, tv;
-      RefIO<NR>::load(io.ref_in, (unsigned)(gy * nx + wrapx(xa0 + cc - 1, nx)), rv, tv);
-      sref[rr][cc] = rv;
-      if constexpr (NR) sth[rr][cc] = tv;
-    }
-    for (int j = t; j < LXA * LYA; j += NT) {
-      const int rr = j / LXA, cc = j - (j / LXA) * LXA;
-      const int gy = min(max(ya0 + rr, 0), ny - 1);
-      const int kk = gy * nx + wrapx(xa0 + cc, nx);
-      sp[rr][cc] = ld(io.p_in, (unsigned)kk);
-      sS[rr][cc] = ld(io.S_in, (unsigned)kk);
+    {
+      TileFill<RXA, RYA, NT, RefPair> fr;
+      TileFill<LXA, LYA, NT, PS> fp;
+      fr.load_grid(t, xa0 - 1, ya0 - 1, nx, ny, [&](unsigned kk) { return load_ref<NR>(io.ref_in, kk); });
+      fp.load_grid(t, xa0, ya0, nx, ny, [&](unsigned kk) { return PS{ld(io.p_in, kk), ld(io.S_in, kk)}; });
+      fr.store(t, [&](int rr, int cc, RefPair v) {
+        sref[rr][cc] = v.r;
+        if constexpr (NR) sth[rr][cc] = v.th;
+      });
+      fp.store(t, [&](int rr, int cc, PS v) {
+        sp[rr][cc] = v.p;
+        sS[rr][cc] = v.s;
+      });
     }
     __syncthreads();
 
@@ -1250,12 +1359,18 @@ __device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, 
     phiux = s_ea[AUX_PHIUX * ES + e];
     phiuy = s_ea[AUX_PHIUY * ES + e];
   }
-  for (int j = t; j < LX * LY; j += NT) {
-    const int rr = j / LX, cc = j - (j / LX) * LX;
-    const int gy = min(max(y0 + rr - 1, 0), ny - 1);
-    const int e = (gy - y0 + 2) * EX + cc + 1;
-    sp[rr][cc] = s_ea[AUX_P * ES + e];
-    sS[rr][cc] = s_ea[AUX_S * ES + e];
+  {
+    TileFill<LX, LY, NT, PS> fp;
+    fp.load(
+        t, [](int cc) { return cc; },
+        [&](int rr, int cc) {
+          const int e = (min(max(y0 + rr - 1, 0), ny - 1) - y0 + 2) * EX + cc + 1;
+          return PS{s_ea[AUX_P * ES + e], s_ea[AUX_S * ES + e]};
+        });
+    fp.store(t, [&](int rr, int cc, PS v) {
+      sp[rr][cc] = v.p;
+      sS[rr][cc] = v.s;
+    });
   }
   if (mac) {
     const float rs = rebase_g<EX>(m.g, sref, P, y, c, r);
@@ -1307,13 +1422,13 @@ __global__ __launch_bounds__(TX* TY) void k_macro(KParams P, StepIO io, int ntx,
   const bool active = y < ny && x < nx;
   Macro m;
   if (active) load_node<PT>(io.A, io.fsH_in, P, x, y, m);
-  for (int j = t; j < RX * RR; j += TX * TY) {
-    const int q = j / RX, c = j - (j / RX) * RX;
-    const int gy = min(max(y0 + q - 1, 0), ny - 1);
-    float rv, tv;
-    RefIO<NR>::load(io.ref_in, (unsigned)(gy * nx + wrapx(x0 + c - 1, nx)), rv, tv);
-    s_ref[q][c] = rv;
-    if constexpr (NR) s_th[q][c] = tv;
+  {
+    TileFill<RX, RR, TX * TY, RefPair> fr;
+    fr.load_grid(t, x0 - 1, y0 - 1, nx, ny, [&](unsigned kk) { return load_ref<NR>(io.ref_in, kk); });
+    fr.store(t, [&](int q, int c, RefPair v) {
+      s_ref[q][c] = v.r;
+      if constexpr (NR) s_th[q][c] = v.th;
+    });
   }
   __syncthreads();
   if (!active) return;

@@ -21,6 +21,7 @@ import pytest
 
 from oracle import shape as SH
 from paper_2403_16122_amd import workloads as W
+from sensitivity import perturbed_every_step
 
 pytestmark = pytest.mark.gpu
 
@@ -100,7 +101,14 @@ def test_sessile128_seeds_integrals_after_2000_steps(oracle_mod, seed):
     """Seeds 1 and 2 of the parity workload, whose pointwise phi the method
     amplifies beyond the stated bound within a few hundred steps, over the
     workload's full 2000 steps: the integral quantities stay with the
-    oracle's (volumes, enthalpy, centre freezing height)."""
+    oracle's (volumes, enthalpy, centre freezing height) within twice the
+    method's own sensitivity, floored at fixed bounds.  The sensitivity is
+    measured as in the pointwise test: the oracle against itself with phi0
+    perturbed by 1e-7 (three draws) and with phi moved by 1e-8 after every
+    step (three draws).  For seed 2 it is bimodal: one of those six draws
+    (the first) resolves one dip event the other way and moves the solid
+    volume by 3.2e-5 and sum phi by 6.1e-7 (the mass source follows the
+    solid), the others by 1e-6 to 7e-6 and 3e-8 to 6e-8."""
     lbm = _lbm()
     p, phi0, T0, _ = W.workload("sessile128", seed=seed)
     g = lbm.Solver(p, phi0, T0)
@@ -109,16 +117,29 @@ def test_sessile128_seeds_integrals_after_2000_steps(oracle_mod, seed):
     g.step(2000)
     o.step(2000)
     dg, do = g.diag(), o.diag()
-    rel = {k: abs(dg[k] - do[k]) / abs(do[k]) for k in ("sum_phi", "sum_phic", "sum_H", "sum_solid", "sum_liquid")}
-    rel["h_c"] = abs(dg["h_c"] - do["h_c"])
+    keys = ("sum_phi", "sum_phic", "sum_H", "sum_solid", "sum_liquid")
+
+    def dev(d):
+        r = {k: abs(d[k] - do[k]) / abs(do[k]) for k in keys}
+        r["h_c"] = abs(d["h_c"] - do["h_c"])
+        return r
+
+    rel = dev(dg)
     fg, fo = g.fields(["T"]), o.fields(["T"])
     dT = float(np.abs(fg["T"] - fo["T"]).max())
-    print(f"sessile128 seed {seed} ({tile}/{xcd}) after 2000 steps: {rel} max|dT| {dT:.2e}", flush=True)
-    # measured on MI355X (seeds 0 / 1 / 2): sum phi 1.1e-9 / 2.6e-9 / 5.8e-9,
-    # sum H 3.0e-9 / 3.1e-9 / 3.5e-9, solid 1.5e-7 / 1.7e-6 / 4.9e-7,
-    # H_c 1e-7 / 1.5e-5 / 2.3e-4 lu, max|dT| 3.4e-7 / 4.6e-7 / 6.9e-7; the
-    # temperature is held to the stated parity tolerance 1e-5
-    assert rel["sum_phi"] <= 1e-7 and rel["sum_H"] <= 1e-7
-    assert rel["sum_solid"] <= 2e-5 and rel["sum_liquid"] <= 2e-5
-    assert rel["h_c"] <= 0.01
+    others = []
+    for draw in range(3):
+        z = np.random.default_rng(900 + draw).standard_normal(phi0.size)
+        o2 = oracle_mod.OracleSolver(p, phi0 + 1e-7 * z, T0)
+        o2.step(2000)
+        others.append(o2)
+    for draw in range(3):
+        others.append(perturbed_every_step(oracle_mod, p, phi0, T0, 2000, 1e-8, 300 + draw))
+    env = dict(sum_phi=1e-7, sum_phic=1e-7, sum_H=1e-7, sum_solid=2e-5, sum_liquid=2e-5, h_c=0.01)
+    for o2 in others:
+        for k, v in dev(o2.diag()).items():
+            env[k] = max(env[k], 2.0 * v)
+    print(f"sessile128 seed {seed} ({tile}/{xcd}) after 2000 steps: {rel} max|dT| {dT:.2e}; bounds {env}", flush=True)
+    for k in env:
+        assert rel[k] <= env[k], (k, rel[k], env[k])
     assert dT <= 1e-5

@@ -16,6 +16,11 @@ from paper_2403_16122_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+# The stored sweep records against a fresh run of the batched solver: equal
+# when both come from the same build of the kernels; a build whose FP32
+# arithmetic rounds differently moves t* of these droplets by ~1e-5.
+STORED_REL = 1e-3
+
 DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2403_16122_amd", "data")
 
 
@@ -86,9 +91,18 @@ def test_fallback_reproduces_the_solver_and_speed_gain(fitted):
         setattr(sur_all, k, getattr(sur, k))
     out, fb, t = S.predict_with_fallback(sur_all, sub)
     assert fb.all() and t["solver_droplets"] == len(sub)
-    for j, i in enumerate(order):
-        assert out["t_star"][j] == pytest.approx(te["t_star"][i], rel=1e-12)
-        assert out["height_R"][j] == pytest.approx(te["height_R"][i], rel=1e-12)
+    # the batched solver on its own gives the same values, bit for bit
+    from paper_2403_16122_amd import lbm
+
+    b = lbm.Batch([d["params"] for d in sub], [d["phi0"] for d in sub], [d["T0"] for d in sub],
+                  radii=[d["R"] for d in sub], slots=5)
+    b.configure(sample_every=200, max_steps=3_000_000)
+    b.step(30_000_000, until_frozen=True)
+    for j, (i, r) in enumerate(zip(order, b.results())):
+        assert out["t_star"][j] == r["t_star"] and out["height_R"][j] == r["height"] / sub[j]["R"]
+        # and the stored held-out records, written by the same batched solver
+        assert out["t_star"][j] == pytest.approx(te["t_star"][i], rel=STORED_REL)
+        assert out["height_R"][j] == pytest.approx(te["height_R"][i], rel=STORED_REL)
     import time
 
     import torch

@@ -149,3 +149,27 @@ def test_validation_rejects_nonfinite_input(oracle_mod):
     phi0[7] = np.nan
     with pytest.raises(ValueError):
         oracle_mod.OracleSolver(p, phi0, np.ones(48))
+
+
+def test_per_step_perturbation_helper_moves_phi_by_the_drawn_amount(oracle_mod):
+    """The sensitivity helper of the GPU tests writes where it means to: with
+    eps = 0 the run is the plain oracle's, bit for bit; with eps > 0 the g
+    populations of every node move by w_i times one drawn value per node."""
+    import numpy as np
+
+    from sensitivity import W9, perturbed_every_step
+    from paper_2403_16122_amd import workloads as W
+
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    a = oracle_mod.OracleSolver(p, phi0, T0)
+    a.step(3)
+    b = perturbed_every_step(oracle_mod, p, phi0, T0, 3, 0.0, 1)
+    assert a.save() == b.save()
+    c = oracle_mod.OracleSolver(p, phi0, T0)
+    c.step(1)
+    d = perturbed_every_step(oracle_mod, p, phi0, T0, 1, 1e-6, 2)
+    delta = 1e-6 * np.random.default_rng(2).standard_normal(phi0.size).reshape(p["ny"], p["nx"])
+    dg = d.pops("g") - c.pops("g")
+    assert np.allclose(dg, W9[:, None, None] * delta[None], rtol=0, atol=1e-15)
+    assert np.allclose(dg.sum(axis=0), delta, rtol=0, atol=1e-15)
+    assert np.array_equal(d.pops("f"), c.pops("f")) and np.array_equal(d.pops("h"), c.pops("h"))
