@@ -38,8 +38,10 @@ __device__ __forceinline__ constexpr int pair_dir(int j) { return j < 2 ? j + 1 
 
 __device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
 __device__ __forceinline__ float mix3(float fs, float pc, float zs, float zl, float zg) {
-  // Eq. (1) with the clamped order parameter
-  return fs * zs + (1.0f - fs) * (pc * zl + (1.0f - pc) * zg);
+  // Eq. (1) with the clamped order parameter, fs zs + (1 - fs)(pc zl +
+  // (1 - pc) zg), as two multiply-adds: exactly zl, zg or zs in a pure phase
+  const float fluid = __builtin_fmaf(pc, zl, (1.0f - pc) * zg);
+  return __builtin_fmaf(fs, zs, (1.0f - fs) * fluid);
 }
 // Periodic x: one compare-and-shift covers |x| < 2 nx; the modulo only
 // runs for grids narrower than a tile.
@@ -70,6 +72,16 @@ __device__ __forceinline__ void st_as(void* a, T v) {
     __builtin_nontemporal_store(v, (T*)a);
   else
     *(T*)a = v;
+}
+
+// Plane j of an array of FP32 planes of pl elements: the same address for
+// every lane (scalar arithmetic), so that an element is then addressed by
+// the node's own 32-bit offset, shared by every plane.
+__device__ __forceinline__ float* fplane(float* base, unsigned j, unsigned pl) {
+  return (float*)((char*)base + (size_t)j * pl * sizeof(float));
+}
+__device__ __forceinline__ const float* fplane(const float* base, unsigned j, unsigned pl) {
+  return (const float*)((const char*)base + (size_t)j * pl * sizeof(float));
 }
 
 // Hardware reciprocal (1 ulp); used identically wherever a node is rebuilt.
@@ -113,14 +125,22 @@ __device__ __forceinline__ float cvt_store<float>(float v, unsigned) {
 }
 template <>
 __device__ __forceinline__ _Float16 cvt_store<_Float16>(float v, unsigned rnd) {
-  half2v h = {0, 0};
+  // the conversion writes the low half; the high half is never read, so
+  // it is left undefined (no register to clear first)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wuninitialized"
+  half2v h;
   h = __builtin_amdgcn_cvt_sr_f16_f32(h, v, rnd, false);
+#pragma clang diagnostic pop
   return h.x;
 }
 template <>
 __device__ __forceinline__ __bf16 cvt_store<__bf16>(float v, unsigned rnd) {
-  bf162v h = {0, 0};
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wuninitialized"
+  bf162v h;
   h = __builtin_amdgcn_cvt_sr_bf16_f32(h, v, rnd, false);
+#pragma clang diagnostic pop
   return h.x;
 }
 template <class PT>
@@ -457,9 +477,9 @@ __device__ __forceinline__ void finish_macro(const KParams& P, float rs, Macro& 
 }
 
 // Gradients and Laplacian of Eq. (38) at one node: phi (with its
-// Laplacian) and rho at time t, lagged p and S.
+// Laplacian) and rho at time t, and q = S/3 - p of the lagged p and S.
 struct Grads {
-  float phx, phy, lphi, rx, ry, px, py, Sx, Sy;
+  float phx, phy, lphi, rx, ry, qx, qy;  // q = S/3 - p (only its gradient enters Eq. (36))
 };
 
 // 3 sum_{i>0} w_i c_i z_i and 6 sum_{i>0} w_i (z_i - z_0) over the 8 neighbours.
@@ -467,10 +487,13 @@ __device__ __forceinline__ void stencil(float C, float E, float Wv, float N, flo
                                         float NW, float SW, float SE, float& gx, float& gy,
                                         float* lap) {
 #pragma clang fp contract(off)
-  gx = (E - Wv) * (1.0f / 3.0f) + (NE - NW - SW + SE) * (1.0f / 12.0f);
-  gy = (N - S) * (1.0f / 3.0f) + (NE + NW - SW - SE) * (1.0f / 12.0f);
+  // differences of neighbours in the same row (for x) or column (for y)
+  // first: exact where the field varies only across them (a layered flow
+  // keeps a zero x-gradient in FP32)
+  gx = __builtin_fmaf(E - Wv, 1.0f / 3.0f, ((NE - NW) + (SE - SW)) * (1.0f / 12.0f));
+  gy = __builtin_fmaf(N - S, 1.0f / 3.0f, ((NE - SE) + (NW - SW)) * (1.0f / 12.0f));
   if (lap)
-    *lap = (E + N + Wv + S - 4.0f * C) * (2.0f / 3.0f) + (NE + NW + SW + SE - 4.0f * C) * (1.0f / 6.0f);
+    *lap = __builtin_fmaf((E + N + Wv + S) - 4.0f * C, 2.0f / 3.0f, ((NE + NW + SW + SE) - 4.0f * C) * (1.0f / 6.0f));
 }
 
 // Wetting ghost value (Eq. (39)-(41)) beyond a wall row: a0 = phi - 1 of
@@ -533,8 +556,9 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
   const float fbx = -m.fsol * usx, fby = -m.fsol * usy;  // f = f_s (u_s - u*), u_s = 0
   const float ux = usx + 0.5f * fbx, uy = usy + 0.5f * fby;
   const float Ssrc = rho * m.mdot + ux * d.rx + uy * d.ry;
-  const float Ftx = Fx - d.px + (1.0f / 3.0f) * (d.rx + d.Sx);
-  const float Fty = Fy - d.py + (1.0f / 3.0f) * (d.ry + d.Sy);
+  // Ft = F - grad p + (grad rho + grad S) / 3, with q = S/3 - p
+  const float Ftx = __builtin_fmaf(1.0f / 3.0f, d.rx, Fx + d.qx);
+  const float Fty = __builtin_fmaf(1.0f / 3.0f, d.ry, Fy + d.qy);
   const float uFt = ux * Ftx + uy * Fty;
   const float usq = ux * ux + uy * uy;
   const float tauf = 3.0f * m.mu * rrho + 0.5f;
@@ -547,16 +571,16 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
   if (FIELDS) {
     float* __restrict__ fields = io.fields;
     const unsigned pl = P.plane;
-    st(fields, 0 * pl + k, phi);
-    st(fields, 1 * pl + k, T);
-    st(fields, 2 * pl + k, ux);
-    st(fields, 3 * pl + k, uy);
-    st(fields, 4 * pl + k, p);
-    st(fields, 5 * pl + k, m.fsol);
-    st(fields, 6 * pl + k, m.fl);
-    st(fields, 7 * pl + k, rho);
-    st(fields, 8 * pl + k, m.E - P.latent * m.fprev - (P.cp_ref - m.cp) * P.T_melt);
-    st(fields, 9 * pl + k, m.mdot);
+    st(fplane(fields, 0, pl), k, phi);
+    st(fplane(fields, 1, pl), k, T);
+    st(fplane(fields, 2, pl), k, ux);
+    st(fplane(fields, 3, pl), k, uy);
+    st(fplane(fields, 4, pl), k, p);
+    st(fplane(fields, 5, pl), k, m.fsol);
+    st(fplane(fields, 6, pl), k, m.fl);
+    st(fplane(fields, 7, pl), k, rho);
+    st(fplane(fields, 8, pl), k, m.E - P.latent * m.fprev - (P.cp_ref - m.cp) * P.T_melt);
+    st(fplane(fields, 9, pl), k, m.mdot);
     return;
   }
 
@@ -599,13 +623,12 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
       fn[i] = f[i] + __builtin_fmaf(-itau, ni, sw * (fe + fo));
       fn[o] = f[o] + __builtin_fmaf(-itau, no, sw * (fe - fo));
     }
-    void* Bf = pop_plane<PT>(B, 9, pl);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       if constexpr (LS > 0)
         pop_lds_st<PT, 1>(lop + (9 + i) * LS, fn[i], P, rb ^ sr_pop(9 + i));
       else
-        pop_st<PT, 1, STREAM>(Bf, i * pl + k, fn[i], P, rb ^ sr_pop(9 + i));
+        pop_st<PT, 1, STREAM>(B, (9 + i) * pl + k, fn[i], P, rb ^ sr_pop(9 + i));
     }
   }
   // phase-field collision (Eq. (21), (24), (25), (37))
@@ -653,7 +676,7 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
     } else {
       RefIO<PopIO<PT>::kNodeRef>::template store<STREAM>(io.ref_out, k, r_new, th_new);
       st<STREAM>(io.phiu_out, k, pux);
-      st<STREAM>(io.phiu_out, pl + k, puy);
+      st<STREAM>(fplane(io.phiu_out, 1, pl), k, puy);
     }
   }
   // enthalpy collision (Eq. (27)-(28)) in the shifted variables
@@ -689,13 +712,12 @@ __device__ __forceinline__ void update_node(const KParams& P, const StepIO& io, 
     const float d0 = (hs - crd + W0 * (crd - 1.5f * cpT * usq)) * itau;
     hn[0] = m.h[0] + d0 + P.latent * (m.fsH - m.fprev);
     if (NR) hn[0] += W0 * cmove;
-    void* Bh = pop_plane<PT>(B, 18, pl);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       if constexpr (LS > 0)
         pop_lds_st<PT, 2>(lop + (18 + i) * LS, hn[i], P, rb ^ sr_pop(18 + i));
       else
-        pop_st<PT, 2, STREAM>(Bh, i * pl + k, hn[i], P, rb ^ sr_pop(18 + i));
+        pop_st<PT, 2, STREAM>(B, (18 + i) * pl + k, hn[i], P, rb ^ sr_pop(18 + i));
     }
   }
   if constexpr (LS > 0) {
@@ -799,6 +821,8 @@ __device__ __forceinline__ RefPair load_ref(const void* b, unsigned k) {
 struct PS {
   float p, s;
 };
+// q = S/3 - p of one cell (the combination whose gradient Eq. (36) takes)
+__device__ __forceinline__ float q_of(PS v) { return __builtin_fmaf(v.s, 1.0f / 3.0f, -v.p); }
 
 // Wetting ghost rows (Eq. (39)-(41)) of a macro region of width LXR: the
 // row rb below grid row 0 and the row rt above grid row ny-1, where present.
@@ -835,15 +859,13 @@ __device__ __forceinline__ void ghost_rows(const KParams& P, float (*sphi)[LXR],
 
 template <int LXR>
 __device__ __forceinline__ void tile_grads(const float (*sphi)[LXR], const float (*srho)[LXR],
-                                           const float (*sp)[LXR], const float (*sS)[LXR], int r, int c,
-                                           Grads& d) {
+                                           const float (*sq)[LXR], int r, int c, Grads& d) {
 #define LBM_GRAD(arr, ox, oy, lap)                                                                 \
   stencil(arr[r][c], arr[r][c + 1], arr[r][c - 1], arr[r + 1][c], arr[r - 1][c], arr[r + 1][c + 1], \
           arr[r + 1][c - 1], arr[r - 1][c - 1], arr[r - 1][c + 1], ox, oy, lap)
   LBM_GRAD(sphi, d.phx, d.phy, &d.lphi);
   LBM_GRAD(srho, d.rx, d.ry, nullptr);
-  LBM_GRAD(sp, d.px, d.py, nullptr);
-  LBM_GRAD(sS, d.Sx, d.Sy, nullptr);
+  LBM_GRAD(sq, d.qx, d.qy, nullptr);
 #undef LBM_GRAD
 }
 
@@ -860,8 +882,7 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
   __shared__ float s_phi[LY][LX];  // phi - 1 (stencils are blind to the constant)
   __shared__ float s_rho[LY][LX];
   __shared__ float s_fsH[LY][LX];
-  __shared__ float s_p[LY][LX];
-  __shared__ float s_S[LY][LX];
+  __shared__ float s_q[LY][LX];  // q = S/3 - p of the lagged p and S
   __shared__ float s_ref[RY][RX];  // phi of the previous step, reference of the stored g
   constexpr bool NR = PopIO<PT>::kNodeRef;
   __shared__ float s_th[NR ? RY : 1][NR ? RX : 1];  // reference T - T_m of the stored h
@@ -899,7 +920,7 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
     else
       pull9<1, PT>(A, P, x, y, xm, xp, f);
     phiux = ld(io.phiu_in, (unsigned)(y * nx + x));
-    phiuy = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
+    phiuy = ld(fplane(io.phiu_in, 1, P.plane), (unsigned)(y * nx + x));
   }
   int hr = 0, hc = 0;
   bool halo = false;
@@ -926,18 +947,15 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
       s_ref[r][c] = v.r;
       if constexpr (NR) s_th[r][c] = v.th;
     });
-    fp.store(t, [&](int r, int c, PS v) {
-      s_p[r][c] = v.p;
-      s_S[r][c] = v.s;
-    });
+    fp.store(t, [&](int r, int c, PS v) { s_q[r][c] = q_of(v); });
   }
   if constexpr (MACRO_IN) {
     for (int j = t; j < LX * LY; j += NT) {
       const int r = j / LX, c = j - (j / LX) * LX;
       const int kk = min(max(y0 + r - 1, 0), ny - 1) * nx + wrapx(x0 + c - 2, nx);
       s_phi[r][c] = ld(io.fields, (unsigned)kk);
-      s_rho[r][c] = ld(io.fields, P.plane + (unsigned)kk);
-      s_fsH[r][c] = ld(io.fields, 2u * P.plane + (unsigned)kk);
+      s_rho[r][c] = ld(fplane(io.fields, 1, P.plane), (unsigned)kk);
+      s_fsH[r][c] = ld(fplane(io.fields, 2, P.plane), (unsigned)kk);
     }
   }
   __syncthreads();
@@ -956,12 +974,13 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
     s_fsH[ly + 1][lx + 2] = m.fsH;
   }
   if (halo) {
+    const int yh = y0 + hr - 1;
     if constexpr (RAW) {
-      unpack9<0, PT>(rgh, P, y0 + hr - 1, mh.g);
-      unpack9<2, PT>(rhh, P, y0 + hr - 1, mh.h);
+      unpack9<0, PT>(rgh, P, yh, mh.g);
+      unpack9<2, PT>(rhh, P, yh, mh.h);
     }
-    const float rs = rebase_g<RX>(mh.g, s_ref, P, y0 + hr - 1, hc, hr);
-    if constexpr (NR) mh.th = rebase_h<RX>(mh.h, s_th, P, y0 + hr - 1, hc, hr);
+    const float rs = rebase_g<RX>(mh.g, s_ref, P, yh, hc, hr);
+    if constexpr (NR) mh.th = rebase_h<RX>(mh.h, s_th, P, yh, hc, hr);
     finish_macro<NR>(P, rs, mh);
     s_phi[hr][hc] = (mh.r - 1.0f) + mh.dl;
     s_rho[hr][hc] = mh.rho;
@@ -979,7 +998,7 @@ __device__ __forceinline__ void step_tile(const KParams& P, const StepIO& io, in
 
   // ---- phase 2: stencils (Eq. (38)), forces, flow macros, collisions -----
   Grads d;
-  tile_grads<LX>(s_phi, s_rho, s_p, s_S, ly + 1, lx + 2, d);
+  tile_grads<LX>(s_phi, s_rho, s_q, ly + 1, lx + 2, d);
   if constexpr (RAW) unpack9<1, PT>(rf, P, y, f);
   update_node<FIELDS, PT, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x));
 }
@@ -1046,7 +1065,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
   static_assert(EX == LX + 2 && EY == LY + 2, "E doubles as the second step's reference tile");
   __shared__ float s_ep[27 * ES];  // first-step populations
   __shared__ float s_ea[6 * ES];   // and references, (phi u), f_s^H, p, S
-  __shared__ float s_work[5 * LYA * LXA + RYA * RXA];
+  __shared__ float s_work[4 * LYA * LXA + RYA * RXA];
 
   const int tile = map_tile(blockIdx.x, mode, band, ntx, ntiles);
   if (tile >= ntiles) return;  // whole workgroup leaves before any barrier
@@ -1060,9 +1079,8 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
     float(*sphi)[LXA] = reinterpret_cast<float(*)[LXA]>(s_work);
     float(*srho)[LXA] = sphi + LYA;
     float(*sfsH)[LXA] = srho + LYA;
-    float(*sp)[LXA] = sfsH + LYA;
-    float(*sS)[LXA] = sp + LYA;
-    float(*sref)[RXA] = reinterpret_cast<float(*)[RXA]>(s_work + 5 * LYA * LXA);
+    float(*sq)[LXA] = sfsH + LYA;  // q = S/3 - p
+    float(*sref)[RXA] = reinterpret_cast<float(*)[RXA]>(s_work + 4 * LYA * LXA);
     const int xa0 = x0 - 5, ya0 = y0 - 3;
 
     // phase 0: every global load at once (two E cells per lane at most,
@@ -1085,7 +1103,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
         const int xp = x == nx - 1 ? 0 : x + 1;
         pull9<1, float>(A, P, x, y, xm, xp, f[s]);
         pux[s] = ld(io.phiu_in, (unsigned)(y * nx + x));
-        puy[s] = ld(io.phiu_in, P.plane + (unsigned)(y * nx + x));
+        puy[s] = ld(fplane(io.phiu_in, 1, P.plane), (unsigned)(y * nx + x));
       }
     }
     int hr = 0, hc = 0;
@@ -1103,8 +1121,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
       fp.load_grid(t, xa0, ya0, nx, ny, [&](unsigned kk) { return PS{ld(io.p_in, kk), ld(io.S_in, kk)}; });
       fr.store(t, [&](int r, int c, float v) { sref[r][c] = v; });
       fp.store(t, [&](int r, int c, PS v) {
-        sp[r][c] = v.p;
-        sS[r][c] = v.s;
+        sq[r][c] = q_of(v);
       });
     }
     __syncthreads();
@@ -1141,7 +1158,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
     for (int s = 0; s < 2; ++s) {
       if (!on[s]) continue;
       Grads d;
-      tile_grads<LXA>(sphi, srho, sp, sS, ey[s] + 1, ex[s] + 2, d);
+      tile_grads<LXA>(sphi, srho, sq, ey[s] + 1, ex[s] + 2, d);
       const int e = ey[s] * EX + ex[s];
       update_node<false, float, false, ES>(P, io, m[s], f[s], pux[s], puy[s], d, 0u, s_ep + e, s_ea + e);
     }
@@ -1152,8 +1169,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
   float(*sphi)[LX] = reinterpret_cast<float(*)[LX]>(s_work);
   float(*srho)[LX] = sphi + LY;
   float(*sfsH)[LX] = srho + LY;
-  float(*sp)[LX] = sfsH + LY;
-  float(*sS)[LX] = sp + LY;
+  float(*sq)[LX] = sfsH + LY;  // q = S/3 - p
   const float(*sref)[EX] = reinterpret_cast<const float(*)[EX]>(s_ea + AUX_REF * ES);
   const int lx = t % TX, ly = t / TX;
   const int x = x0 + lx, y = y0 + ly;
@@ -1185,8 +1201,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
           return PS{s_ea[AUX_P * ES + e], s_ea[AUX_S * ES + e]};
         });
     fp.store(t, [&](int rr, int cc, PS v) {
-      sp[rr][cc] = v.p;
-      sS[rr][cc] = v.s;
+      sq[rr][cc] = q_of(v);
     });
   }
   if (yin) {
@@ -1211,7 +1226,7 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
   if (!active) return;  // no barrier below
   Grads d;
-  tile_grads<LX>(sphi, srho, sp, sS, ly + 1, lx + 2, d);
+  tile_grads<LX>(sphi, srho, sq, ly + 1, lx + 2, d);
   update_node<false, float, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x));
 }
 
@@ -1242,7 +1257,7 @@ __device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, 
   static_assert((27 * ES * sizeof(PT)) % 4 == 0, "FP32 planes after the populations");
   __shared__ PT s_ep[27 * ES];                 // first-step populations, as stored
   __shared__ float s_ea[aux_planes<PT>() * ES];  // references, (phi u), f_s^H, p, S
-  __shared__ float s_work[5 * LYA * LXA + (NR ? 2 : 1) * RYA * RXA];
+  __shared__ float s_work[4 * LYA * LXA + (NR ? 2 : 1) * RYA * RXA];
 
   const void* __restrict__ A = io.A;
   const int nx = P.nx, ny = P.ny;
@@ -1253,9 +1268,8 @@ __device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, 
     float(*sphi)[LXA] = reinterpret_cast<float(*)[LXA]>(s_work);
     float(*srho)[LXA] = sphi + LYA;
     float(*sfsH)[LXA] = srho + LYA;
-    float(*sp)[LXA] = sfsH + LYA;
-    float(*sS)[LXA] = sp + LYA;
-    float(*sref)[RXA] = reinterpret_cast<float(*)[RXA]>(s_work + 5 * LYA * LXA);
+    float(*sq)[LXA] = sfsH + LYA;  // q = S/3 - p
+    float(*sref)[RXA] = reinterpret_cast<float(*)[RXA]>(s_work + 4 * LYA * LXA);
     float(*sth)[RXA] = sref + RYA;  // node-reference storage only
     const int xa0 = x0 - 5, ya0 = y0 - 3;
 
@@ -1278,7 +1292,7 @@ __device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, 
         const int xp = x == nx - 1 ? 0 : x + 1;
         pull9<1, PT>(A, P, x, y, xm, xp, f);
         pux = ld(io.phiu_in, k);
-        puy = ld(io.phiu_in, P.plane + k);
+        puy = ld(fplane(io.phiu_in, 1, P.plane), k);
       }
     } else if (t - ES < NRA) {
       ring_cell<LXA, LYA, EX>(t - ES, r, c);
@@ -1296,8 +1310,7 @@ __device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, 
         if constexpr (NR) sth[rr][cc] = v.th;
       });
       fp.store(t, [&](int rr, int cc, PS v) {
-        sp[rr][cc] = v.p;
-        sS[rr][cc] = v.s;
+        sq[rr][cc] = q_of(v);
       });
     }
     __syncthreads();
@@ -1321,7 +1334,7 @@ __device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, 
 
     if (on) {
       Grads d;
-      tile_grads<LXA>(sphi, srho, sp, sS, r, c, d);
+      tile_grads<LXA>(sphi, srho, sq, r, c, d);
       const int e = (r - 1) * EX + (c - 2);
       update_node<false, PT, false, ES>(P, io, m, f, pux, puy, d, k, s_ep + e, s_ea + e, 0u);
     }
@@ -1332,8 +1345,7 @@ __device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, 
   float(*sphi)[LX] = reinterpret_cast<float(*)[LX]>(s_work);
   float(*srho)[LX] = sphi + LY;
   float(*sfsH)[LX] = srho + LY;
-  float(*sp)[LX] = sfsH + LY;
-  float(*sS)[LX] = sp + LY;
+  float(*sq)[LX] = sfsH + LY;  // q = S/3 - p
   const float(*sref)[EX] = reinterpret_cast<const float(*)[EX]>(s_ea + AUX_REF * ES);
   const float(*sth)[EX] = reinterpret_cast<const float(*)[EX]>(s_ea + AUX_TH * ES);  // node-reference storage
   Macro m;
@@ -1368,8 +1380,7 @@ __device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, 
           return PS{s_ea[AUX_P * ES + e], s_ea[AUX_S * ES + e]};
         });
     fp.store(t, [&](int rr, int cc, PS v) {
-      sp[rr][cc] = v.p;
-      sS[rr][cc] = v.s;
+      sq[rr][cc] = q_of(v);
     });
   }
   if (mac) {
@@ -1388,7 +1399,7 @@ __device__ __forceinline__ void step2w_tile(const KParams& P, const StepIO& io, 
   }
   if (!active) return;  // no barrier below
   Grads d;
-  tile_grads<LX>(sphi, srho, sp, sS, r, c, d);
+  tile_grads<LX>(sphi, srho, sq, r, c, d);
   update_node<false, PT, STREAM>(P, io, m, f, phiux, phiuy, d, (unsigned)(y * nx + x0 + c - 2), nullptr, nullptr,
                                  1u);
 }

@@ -551,10 +551,17 @@ def test_sessile512_1000_steps_in_the_benchmarked_launch(oracle_mod):
     any perturbation (the oracle against itself with phi0 perturbed by 1e-7
     already differs by ~0.1 in phi at a dip), so, as for the Sec. 4.2.1
     droplet, T, u and the L2 norm of phi are held within twice the method's
-    own sensitivity (two draws, floored at the stated tolerances).  The
-    conserved sums (phi, clamp(phi), H) match to 2e-6 of their scale; the
-    solid and liquid volumes, which the dips move, within twice their
-    envelope.  Pointwise phi is reported."""
+    own sensitivity, floored at the stated tolerances: the largest deviation
+    of the oracle from itself over eight draws, four with phi0 perturbed by
+    1e-7 and four with phi moved by 1e-8 after every step (stored by
+    tests/golden/make_sensitivity_envelopes.py, which runs the oracle only;
+    the per-step draws take minutes each at this size).  The solid and
+    liquid volumes, which the dips move, are held the same way (the draws
+    move the solid volume by 2e-6 to 8e-5); the conserved sums (phi,
+    clamp(phi), H) to 2e-6 of their scale.  Pointwise phi is reported."""
+    import json
+    import os
+
     lbm = _gpu()
     p, phi0, T0, _ = W.workload("sessile512", seed=0)
     g = lbm.Solver(p, phi0, T0)
@@ -564,22 +571,12 @@ def test_sessile512_1000_steps_in_the_benchmarked_launch(oracle_mod):
     o = oracle_mod.OracleSolver(p, phi0, T0)
     o.step(1000)
     fo, fg = o.fields(FIELDS), g.fields(FIELDS)
-    env = dict(phi=0.0, T=1e-5, u=1e-4, lphi=0.0)
     do = o.diag()
     vols = ("sum_solid", "sum_liquid")
-    env_vol = {k: 2e-6 for k in vols}
-    for draw in range(2):
-        z = np.random.default_rng(5120 + draw).standard_normal(phi0.size)
-        o2 = oracle_mod.OracleSolver(p, phi0 + 1e-7 * z, T0)
-        o2.step(1000)
-        f2 = o2.fields(FIELDS)
-        env["phi"] = max(env["phi"], np.abs(f2["phi"] - fo["phi"]).max())
-        env["T"] = max(env["T"], np.abs(f2["T"] - fo["T"]).max())
-        env["u"] = max(env["u"], relL2(np.stack([f2["ux"], f2["uy"]]), np.stack([fo["ux"], fo["uy"]])))
-        env["lphi"] = max(env["lphi"], relL2(f2["phi"], fo["phi"]))
-        d2 = o2.diag()
-        for k in vols:
-            env_vol[k] = max(env_vol[k], abs(d2[k] - do[k]) / max(1.0, abs(do[k])))
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sensitivity_envelopes.json")) as f:
+        stored = json.load(f)["sessile512_1000"]["max"]
+    env = dict(phi=stored["phi"], T=max(1e-5, stored["T"]), u=max(1e-4, stored["u"]), lphi=stored["lphi"])
+    env_vol = {k: max(2e-6, stored[k]) for k in vols}
     dT = np.abs(fg["T"] - fo["T"]).max()
     eu = relL2(np.stack([fg["ux"], fg["uy"]]), np.stack([fo["ux"], fo["uy"]]))
     lphi = relL2(fg["phi"], fo["phi"])

@@ -262,11 +262,15 @@ def test_layered_channel_flow_against_the_momentum_balance(oracle_mod, storage):
     o.step(10000)
     uo = o.fields(["ux"])["ux"]
     du = np.abs(f["ux"] - uo).max() / uo.max()
-    print(f"{storage} layered: |u - balance| {err:.3e}; GPU vs oracle {du:.2e}", flush=True)
-    # measured: FP32 6.65e-2 (as the oracle) and 2.6e-5 from the oracle;
-    # FP16 6.85e-2 and 1.8e-3; BF16 6.95e-2 and 4.3e-3
-    assert err < 8e-2
-    assert du < {"fp32": 1e-3, "fp16": 1e-2, "bf16": 2e-2}[storage]
+    err_o = np.abs(uo[:, 1] - ref).max() / ref.max()
+    print(f"{storage} layered: |u - balance| {err:.3e} (oracle {err_o:.3e}); GPU vs oracle {du:.2e}", flush=True)
+    # the oracle's own distance from the balance (6.65e-2) is the diffuse
+    # interface's discretisation error; the GPU may add its storage noise.
+    # Measured GPU vs oracle over twelve starts (phi0 perturbed by 1e-6):
+    # FP32 ~1e-5; FP16 7e-4 to 2.5e-3; BF16 (8-bit mantissa) 5e-3 to 2.7e-2
+    tol = {"fp32": 1e-3, "fp16": 1e-2, "bf16": 4e-2}[storage]
+    assert du < tol
+    assert err < err_o + tol
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])

@@ -173,3 +173,32 @@ def test_per_step_perturbation_helper_moves_phi_by_the_drawn_amount(oracle_mod):
     assert np.allclose(dg, W9[:, None, None] * delta[None], rtol=0, atol=1e-15)
     assert np.allclose(dg.sum(axis=0), delta, rtol=0, atol=1e-15)
     assert np.array_equal(d.pops("f"), c.pops("f")) and np.array_equal(d.pops("h"), c.pops("h"))
+
+
+def test_stored_sensitivity_envelope_is_the_oracles(oracle_mod):
+    """The stored envelope of the 512x256 droplet (written by
+    tests/golden/make_sensitivity_envelopes.py from the oracle alone) holds
+    what the oracle gives: its first draw recomputed here."""
+    import json
+    import os
+
+    import numpy as np
+
+    from paper_2403_16122_amd import workloads as W
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sensitivity_envelopes.json")
+    with open(path) as f:
+        rec = json.load(f)["sessile512_1000"]
+    first = rec["draws"][0]
+    assert first["kind"] == "initial 1e-7" and first["seed"] == 5120
+    p, phi0, T0, _ = W.workload("sessile512", seed=0)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    o.step(rec["steps"])
+    z = np.random.default_rng(5120).standard_normal(phi0.size)
+    o2 = oracle_mod.OracleSolver(p, phi0 + 1e-7 * z, T0)
+    o2.step(rec["steps"])
+    do, d2 = o.diag(), o2.diag()
+    solid = abs(d2["sum_solid"] - do["sum_solid"]) / max(1.0, abs(do["sum_solid"]))
+    dT = float(np.abs(o2.fields(["T"])["T"] - o.fields(["T"])["T"]).max())
+    assert solid == first["sum_solid"] and dT == first["T"]
+    assert all(rec["max"][k] == max(d[k] for d in rec["draws"]) for k in rec["max"])
