@@ -16,10 +16,12 @@ from paper_2403_16122_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-# The stored sweep records against a fresh run of the batched solver: equal
-# when both come from the same build of the kernels; a build whose FP32
-# arithmetic rounds differently moves t* of these droplets by ~1e-5.
-STORED_REL = 1e-3
+# The stored sweep records against a fresh run of the batched solver: the
+# records are written by paper_2403_16122_amd/sweep_data.py with the kernels
+# of this build, so they are equal bit for bit (a kernel change that moves the
+# FP32 rounding moves t* of these droplets by ~1e-5 and calls for writing them
+# again).
+STORED_REL = 1e-12
 
 DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2403_16122_amd", "data")
 
@@ -62,9 +64,9 @@ def test_error_model_ranks_errors_and_holds_the_2pct_threshold(fitted):
     than the ensemble's spread, and at the 2 % threshold the droplets it
     accepts keep their errors within it at the 95th percentile, while it
     accepts enough of them to save solver time.  Measured on MI355X: rank
-    correlation 0.43 (calibration) and 0.38 (held out) against 0.10 for the
-    spread; 31 % accepted, accepted error median 0.47 %, 95th percentile
-    2.03 %."""
+    correlation 0.43 (calibration) and 0.36 (held out) against 0.06 for the
+    spread; 31 % accepted, accepted error median 0.42 %, 95th percentile
+    1.71 %."""
     S, sur, te = fitted
     ev = S.evaluate(sur, te)
     print({k: (round(v, 5) if isinstance(v, float) else v) for k, v in ev.items()}, flush=True)
