@@ -18,9 +18,9 @@
  * (39)-(41) wetting boundary.  Where the paper is silent or garbled the
  * reading taken is named inline; the full list lives with the design notes.
  *
- * Parity unpinned: the c_s^2 grad S term of F~ (Eq. (33)).  No closed form
- * in the tests reaches it (it needs flow across a gradient of the mass
- * source), so only this definition and parity with the GPU library fix it.
+ * Every term is pinned by a CPU test against a closed form; the c_s^2 grad S
+ * term of F~ (Eq. (33)) by the exact one-step response of the pressure of
+ * Eq. (36) to a prescribed lagged S under uniform flow.
  *
  * Plain loops; OpenMP splits rows of each pass (results do not depend on the
  * thread count: no reduction runs in parallel).

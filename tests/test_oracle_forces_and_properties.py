@@ -16,7 +16,11 @@ mistake in the term fails it by far more than the discretisation error:
   (the property ratios of Sec. 4.2.1) and a superheated liquid, against
   the similarity solution of the enthalpy formulation (swapped
   conductivities or heat capacities, or breakpoints of Eq. (9) that ignore
-  the mixture heat capacity, move the front by 10-50 %).
+  the mixture heat capacity, move the front by 10-50 %);
+- the one-step pressure response to a prescribed lagged mass source under
+  uniform flow, which fixes the c_s^2 grad S term of F~ (Eq. (33), (36);
+  exact to rounding: a dropped term, a flipped sign or a missing c_s^2
+  misses it by 100 % or more).
 """
 import math
 
@@ -142,3 +146,59 @@ def test_two_phase_front_with_unequal_heat_capacity_and_conductivity(oracle_mod)
         assert abs(front - exact) < 0.04 * exact, (t, front, exact)
     # the offset is a fixed fraction of a lattice spacing, not a rate error
     assert max(offs) - min(offs) < 0.05 and all(-1.0 < o < 0.0 for o in offs), offs
+
+
+def test_lagged_mass_source_gradient_enters_the_pressure_through_the_forcing(oracle_mod):
+    """The c_s^2 grad S term of F~ (Eq. (33), with S the lagged mass source
+    of Eq. (38)) reaches the pressure of Eq. (36) through the forcing's rest
+    component F_0 = w_0 (S - u.F~ / c_s^2).  One liquid phase above T_m
+    (nothing freezes, rho uniform: the current S = rho mdot + u.grad rho is
+    0), moving uniformly with u0 along x, started from f = f^eq(0, rho, u0)
+    with a prescribed lagged S(x) = A sin(2 pi x / nx): after one step the
+    pressure differs from the same step with S = 0 by
+        dp = c_s^2 / (1 - w_0) tau_f (-w_0 u0 dS/dx) = -(4/15) tau_f u0 dS/dx,
+    dS/dx being the isotropic stencil of S, (S(x+1) - S(x-1)) / 2 for a
+    field constant in y.  Exact to rounding; without the term dp = 0, with
+    its sign flipped -1x, with grad S not scaled by c_s^2 3x.  The lagged
+    state is written through the oracle's checkpoint (four int64 header
+    words, then g, f, h as nine planes each, then (phi u)_x, (phi u)_y,
+    f_s^H, p and S of the previous step)."""
+    nx, ny, u0, A = 16, 8, 0.02, 1e-3
+    p = W.default_params(nx, ny, T_bottom=2.0, rho_s=1.0)
+    n = nx * ny
+    base = oracle_mod.OracleSolver(p, np.ones(n), np.full(n, 2.0), threads=1)
+    rho = base.fields(["rho"])["rho"]
+    assert np.ptp(rho) == 0.0
+    feq = np.asarray(oracle_mod.node_feq(0.0, float(rho.flat[0]), u0, 0.0))
+    blob0 = bytearray(base.save())
+    off = 32 + 9 * n * 8  # the f planes follow the nine g planes
+
+    def run(S_prev):
+        o = oracle_mod.OracleSolver(p, np.ones(n), np.full(n, 2.0), threads=1)
+        blob = bytearray(blob0)
+        blob[off:off + 9 * n * 8] = np.repeat(feq, n).tobytes()
+        hist = 32 + 27 * n * 8  # (phi u)_x, (phi u)_y, f_s^H, p, S
+        blob[hist:hist + 8 * n] = np.full(n, u0).tobytes()
+        blob[hist + 8 * n:hist + 16 * n] = np.zeros(n).tobytes()
+        blob[hist + 32 * n:hist + 40 * n] = np.ascontiguousarray(S_prev, dtype=np.float64).reshape(-1).tobytes()
+        o.load(bytes(blob))
+        o.step(1)
+        after = o.save()
+        pr = np.frombuffer(after, dtype=np.float64, count=n, offset=hist + 24 * n)
+        ux = np.frombuffer(after, dtype=np.float64, count=n, offset=hist)  # phi u with phi = 1
+        return pr.reshape(ny, nx), ux.reshape(ny, nx)
+
+    x = np.arange(nx)
+    S = np.tile(A * np.sin(2.0 * np.pi * x / nx), (ny, 1))
+    (p1, ux), (p0, ux0) = run(S), run(np.zeros_like(S))
+    assert np.array_equal(ux, ux0)  # the lagged S moves the pressure only
+    dp = p1 - p0
+    dSdx = 0.5 * (np.roll(S, -1, axis=1) - np.roll(S, 1, axis=1))
+    tau_f = 3.0 * p["mu_l"] / p["rho_l"] + 0.5
+    # u is the step's velocity: u0 away from the walls, less in the wall rows,
+    # where half-way bounce-back has already acted
+    assert np.abs(ux[2:-2] - u0).max() < 1e-15
+    expect = -(4.0 / 15.0) * tau_f * ux * dSdx
+    scale = np.abs(expect).max()
+    assert scale > 1e-6
+    assert np.abs(dp - expect).max() < 1e-12 * scale, np.abs(dp - expect).max() / scale
