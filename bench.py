@@ -407,6 +407,41 @@ def timed_run(lbm, W, name: str, storage: str, steps: int, warmup: int, args):
     return rec, secs, wall, (params, phi0, T0, meta)
 
 
+def persistent_vs_per_step(lbm, W, name: str, steps: int, warmup: int):
+    """`steps` FP32 steps of a workload as one persistent cooperative launch
+    (a grid-wide barrier between steps, lbm_step_persistent) and as one
+    launch per step, both on 64x8 tiles in tile order 2 from the same state;
+    HIP events on the solver's stream bracket each.  The persistent call
+    also clears its barrier words and reads them back (a few microseconds
+    per call)."""
+    import torch
+
+    params, phi0, T0, _ = W.workload(name, seed=0)
+    N = params["nx"] * params["ny"]
+    rec = {"workload": name, "steps": steps, "tile": "64x8", "xcd_remap": 2}
+    for mode in ("per_step", "persistent"):
+        s = lbm.Solver(params, phi0, T0)
+        s.set_launch("64x8", 2)
+        run = s.step if mode == "per_step" else s.step_persistent
+        run(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s.stream)
+        wg = run(steps)
+        e1.record(s.stream)
+        torch.cuda.synchronize()
+        secs = e0.elapsed_time(e1) / 1e3
+        rec[mode] = {"us_per_step": round(secs / steps * 1e6, 3), "MLUPS": round(N * steps / secs / 1e6, 1)}
+        if mode == "persistent":
+            rec[mode]["workgroups"] = wg
+        del s
+        torch.cuda.empty_cache()
+    rec["persistent_over_per_step"] = round(rec["persistent"]["us_per_step"] / rec["per_step"]["us_per_step"], 3)
+    note(f"{name}: per-step launches {rec['per_step']['us_per_step']} us/step, "
+         f"persistent {rec['persistent']['us_per_step']} us/step")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -435,6 +470,8 @@ def main():
                     help="skip training and scoring the surrogate network")
     ap.add_argument("--no-others", dest="others", action="store_false",
                     help="headline workload only (no 128x64 and 512x256 rates)")
+    ap.add_argument("--no-persistent", dest="persistent", action="store_false",
+                    help="skip the persistent-launch comparison")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -502,6 +539,18 @@ def main():
             if name == "sessile512" and args.to_frozen:
                 out["to_frozen"] = to_frozen(lbm, pp, pphi, pT, rec["tile"], rec["xcd_remap"])
             torch.cuda.empty_cache()
+    if args.persistent:
+        # one persistent launch over all steps against one launch per step
+        per = {}
+        runs = [(n, max(args.steps, 200)) for n in ("sessile128", "sessile512", args.workload)]
+        if args.probe_steps > 0:
+            runs.append(("probe4096", args.probe_steps))
+        for name, n in runs:
+            try:
+                per[name] = persistent_vs_per_step(lbm, W, name, n, 10)
+            except lbm.LbmError as e:
+                per[name] = {"error": str(e)}
+        out["persistent_launch"] = per
     if args.probe_steps > 0:
         # the roofline: the dominant step kernel on a state beyond the Infinity Cache
         prec, psecs, _, (pp, pphi, pT, _m) = timed_run(lbm, W, "probe4096", "fp32", args.probe_steps, 10, args)

@@ -113,6 +113,21 @@ int lbm_init(const lbm_params* p, const double* phi0, const double* T0, void* d_
  * negative count; launch failures give LBM_EDEVICE. */
 int lbm_step(lbm_ctx* c, int32_t nsteps);
 
+/* The same nsteps time steps (Sec. 3, as lbm_step) in ONE persistent launch:
+ * a cooperative grid of co-resident workgroups on 64x8 tiles (the context's
+ * xcd_remap order; its tile variant is not used) loops over the steps with a
+ * grid-wide barrier between them, since every step pulls the halo its
+ * neighbours wrote in the step before.  Results are bitwise those of
+ * lbm_step.  Kept to measure a persistent launch against one launch per
+ * step; lbm_step is the faster path on MI355X.  nsteps in
+ * 0..LBM_PERSIST_MAX_STEPS (else LBM_EINVAL).  *workgroups (optional)
+ * receives the grid size.  Uses the context's reduction scratch for the
+ * barrier.  Synchronises.  LBM_EDEVICE if the device has no cooperative
+ * launch, no grid fits, or a barrier wait exceeded 2 s (then the state is
+ * invalid: every wave still leaves the kernel). */
+#define LBM_PERSIST_MAX_STEPS 1000000
+int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t* workgroups);
+
 /* Macroscopic fields at the current time level as the next step would
  * compute them: phi (Eq. (26)), T and f_l (Eq. (9)), u (Eq. (34)-(35), with
  * the fluid-solid force), p (Eq. (36)), f_s = clamp(phi) (1 - f_l), rho

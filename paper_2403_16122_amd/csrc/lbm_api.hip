@@ -358,6 +358,40 @@ int lbm_step(lbm_ctx* c, int32_t nsteps) {
   return LBM_OK;
 }
 
+int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t* workgroups) {
+  if (!c || nsteps < 0 || nsteps > LBM_PERSIST_MAX_STEPS) return LBM_EINVAL;
+  if (nsteps == 0) return LBM_OK;
+  int rate_khz = 0;
+  LBM_CK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
+  if (rate_khz <= 0) {
+    g_last_error = "device reports no wall-clock rate";
+    return LBM_EDEVICE;
+  }
+  // a barrier wait of 2 s is a failure: a step of the largest grid takes ~1 ms
+  const unsigned long long limit = 2000ull * (unsigned long long)rate_khz;
+  // the barrier words sit in the reduction scratch, which no step reads
+  unsigned long long* bar = (unsigned long long*)c->S.part;
+  c->K.seed = (unsigned)c->step;
+  int grid = 0;
+  hipError_t e = lbmk::launch_persist(c->K, c->S, c->cur, nsteps, c->xcd, bar, limit, &grid, c->stream);
+  if (e != hipSuccess) return dev_error(e, "persistent step launch");
+  unsigned long long flag[2] = {0, 0};
+  LBM_CK(hipMemcpyAsync(flag, bar, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+  LBM_CK(hipStreamSynchronize(c->stream));
+  if (flag[1]) {
+    g_last_error = "grid barrier of the persistent step timed out; the state is invalid";
+    return LBM_EDEVICE;
+  }
+  if (flag[0] != (unsigned long long)(nsteps - 1) * (unsigned long long)grid) {
+    g_last_error = "grid barrier arrivals of the persistent step do not add up; the state is invalid";
+    return LBM_EDEVICE;
+  }
+  if ((nsteps & 1) != 0) c->cur ^= 1;
+  c->step += nsteps;
+  if (workgroups) *workgroups = grid;
+  return LBM_OK;
+}
+
 int lbm_fields_device(lbm_ctx* c, uint32_t mask, float* const* d_out) {
   if (!c || !d_out || (mask >> lbmk::NFIELD)) return LBM_EINVAL;
   int rc = run_fields(c);

@@ -70,7 +70,7 @@ struct StepIO {
 };
 
 
-inline StepIO make_io(const State& S, int cur) {
+__host__ __device__ inline StepIO make_io(const State& S, int cur) {
   const int nxt = cur ^ 1;
   return StepIO{S.pops[cur], S.pops[nxt], S.phiu[cur], S.phiu[nxt], S.ref[cur], S.ref[nxt],
                 S.fsH[cur], S.fsH[nxt], S.p[cur], S.p[nxt], S.S[cur], S.S[nxt], S.fields};
@@ -115,6 +115,15 @@ int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int
 // every format; steps P.seed and P.seed + 1): reads buffer cur, writes
 // buffer cur^1, like one step.
 int launch_step2(const KParams& P, const State& S, int cur, int tile_variant, int xcd_remap, hipStream_t st);
+// nsteps single steps n -> n + nsteps (steps P.seed, P.seed + 1, ...) in one
+// cooperative launch on 64x8 tiles, with a grid-wide barrier between steps.
+// bar: two 64-bit words of device memory (zeroed here on the stream); bar[1]
+// is nonzero afterwards if a barrier wait exceeded limit_ticks of the
+// device's wall clock.  *grid_out receives the number of workgroups.
+// Returns the runtime's error, hipErrorNotSupported without cooperative
+// launches, or hipErrorCooperativeLaunchTooLarge if no grid fits.
+hipError_t launch_persist(const KParams& P, const State& S, int cur, int nsteps, int xcd_remap,
+                          unsigned long long* bar, unsigned long long limit_ticks, int* grid_out, hipStream_t st);
 // The 9 populations of `lattice` as FP32 (shifted variables) into the first
 // nine field planes.
 int launch_expand(const KParams& P, const State& S, int cur, int lattice, hipStream_t st);

@@ -1011,6 +1011,84 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
   step_tile<TX, TY, FIELDS, PT, false, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
 }
 
+// ---- many steps per launch (persistent grid) -----------------------------
+// Every step pulls the halo its neighbours wrote in the step before, so one
+// launch over several steps needs a grid-wide barrier between them.  It is
+// only safe when every workgroup is resident at once, which a cooperative
+// launch guarantees (the runtime refuses a grid that does not fit).
+//
+// bar[0] counts arrivals over the whole launch: barrier k (from 1) is
+// complete once it reaches k * gridDim.x.  A wait longer than `limit`
+// wall-clock ticks sets bar[1]; no workgroup waits once it is set, and the
+// kernel stops stepping, so every wave reaches the end whatever happens and
+// the host reports the flag.  Each wave first waits for its own stores;
+// thread 0 then publishes the workgroup's stores at agent scope (the 8
+// XCDs' L2s are not coherent: release writes dirty L2 lines back) with its
+// arrival, and after the wait acquires the others' (L2 invalidate).
+__device__ __forceinline__ bool grid_barrier(unsigned long long* bar, unsigned long long target,
+                                             unsigned long long limit) {
+  __shared__ unsigned s_go;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned go = 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);  // the write-back has completed before the arrival counts
+    __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long t0 = wall_clock64();
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull) {
+        go = 0;
+        break;
+      }
+      if (wall_clock64() - t0 > limit) {
+        __hip_atomic_store(bar + 1, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        go = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
+    s_go = go;
+  }
+  __syncthreads();
+  return s_go != 0;
+}
+
+// The buffers of the step after io's: its outputs become the inputs.
+__device__ __forceinline__ StepIO next_io(const StepIO& io) {
+  return StepIO{io.B, const_cast<void*>(io.A), io.phiu_out, const_cast<float*>(io.phiu_in),
+                io.ref_out, const_cast<void*>(io.ref_in), io.fsH_out, const_cast<float*>(io.fsH_in),
+                io.p_out, const_cast<float*>(io.p_in), io.S_out, const_cast<float*>(io.S_in), io.fields};
+}
+
+// nsteps single steps in one launch from the buffers io: step s reads what
+// step s - 1 wrote and seeds the stochastic rounding with P.seed + s,
+// exactly as nsteps k_step launches would.  Workgroup b takes the tiles
+// k_step's workgroups b, b + gridDim.x, ... would take; gridDim.x is a
+// multiple of 8 (or the whole launch), so each tile stays on the XCD the
+// tile order gives it.
+template <int TX, int TY, class PT, bool STREAM>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(4))) void k_persist(
+    KParams P, StepIO io, int nsteps, int ntx, int ntiles, int band, int mode, int vgrid,
+    unsigned long long* bar, unsigned long long limit) {
+  const unsigned seed0 = P.seed;
+  for (int s = 0; s < nsteps; ++s, io = next_io(io)) {
+    P.seed = seed0 + (unsigned)s;
+    for (int v = blockIdx.x; v < vgrid; v += gridDim.x) {
+      const int tile = map_tile(v, mode, band, ntx, ntiles);  // uniform over the workgroup
+      if (tile < ntiles) step_tile<TX, TY, false, PT, false, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
+      __syncthreads();  // the next tile refills the LDS
+    }
+    if (s + 1 < nsteps && !grid_barrier(bar, (unsigned long long)(s + 1) * gridDim.x, limit)) return;
+  }
+}
+
+__global__ void k_zero_words(unsigned long long* w, int n) {
+  if ((int)threadIdx.x < n) w[threadIdx.x] = 0ull;
+}
+
 // ---- two steps per launch (FP32) -----------------------------------------
 // The second step of a TX x TY tile reads first-step results on the tile
 // plus 3 columns and 2 rows on each side (its halo macros pull from one cell
@@ -1906,6 +1984,53 @@ int launch_step2(const KParams& P, const State& S, int cur, int tile_variant, in
     default:
       return -1;
   }
+}
+
+namespace {
+
+template <int TX, int TY, class PT>
+hipError_t launch_persist_t(const KParams& P, const State& S, int cur, int nsteps, int xcd,
+                            unsigned long long* bar, unsigned long long limit, int* grid_out, hipStream_t st) {
+  const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
+  int ntiles = ntx * nty, band = 0, vgrid = ntiles;
+  if (xcd == 1) {
+    band = (ntiles + 7) / 8;
+    vgrid = 8 * band;
+  } else if (xcd == 2) {
+    band = (ntx + 7) / 8;
+    vgrid = 8 * band * nty;
+  }
+  const void* fn = P.stream_stores ? (const void*)k_persist<TX, TY, PT, true> : (const void*)k_persist<TX, TY, PT, false>;
+  int dev = 0, ncu = 0, coop = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, TX * TY, 0);
+  if (e != hipSuccess) return e;
+  if (!coop) return hipErrorNotSupported;
+  // co-resident workgroups, a multiple of 8 so that the XCD of a tile is the
+  // one its place in the tile order gives it
+  const int cap = (per_cu * ncu) & ~7;
+  if (cap < 8) return hipErrorCooperativeLaunchTooLarge;
+  int grid = vgrid < cap ? vgrid : cap;
+  *grid_out = grid;
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, bar, 2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  KParams Pa = P;
+  StepIO io = make_io(S, cur);
+  void* args[] = {&Pa, &io, &nsteps, (void*)&ntx, &ntiles, &band, &xcd, &vgrid, &bar, &limit};
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(TX * TY), args, 0, st);
+}
+
+}  // namespace
+
+hipError_t launch_persist(const KParams& P, const State& S, int cur, int nsteps, int xcd_remap,
+                          unsigned long long* bar, unsigned long long limit_ticks, int* grid_out, hipStream_t st) {
+  if (P.storage == STORE_FP16)
+    return launch_persist_t<64, 8, _Float16>(P, S, cur, nsteps, xcd_remap, bar, limit_ticks, grid_out, st);
+  if (P.storage == STORE_BF16)
+    return launch_persist_t<64, 8, __bf16>(P, S, cur, nsteps, xcd_remap, bar, limit_ticks, grid_out, st);
+  return launch_persist_t<64, 8, float>(P, S, cur, nsteps, xcd_remap, bar, limit_ticks, grid_out, st);
 }
 
 int launch_expand(const KParams& P, const State& S, int cur, int lattice, hipStream_t st) {

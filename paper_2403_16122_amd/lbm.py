@@ -31,8 +31,8 @@ STORE_MODES = {"auto": 0, "cached": 1, "streaming": 2}  # lbm_set_store_mode  # 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 
 EXPORTED = [
-    "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_fields", "lbm_fields_device", "lbm_diag",
-    "lbm_pops", "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_step_count", "lbm_sync",
+    "lbm_workspace_bytes", "lbm_init", "lbm_step", "lbm_step_persistent", "lbm_fields", "lbm_fields_device",
+    "lbm_diag", "lbm_pops", "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_step_count", "lbm_sync",
     "lbm_destroy", "lbm_strerror", "lbm_last_error", "lbm_set_launch", "lbm_set_store_mode", "lbm_autotune",
     "lbm_batch_workspace_bytes", "lbm_batch_init", "lbm_batch_configure", "lbm_batch_set_launch",
     "lbm_batch_autotune", "lbm_batch_set_store_mode", "lbm_batch_step", "lbm_batch_results", "lbm_batch_fields",
@@ -40,6 +40,7 @@ EXPORTED = [
     "lbm_mlp_param_count", "lbm_mlp_create", "lbm_mlp_set_params", "lbm_mlp_get_params", "lbm_mlp_forward",
     "lbm_mlp_gradient", "lbm_mlp_train", "lbm_mlp_last_error", "lbm_mlp_destroy", "lbm_mlp_forward_noalloc",
 ]
+PERSIST_MAX_STEPS = 1000000  # LBM_PERSIST_MAX_STEPS
 DROP_STATUS = {0: "queued", 1: "running", 2: "frozen", 3: "limit", 4: "nonfinite"}
 
 
@@ -96,6 +97,7 @@ def load_library():
     L.lbm_workspace_bytes.argtypes = [C.POINTER(Params), C.POINTER(C.c_size_t)]
     L.lbm_init.argtypes = [C.POINTER(Params), dp, dp, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.lbm_step.argtypes = [vp, C.c_int32]
+    L.lbm_step_persistent.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
     L.lbm_fields.argtypes = [vp, C.c_uint32, C.POINTER(dp)]
     L.lbm_fields_device.argtypes = [vp, C.c_uint32, C.POINTER(vp)]
     L.lbm_diag.argtypes = [vp, C.POINTER(Diag)]
@@ -227,6 +229,14 @@ class Solver:
 
     def step(self, n: int = 1):
         self._check(self.L.lbm_step(self._h, int(n)), "lbm_step")
+
+    def step_persistent(self, n: int = 1) -> int:
+        """The same n steps in one persistent cooperative launch with a grid
+        barrier between steps (lbm_step_persistent); synchronises and returns
+        the number of workgroups."""
+        wg = C.c_int32(0)
+        self._check(self.L.lbm_step_persistent(self._h, int(n), C.byref(wg)), "lbm_step_persistent")
+        return int(wg.value)
 
     def sync(self):
         self._check(self.L.lbm_sync(self._h), "lbm_sync")

@@ -1,0 +1,111 @@
+"""One persistent launch over many steps (lbm_step_persistent) against one
+launch per step (lbm_step), through the C ABI.
+
+The persistent kernel runs the same per-node update of Sec. 3 on 64x8 tiles
+and orders the steps with a grid-wide barrier, so its states must be
+bitwise those of per-step launches: a difference would be a halo pulled
+before its neighbour's stores were visible (a barrier that does not order
+them across the XCDs' L2s), not rounding.  The grids are ragged in both
+directions, and one has more tiles than workgroups that can be resident at
+once, so that each workgroup steps several tiles between two barriers.
+"""
+import numpy as np
+import pytest
+
+from paper_2403_16122_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_16122_amd import lbm
+
+    return lbm
+
+
+def pair(lbm, p, phi0, T0, storage, xcd):
+    out = []
+    for _ in range(2):
+        s = lbm.Solver(dict(p, storage=lbm.STORAGE[storage]), phi0, T0)
+        s.set_launch("64x8", xcd)
+        out.append(s)
+    return out
+
+
+def droplet(nx, ny, seed=3):
+    p = W.default_params(nx, ny, rho_s=0.9, theta_bottom_deg=70.0)
+    phi0 = W.sessile_droplet(nx, ny, 0.14 * nx, 70.0, 4.0, x0=0.503 * nx)
+    T0 = W.temperature_noise(nx, ny, p["T_melt"], 1e-3, seed)
+    return p, phi0, T0
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("xcd", [0, 1, 2])
+def test_persistent_steps_bitwise_equal_per_step_launches(storage, xcd):
+    lbm = _lbm()
+    p, phi0, T0 = droplet(100, 37)
+    print(f"persistent storage={storage} xcd={xcd} grid=100x37", flush=True)
+    a, b = pair(lbm, p, phi0, T0, storage, xcd)
+    a.step(41)
+    wg = b.step_persistent(17)  # odd and even counts, and calls that continue a run
+    b.step_persistent(24)
+    assert b.step_count == a.step_count == 41
+    ntx, nty = 2, 5  # 64x8 tiles over 100x37, the last column and row ragged
+    order = {0: ntx * nty, 1: 8 * -(-(ntx * nty) // 8), 2: 8 * -(-ntx // 8) * nty}
+    assert wg == order[xcd]  # every workgroup of the tile order fits at once
+    assert b.save() == a.save()
+
+
+def test_persistent_grid_strides_over_more_tiles_than_resident_workgroups():
+    lbm = _lbm()
+    p, phi0, T0 = droplet(1100, 530)
+    ntiles = ((1100 + 63) // 64) * ((530 + 7) // 8)
+    print(f"persistent grid=1100x530 tiles={ntiles}", flush=True)
+    a, b = pair(lbm, p, phi0, T0, "fp32", 2)
+    a.step(12)
+    wg = b.step_persistent(12)
+    print(f"workgroups={wg}", flush=True)
+    assert wg % 8 == 0 and wg < ntiles
+    assert b.save() == a.save()
+
+
+def test_persistent_mixes_with_per_step_launches_and_counts_steps():
+    lbm = _lbm()
+    p, phi0, T0, _ = W.workload("sessile128", seed=1)
+    a, b = pair(lbm, p, phi0, T0, "fp16", 2)
+    a.step(30)
+    b.step_persistent(0)  # no-op
+    b.step_persistent(1)  # a single step: no barrier
+    b.step(10)
+    b.step_persistent(19)
+    assert b.step_count == 30
+    assert b.save() == a.save()
+    with pytest.raises(lbm.LbmError):
+        b.step_persistent(-1)
+    with pytest.raises(lbm.LbmError):
+        b.step_persistent(lbm.PERSIST_MAX_STEPS + 1)
+    assert b.step_count == 30
+
+
+def test_persistent_run_against_the_oracle(oracle_mod):
+    """The 128x64 sessile droplet after 1000 steps in one launch, held to the
+    FP32 bounds of the per-step path: max|d phi|, max|d T| <= 1e-5 and a
+    relative L2 of u <= 1e-4."""
+    lbm = _lbm()
+    p, phi0, T0, _ = W.workload("sessile128", seed=0)
+    g = lbm.Solver(p, phi0, T0)
+    g.set_launch("64x8", 2)
+    g.step_persistent(1000)
+    o = oracle_mod.OracleSolver(p, phi0, T0)
+    o.step(1000)
+    fg, fo = g.fields(("phi", "T", "ux", "uy")), o.fields(("phi", "T", "ux", "uy"))
+    dphi = float(np.abs(fg["phi"] - fo["phi"]).max())
+    dT = float(np.abs(fg["T"] - fo["T"]).max())
+    ug, uo = np.stack([fg["ux"], fg["uy"]]), np.stack([fo["ux"], fo["uy"]])
+    eu = float(np.linalg.norm(ug - uo) / np.linalg.norm(uo))
+    print(f"persistent 1000 steps: max|dphi|={dphi:.3e} max|dT|={dT:.3e} relL2(u)={eu:.3e}", flush=True)
+    assert dphi <= 1e-5 and dT <= 1e-5 and eu <= 1e-4
