@@ -408,21 +408,25 @@ def timed_run(lbm, W, name: str, storage: str, steps: int, warmup: int, args):
 
 
 def persistent_vs_per_step(lbm, W, name: str, steps: int, warmup: int):
-    """`steps` FP32 steps of a workload as one persistent cooperative launch
-    (a grid-wide barrier between steps, lbm_step_persistent) and as one
-    launch per step, both on 64x8 tiles in tile order 2 from the same state;
-    HIP events on the solver's stream bracket each.  The persistent call
-    also clears its barrier words and reads them back (a few microseconds
-    per call)."""
+    """`steps` FP32 steps of a workload as one launch per step and as one
+    persistent cooperative launch (lbm_step_persistent) with each of its two
+    grid barriers, all on 64x8 tiles in tile order 2 from the same state;
+    HIP events on the solver's stream bracket each.  A persistent call also
+    clears its barrier words and reads them back (a few microseconds per
+    call)."""
     import torch
 
     params, phi0, T0, _ = W.workload(name, seed=0)
     N = params["nx"] * params["ny"]
     rec = {"workload": name, "steps": steps, "tile": "64x8", "xcd_remap": 2}
-    for mode in ("per_step", "persistent"):
+    for mode in ("per_step", "persistent_flat", "persistent_per_xcd"):
         s = lbm.Solver(params, phi0, T0)
         s.set_launch("64x8", 2)
-        run = s.step if mode == "per_step" else s.step_persistent
+        if mode == "per_step":
+            run = s.step
+        else:
+            barrier = mode[len("persistent_"):]
+            run = lambda n, s=s, barrier=barrier: s.step_persistent(n, barrier)  # noqa: E731
         run(warmup)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -432,13 +436,14 @@ def persistent_vs_per_step(lbm, W, name: str, steps: int, warmup: int):
         torch.cuda.synchronize()
         secs = e0.elapsed_time(e1) / 1e3
         rec[mode] = {"us_per_step": round(secs / steps * 1e6, 3), "MLUPS": round(N * steps / secs / 1e6, 1)}
-        if mode == "persistent":
+        if mode != "per_step":
             rec[mode]["workgroups"] = wg
+            rec[mode]["over_per_step"] = round(rec[mode]["us_per_step"] / rec["per_step"]["us_per_step"], 3)
         del s
         torch.cuda.empty_cache()
-    rec["persistent_over_per_step"] = round(rec["persistent"]["us_per_step"] / rec["per_step"]["us_per_step"], 3)
-    note(f"{name}: per-step launches {rec['per_step']['us_per_step']} us/step, "
-         f"persistent {rec['persistent']['us_per_step']} us/step")
+    note(f"{name}: per-step launches {rec['per_step']['us_per_step']} us/step, persistent "
+         f"{rec['persistent_flat']['us_per_step']} (flat barrier) / "
+         f"{rec['persistent_per_xcd']['us_per_step']} (per-XCD barrier) us/step")
     return rec
 
 

@@ -117,16 +117,21 @@ int lbm_step(lbm_ctx* c, int32_t nsteps);
  * a cooperative grid of co-resident workgroups on 64x8 tiles (the context's
  * xcd_remap order; its tile variant is not used) loops over the steps with a
  * grid-wide barrier between them, since every step pulls the halo its
- * neighbours wrote in the step before.  Results are bitwise those of
- * lbm_step.  Kept to measure a persistent launch against one launch per
- * step; lbm_step is the faster path on MI355X.  nsteps in
- * 0..LBM_PERSIST_MAX_STEPS (else LBM_EINVAL).  *workgroups (optional)
- * receives the grid size.  Uses the context's reduction scratch for the
- * barrier.  Synchronises.  LBM_EDEVICE if the device has no cooperative
- * launch, no grid fits, or a barrier wait exceeded 2 s (then the state is
- * invalid: every wave still leaves the kernel). */
+ * neighbours wrote in the step before.  barrier LBM_BARRIER_FLAT: every
+ * workgroup writes its XCD's L2 back before it arrives (the agent-scope
+ * release of the HIP memory model); LBM_BARRIER_PER_XCD: the last workgroup
+ * to arrive on each XCD (read from the XCC_ID hardware register) writes that
+ * L2 back once for all of them.  Results are bitwise those of lbm_step in
+ * both.  Kept to measure a persistent launch against one launch per step;
+ * lbm_step is the faster path on MI355X.  nsteps in 0..LBM_PERSIST_MAX_STEPS
+ * and barrier 0 or 1, else LBM_EINVAL.  *workgroups (optional) receives the
+ * grid size.  Uses the context's reduction scratch for the barrier words.
+ * Synchronises.  LBM_EDEVICE if the device has no cooperative launch, no
+ * grid fits, or a barrier wait exceeded 2 s (then the state is invalid:
+ * every wave still leaves the kernel). */
 #define LBM_PERSIST_MAX_STEPS 1000000
-int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t* workgroups);
+enum { LBM_BARRIER_FLAT = 0, LBM_BARRIER_PER_XCD = 1 };
+int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t barrier, int32_t* workgroups);
 
 /* Macroscopic fields at the current time level as the next step would
  * compute them: phi (Eq. (26)), T and f_l (Eq. (9)), u (Eq. (34)-(35), with

@@ -358,8 +358,9 @@ int lbm_step(lbm_ctx* c, int32_t nsteps) {
   return LBM_OK;
 }
 
-int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t* workgroups) {
+int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t barrier, int32_t* workgroups) {
   if (!c || nsteps < 0 || nsteps > LBM_PERSIST_MAX_STEPS) return LBM_EINVAL;
+  if (barrier != LBM_BARRIER_FLAT && barrier != LBM_BARRIER_PER_XCD) return LBM_EINVAL;
   if (nsteps == 0) return LBM_OK;
   int rate_khz = 0;
   LBM_CK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
@@ -370,19 +371,29 @@ int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t* workgroups) {
   // a barrier wait of 2 s is a failure: a step of the largest grid takes ~1 ms
   const unsigned long long limit = 2000ull * (unsigned long long)rate_khz;
   // the barrier words sit in the reduction scratch, which no step reads
+  static_assert(lbmk::NPERSIST_WORDS <= (lbmk::RED_BLOCKS + 1) * lbmk::RED_NVAL, "barrier words");
   unsigned long long* bar = (unsigned long long*)c->S.part;
   c->K.seed = (unsigned)c->step;
   int grid = 0;
-  hipError_t e = lbmk::launch_persist(c->K, c->S, c->cur, nsteps, c->xcd, bar, limit, &grid, c->stream);
+  hipError_t e = lbmk::launch_persist(c->K, c->S, c->cur, nsteps, c->xcd, barrier, bar, limit, &grid, c->stream);
   if (e != hipSuccess) return dev_error(e, "persistent step launch");
-  unsigned long long flag[2] = {0, 0};
-  LBM_CK(hipMemcpyAsync(flag, bar, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+  unsigned long long w[lbmk::NPERSIST_WORDS];
+  LBM_CK(hipMemcpyAsync(w, bar, sizeof(w), hipMemcpyDeviceToHost, c->stream));
   LBM_CK(hipStreamSynchronize(c->stream));
-  if (flag[1]) {
+  if (w[1]) {
     g_last_error = "grid barrier of the persistent step timed out; the state is invalid";
     return LBM_EDEVICE;
   }
-  if (flag[0] != (unsigned long long)(nsteps - 1) * (unsigned long long)grid) {
+  // every workgroup arrives once per barrier: the counts must add up
+  const unsigned long long g = (unsigned long long)grid, nb = (unsigned long long)(nsteps - 1);
+  unsigned long long arrivals = 0, placed = 0;
+  for (int x = 0; x < 8; ++x) {
+    arrivals += w[3 + x];
+    placed += w[11 + x];
+  }
+  const bool census = barrier == LBM_BARRIER_PER_XCD && nsteps > 1;
+  const bool ok = census ? (w[0] == g && arrivals == nb * g && placed == g) : (w[0] == nb * g && arrivals == 0);
+  if (!ok) {
     g_last_error = "grid barrier arrivals of the persistent step do not add up; the state is invalid";
     return LBM_EDEVICE;
   }

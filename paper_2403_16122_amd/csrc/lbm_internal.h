@@ -116,13 +116,17 @@ int launch_step(const KParams& P, const State& S, int cur, bool fields_only, int
 // buffer cur^1, like one step.
 int launch_step2(const KParams& P, const State& S, int cur, int tile_variant, int xcd_remap, hipStream_t st);
 // nsteps single steps n -> n + nsteps (steps P.seed, P.seed + 1, ...) in one
-// cooperative launch on 64x8 tiles, with a grid-wide barrier between steps.
-// bar: two 64-bit words of device memory (zeroed here on the stream); bar[1]
-// is nonzero afterwards if a barrier wait exceeded limit_ticks of the
-// device's wall clock.  *grid_out receives the number of workgroups.
-// Returns the runtime's error, hipErrorNotSupported without cooperative
-// launches, or hipErrorCooperativeLaunchTooLarge if no grid fits.
-hipError_t launch_persist(const KParams& P, const State& S, int cur, int nsteps, int xcd_remap,
+// cooperative launch on 64x8 tiles, with a grid-wide barrier between steps:
+// every workgroup writes its XCD's L2 back (per_xcd 0), or the last
+// workgroup to arrive on each XCD does it for all (per_xcd 1).  bar:
+// NPERSIST_WORDS 64-bit words of device memory (zeroed here on the stream):
+// [0] flat-barrier arrivals, [1] nonzero if a wait exceeded limit_ticks of
+// the device's wall clock, [2] XCD arrivals, [3..10] workgroup arrivals per
+// XCD, [11..18] workgroups per XCD.  *grid_out receives the number of
+// workgroups.  Returns the runtime's error, hipErrorNotSupported without
+// cooperative launches, or hipErrorCooperativeLaunchTooLarge if no grid fits.
+enum { NPERSIST_WORDS = 19 };
+hipError_t launch_persist(const KParams& P, const State& S, int cur, int nsteps, int xcd_remap, int per_xcd,
                           unsigned long long* bar, unsigned long long limit_ticks, int* grid_out, hipStream_t st);
 // The 9 populations of `lattice` as FP32 (shifted variables) into the first
 // nine field planes.

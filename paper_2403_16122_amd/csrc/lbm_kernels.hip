@@ -1017,37 +1017,103 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(6))) voi
 // only safe when every workgroup is resident at once, which a cooperative
 // launch guarantees (the runtime refuses a grid that does not fit).
 //
-// bar[0] counts arrivals over the whole launch: barrier k (from 1) is
-// complete once it reaches k * gridDim.x.  A wait longer than `limit`
-// wall-clock ticks sets bar[1]; no workgroup waits once it is set, and the
-// kernel stops stepping, so every wave reaches the end whatever happens and
-// the host reports the flag.  Each wave first waits for its own stores;
-// thread 0 then publishes the workgroup's stores at agent scope (the 8
-// XCDs' L2s are not coherent: release writes dirty L2 lines back) with its
-// arrival, and after the wait acquires the others' (L2 invalidate).
+// Barrier words (64-bit, zeroed before the launch): bar[0] arrivals at the
+// flat barrier, bar[1] the time-out flag, bar[2] XCD arrivals of the per-XCD
+// barrier, bar[3 + x] arrivals of workgroups on XCD x, bar[11 + x] the
+// number of workgroups on XCD x.  Every wait polls with a bound of `limit`
+// wall-clock ticks; a wait that exceeds it sets bar[1], no workgroup waits
+// once it is set, and the kernel stops stepping, so every wave reaches the
+// end whatever happens and the host reports the flag.
+enum { BAR_FLAT = 0, BAR_FLAG = 1, BAR_XCD = 2, BAR_ARRIVE = 3, BAR_COUNT = 11 };
+static_assert(BAR_COUNT + 8 == NPERSIST_WORDS, "barrier words");
+
+__device__ __forceinline__ bool spin_until(unsigned long long* ctr, unsigned long long target,
+                                           unsigned long long* flag, unsigned long long limit) {
+  const unsigned long long t0 = wall_clock64();
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull) return false;
+    if (wall_clock64() - t0 > limit) {
+      __hip_atomic_store(flag, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+// Flat barrier: barrier k (from 1) is complete once bar[0] reaches
+// k * gridDim.x.  Each wave first waits for its own stores; thread 0 then
+// publishes the workgroup's stores at agent scope (the 8 XCDs' L2s are not
+// coherent: release writes the dirty lines of its XCD's L2 back) before it
+// arrives, and after the wait acquires the others' (L2 invalidate).
 __device__ __forceinline__ bool grid_barrier(unsigned long long* bar, unsigned long long target,
                                              unsigned long long limit) {
   __shared__ unsigned s_go;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned go = 1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __builtin_amdgcn_s_waitcnt(0);  // the write-back has completed before the arrival counts
-    __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long t0 = wall_clock64();
-    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull) {
-        go = 0;
-        break;
-      }
-      if (wall_clock64() - t0 > limit) {
-        __hip_atomic_store(bar + 1, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        go = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
+    __hip_atomic_fetch_add(bar + BAR_FLAT, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool go = spin_until(bar + BAR_FLAT, target, bar + BAR_FLAG, limit);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
+    s_go = go;
+  }
+  __syncthreads();
+  return s_go != 0;
+}
+
+// Per-XCD barrier.  An XCD's L2 is shared by all of its CUs, so one
+// write-back publishes the stores of every workgroup on it once they have
+// reached it: each wave waits for its stores (they are then in its XCD's
+// L2), thread 0 counts the workgroup's arrival on its XCD, and the
+// workgroup that completes that count writes the L2 back and arrives for
+// the whole XCD at bar[2].  Barrier k is complete once bar[2] reaches
+// k * (XCDs with workgroups); every workgroup then invalidates as above.
+// One write-back per XCD and step instead of one per workgroup.
+struct XcdPlace {
+  unsigned xcd;              // XCC_ID of the workgroup's XCD
+  unsigned long long nwg;    // workgroups on that XCD
+  unsigned long long nxcd;   // XCDs with workgroups
+};
+
+// Where each workgroup runs, counted once per launch behind a flat barrier.
+__device__ __forceinline__ bool xcd_census(unsigned long long* bar, unsigned long long limit, XcdPlace& pl) {
+  __shared__ unsigned s_xcd;
+  __shared__ unsigned long long s_nwg, s_nxcd;
+  if (threadIdx.x == 0) {
+    // hardware register XCC_ID (hwreg 20), bits 3:0
+    s_xcd = (unsigned)__builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u;
+    __hip_atomic_fetch_add(bar + BAR_COUNT + s_xcd, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (!grid_barrier(bar, gridDim.x, limit)) return false;
+  if (threadIdx.x == 0) {
+    unsigned long long n = 0;
+    for (int x = 0; x < 8; ++x)
+      n += __hip_atomic_load(bar + BAR_COUNT + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1ull : 0ull;
+    s_nxcd = n;
+    s_nwg = __hip_atomic_load(bar + BAR_COUNT + s_xcd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  pl = XcdPlace{s_xcd, s_nwg, s_nxcd};
+  return true;
+}
+
+__device__ __forceinline__ bool xcd_barrier(unsigned long long* bar, unsigned k, const XcdPlace& pl,
+                                            unsigned long long limit) {
+  __shared__ unsigned s_go;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long before =
+        __hip_atomic_fetch_add(bar + BAR_ARRIVE + pl.xcd, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (before + 1 == (unsigned long long)k * pl.nwg) {  // the XCD's last arrival of barrier k
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __builtin_amdgcn_s_waitcnt(0);
+      __hip_atomic_fetch_add(bar + BAR_XCD, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    const bool go = spin_until(bar + BAR_XCD, (unsigned long long)k * pl.nxcd, bar + BAR_FLAG, limit);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __builtin_amdgcn_s_waitcnt(0);
     s_go = go;
@@ -1068,12 +1134,14 @@ __device__ __forceinline__ StepIO next_io(const StepIO& io) {
 // exactly as nsteps k_step launches would.  Workgroup b takes the tiles
 // k_step's workgroups b, b + gridDim.x, ... would take; gridDim.x is a
 // multiple of 8 (or the whole launch), so each tile stays on the XCD the
-// tile order gives it.
+// tile order gives it.  per_xcd selects the barrier between steps.
 template <int TX, int TY, class PT, bool STREAM>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(4))) void k_persist(
-    KParams P, StepIO io, int nsteps, int ntx, int ntiles, int band, int mode, int vgrid,
+    KParams P, StepIO io, int nsteps, int ntx, int ntiles, int band, int mode, int vgrid, int per_xcd,
     unsigned long long* bar, unsigned long long limit) {
   const unsigned seed0 = P.seed;
+  XcdPlace pl{0u, 0ull, 0ull};
+  if (per_xcd && nsteps > 1 && !xcd_census(bar, limit, pl)) return;
   for (int s = 0; s < nsteps; ++s, io = next_io(io)) {
     P.seed = seed0 + (unsigned)s;
     for (int v = blockIdx.x; v < vgrid; v += gridDim.x) {
@@ -1081,7 +1149,11 @@ __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(4))) voi
       if (tile < ntiles) step_tile<TX, TY, false, PT, false, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
       __syncthreads();  // the next tile refills the LDS
     }
-    if (s + 1 < nsteps && !grid_barrier(bar, (unsigned long long)(s + 1) * gridDim.x, limit)) return;
+    if (s + 1 < nsteps) {
+      const bool go = per_xcd ? xcd_barrier(bar, (unsigned)(s + 1), pl, limit)
+                              : grid_barrier(bar, (unsigned long long)(s + 1) * gridDim.x, limit);
+      if (!go) return;
+    }
   }
 }
 
@@ -1989,7 +2061,7 @@ int launch_step2(const KParams& P, const State& S, int cur, int tile_variant, in
 namespace {
 
 template <int TX, int TY, class PT>
-hipError_t launch_persist_t(const KParams& P, const State& S, int cur, int nsteps, int xcd,
+hipError_t launch_persist_t(const KParams& P, const State& S, int cur, int nsteps, int xcd, int per_xcd,
                             unsigned long long* bar, unsigned long long limit, int* grid_out, hipStream_t st) {
   const int ntx = (P.nx + TX - 1) / TX, nty = (P.ny + TY - 1) / TY;
   int ntiles = ntx * nty, band = 0, vgrid = ntiles;
@@ -2014,23 +2086,23 @@ hipError_t launch_persist_t(const KParams& P, const State& S, int cur, int nstep
   if (cap < 8) return hipErrorCooperativeLaunchTooLarge;
   int grid = vgrid < cap ? vgrid : cap;
   *grid_out = grid;
-  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, bar, 2);
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, bar, (int)NPERSIST_WORDS);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   KParams Pa = P;
   StepIO io = make_io(S, cur);
-  void* args[] = {&Pa, &io, &nsteps, (void*)&ntx, &ntiles, &band, &xcd, &vgrid, &bar, &limit};
+  void* args[] = {&Pa, &io, &nsteps, (void*)&ntx, &ntiles, &band, &xcd, &vgrid, &per_xcd, &bar, &limit};
   return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(TX * TY), args, 0, st);
 }
 
 }  // namespace
 
-hipError_t launch_persist(const KParams& P, const State& S, int cur, int nsteps, int xcd_remap,
+hipError_t launch_persist(const KParams& P, const State& S, int cur, int nsteps, int xcd_remap, int per_xcd,
                           unsigned long long* bar, unsigned long long limit_ticks, int* grid_out, hipStream_t st) {
   if (P.storage == STORE_FP16)
-    return launch_persist_t<64, 8, _Float16>(P, S, cur, nsteps, xcd_remap, bar, limit_ticks, grid_out, st);
+    return launch_persist_t<64, 8, _Float16>(P, S, cur, nsteps, xcd_remap, per_xcd, bar, limit_ticks, grid_out, st);
   if (P.storage == STORE_BF16)
-    return launch_persist_t<64, 8, __bf16>(P, S, cur, nsteps, xcd_remap, bar, limit_ticks, grid_out, st);
-  return launch_persist_t<64, 8, float>(P, S, cur, nsteps, xcd_remap, bar, limit_ticks, grid_out, st);
+    return launch_persist_t<64, 8, __bf16>(P, S, cur, nsteps, xcd_remap, per_xcd, bar, limit_ticks, grid_out, st);
+  return launch_persist_t<64, 8, float>(P, S, cur, nsteps, xcd_remap, per_xcd, bar, limit_ticks, grid_out, st);
 }
 
 int launch_expand(const KParams& P, const State& S, int cur, int lattice, hipStream_t st) {

@@ -41,6 +41,7 @@ EXPORTED = [
     "lbm_mlp_gradient", "lbm_mlp_train", "lbm_mlp_last_error", "lbm_mlp_destroy", "lbm_mlp_forward_noalloc",
 ]
 PERSIST_MAX_STEPS = 1000000  # LBM_PERSIST_MAX_STEPS
+PERSIST_BARRIERS = {"flat": 0, "per_xcd": 1}  # LBM_BARRIER_FLAT / LBM_BARRIER_PER_XCD
 DROP_STATUS = {0: "queued", 1: "running", 2: "frozen", 3: "limit", 4: "nonfinite"}
 
 
@@ -97,7 +98,7 @@ def load_library():
     L.lbm_workspace_bytes.argtypes = [C.POINTER(Params), C.POINTER(C.c_size_t)]
     L.lbm_init.argtypes = [C.POINTER(Params), dp, dp, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.lbm_step.argtypes = [vp, C.c_int32]
-    L.lbm_step_persistent.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
+    L.lbm_step_persistent.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     L.lbm_fields.argtypes = [vp, C.c_uint32, C.POINTER(dp)]
     L.lbm_fields_device.argtypes = [vp, C.c_uint32, C.POINTER(vp)]
     L.lbm_diag.argtypes = [vp, C.POINTER(Diag)]
@@ -230,12 +231,13 @@ class Solver:
     def step(self, n: int = 1):
         self._check(self.L.lbm_step(self._h, int(n)), "lbm_step")
 
-    def step_persistent(self, n: int = 1) -> int:
+    def step_persistent(self, n: int = 1, barrier: str = "flat") -> int:
         """The same n steps in one persistent cooperative launch with a grid
-        barrier between steps (lbm_step_persistent); synchronises and returns
-        the number of workgroups."""
+        barrier between steps (lbm_step_persistent), barrier "flat" or
+        "per_xcd"; synchronises and returns the number of workgroups."""
         wg = C.c_int32(0)
-        self._check(self.L.lbm_step_persistent(self._h, int(n), C.byref(wg)), "lbm_step_persistent")
+        self._check(self.L.lbm_step_persistent(self._h, int(n), PERSIST_BARRIERS[barrier], C.byref(wg)),
+                    "lbm_step_persistent")
         return int(wg.value)
 
     def sync(self):

@@ -5,9 +5,12 @@ The persistent kernel runs the same per-node update of Sec. 3 on 64x8 tiles
 and orders the steps with a grid-wide barrier, so its states must be
 bitwise those of per-step launches: a difference would be a halo pulled
 before its neighbour's stores were visible (a barrier that does not order
-them across the XCDs' L2s), not rounding.  The grids are ragged in both
-directions, and one has more tiles than workgroups that can be resident at
-once, so that each workgroup steps several tiles between two barriers.
+them across the XCDs' L2s), not rounding.  Both barriers are checked: the
+flat one (every workgroup writes its XCD's L2 back) and the per-XCD one
+(the last workgroup to arrive on an XCD writes it back for all).  The grids
+are ragged in both directions, and one has more tiles than workgroups that
+can be resident at once, so that each workgroup steps several tiles between
+two barriers.
 """
 import numpy as np
 import pytest
@@ -43,16 +46,20 @@ def droplet(nx, ny, seed=3):
     return p, phi0, T0
 
 
+BARRIERS = ["flat", "per_xcd"]
+
+
+@pytest.mark.parametrize("barrier", BARRIERS)
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("xcd", [0, 1, 2])
-def test_persistent_steps_bitwise_equal_per_step_launches(storage, xcd):
+def test_persistent_steps_bitwise_equal_per_step_launches(storage, xcd, barrier):
     lbm = _lbm()
     p, phi0, T0 = droplet(100, 37)
-    print(f"persistent storage={storage} xcd={xcd} grid=100x37", flush=True)
+    print(f"persistent storage={storage} xcd={xcd} barrier={barrier} grid=100x37", flush=True)
     a, b = pair(lbm, p, phi0, T0, storage, xcd)
     a.step(41)
-    wg = b.step_persistent(17)  # odd and even counts, and calls that continue a run
-    b.step_persistent(24)
+    wg = b.step_persistent(17, barrier)  # odd and even counts, and calls that continue a run
+    b.step_persistent(24, barrier)
     assert b.step_count == a.step_count == 41
     ntx, nty = 2, 5  # 64x8 tiles over 100x37, the last column and row ragged
     order = {0: ntx * nty, 1: 8 * -(-(ntx * nty) // 8), 2: 8 * -(-ntx // 8) * nty}
@@ -60,14 +67,15 @@ def test_persistent_steps_bitwise_equal_per_step_launches(storage, xcd):
     assert b.save() == a.save()
 
 
-def test_persistent_grid_strides_over_more_tiles_than_resident_workgroups():
+@pytest.mark.parametrize("barrier", BARRIERS)
+def test_persistent_grid_strides_over_more_tiles_than_resident_workgroups(barrier):
     lbm = _lbm()
     p, phi0, T0 = droplet(1100, 530)
     ntiles = ((1100 + 63) // 64) * ((530 + 7) // 8)
-    print(f"persistent grid=1100x530 tiles={ntiles}", flush=True)
+    print(f"persistent grid=1100x530 tiles={ntiles} barrier={barrier}", flush=True)
     a, b = pair(lbm, p, phi0, T0, "fp32", 2)
     a.step(12)
-    wg = b.step_persistent(12)
+    wg = b.step_persistent(12, barrier)
     print(f"workgroups={wg}", flush=True)
     assert wg % 8 == 0 and wg < ntiles
     assert b.save() == a.save()
@@ -79,19 +87,20 @@ def test_persistent_mixes_with_per_step_launches_and_counts_steps():
     a, b = pair(lbm, p, phi0, T0, "fp16", 2)
     a.step(30)
     b.step_persistent(0)  # no-op
-    b.step_persistent(1)  # a single step: no barrier
+    b.step_persistent(1, "per_xcd")  # a single step: no barrier
     b.step(10)
-    b.step_persistent(19)
+    b.step_persistent(7, "per_xcd")
+    b.step_persistent(12)
     assert b.step_count == 30
     assert b.save() == a.save()
-    with pytest.raises(lbm.LbmError):
-        b.step_persistent(-1)
-    with pytest.raises(lbm.LbmError):
-        b.step_persistent(lbm.PERSIST_MAX_STEPS + 1)
+    for bad in ((-1, 0), (lbm.PERSIST_MAX_STEPS + 1, 0), (5, 2), (5, -1)):
+        with pytest.raises(lbm.LbmError):
+            b._check(b.L.lbm_step_persistent(b._h, bad[0], bad[1], None), "lbm_step_persistent")
     assert b.step_count == 30
 
 
-def test_persistent_run_against_the_oracle(oracle_mod):
+@pytest.mark.parametrize("barrier", BARRIERS)
+def test_persistent_run_against_the_oracle(oracle_mod, barrier):
     """The 128x64 sessile droplet after 1000 steps in one launch, held to the
     FP32 bounds of the per-step path: max|d phi|, max|d T| <= 1e-5 and a
     relative L2 of u <= 1e-4."""
@@ -99,7 +108,7 @@ def test_persistent_run_against_the_oracle(oracle_mod):
     p, phi0, T0, _ = W.workload("sessile128", seed=0)
     g = lbm.Solver(p, phi0, T0)
     g.set_launch("64x8", 2)
-    g.step_persistent(1000)
+    g.step_persistent(1000, barrier)
     o = oracle_mod.OracleSolver(p, phi0, T0)
     o.step(1000)
     fg, fo = g.fields(("phi", "T", "ux", "uy")), o.fields(("phi", "T", "ux", "uy"))
