@@ -115,16 +115,18 @@ def plain_until_frozen(lbm, d, every: int, max_steps: int):
     return tf, steps[-1], secs
 
 
-def run_sweep(lbm, W, n: int, storage: str, time_limit: float, chunk: int = 50000):
+def run_sweep(lbm, W, n: int, storage: str, time_limit: float, chunk: int = 50000, persistent=None):
     """The batched sweep in one storage format: every droplet run until 1 %
-    of its liquid is left; returns (results, seconds, node_steps, launch)."""
+    of its liquid is left; returns (results, seconds, node_steps, launch).
+    persistent: None (each interval a replayed graph of per-step launches)
+    or the grid barrier of one persistent launch per interval."""
     import torch
 
     every, max_steps = 200, 2_000_000
     drops = W.sweep_droplets(n, seed=0, storage=lbm.STORAGE[storage])
     b = lbm.Batch([d["params"] for d in drops], [d["phi0"] for d in drops], [d["T0"] for d in drops],
                   radii=[d["R"] for d in drops], slots=n)
-    b.configure(sample_every=every, max_steps=max_steps)
+    b.configure(sample_every=every, max_steps=max_steps, persistent=persistent)
     tile, grp = b.autotune(reps=5)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -132,8 +134,8 @@ def run_sweep(lbm, W, n: int, storage: str, time_limit: float, chunk: int = 5000
         b.step(chunk, until_frozen=True)
         res = b.results()
         done = sum(r["status"] != "running" and r["status"] != "queued" for r in res)
-        print(f"sweep {storage}: {done}/{n} droplets finished after {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-              flush=True)
+        print(f"sweep {storage}{' persistent ' + persistent if persistent else ''}: {done}/{n} droplets finished "
+              f"after {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         if done == n or time.perf_counter() - t0 > time_limit:
             break
     secs = time.perf_counter() - t0
@@ -162,6 +164,20 @@ def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float, reference: bool
         "node_steps": int(node_steps), "MLUPS": round(node_steps / secs / 1e6, 1), "tile": tile, "xcd_group": grp,
         "t_freeze_steps": [round(float(q), 1) for q in np.nanpercentile([r["t_freeze"] for r in res], [0, 50, 100])],
     }
+    # the same queue with every 200-step interval in one persistent launch
+    try:
+        _, resp, secsp, nsp, (tilep, grpp) = run_sweep(lbm, W, n, "fp16", time_limit, chunk, persistent="per_xcd")
+        same = all(a["steps"] == c["steps"] and (a["t_freeze"] == c["t_freeze"] or
+                                                 (np.isnan(a["t_freeze"]) and np.isnan(c["t_freeze"])))
+                   for a, c in zip(res, resp))
+        out["persistent_intervals"] = {
+            "barrier": "per_xcd", "seconds": round(secsp, 2),
+            "droplets_per_s": round(sum(r["status"] == "frozen" for r in resp) / secsp, 3),
+            "MLUPS": round(nsp / secsp / 1e6, 1), "tile": tilep, "xcd_group": grpp, "same_results": same,
+            "note": "each 200-step interval as one cooperative launch with a grid barrier between steps, "
+                    "against the replayed graph of per-step launches above"}
+    except lbm.LbmError as e:
+        out["persistent_intervals"] = {"error": str(e)}
     if not reference:
         return out
     _, res32, secs32, ns32, (tile32, grp32) = run_sweep(lbm, W, n, "fp32", time_limit)

@@ -263,10 +263,24 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
                    lbm_batch** out);
 
 /* Sampling interval (even, >= 2; default 100), per-droplet step limit
- * (0 = none), freezing threshold (default 0.01), and whether each interval
- * runs as a replayed hipGraph (default 1) or as individual launches. */
+ * (0 = none), freezing threshold (default 0.01), and how the steps of an
+ * interval are launched: LBM_INTERVAL_LAUNCHES one launch per step (or per
+ * two), LBM_INTERVAL_GRAPH the same launches captured once as a hipGraph
+ * and replayed (default), or LBM_INTERVAL_PERSIST_FLAT / _PER_XCD all steps
+ * of the interval in ONE persistent cooperative launch over the resident
+ * droplets' tiles, with the flat or per-XCD grid barrier of
+ * lbm_step_persistent between steps (64x8 tiles only: the tile variant is
+ * set to 2, and lbm_batch_set_launch and lbm_batch_autotune keep it there;
+ * LBM_EDEVICE from lbm_batch_step if a barrier wait exceeds 2 s).  Results
+ * are bitwise the same in every mode; anything else is LBM_EINVAL. */
+enum {
+  LBM_INTERVAL_LAUNCHES = 0,
+  LBM_INTERVAL_GRAPH = 1,
+  LBM_INTERVAL_PERSIST_FLAT = 2,
+  LBM_INTERVAL_PERSIST_PER_XCD = 3
+};
 int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, double freeze_frac,
-                        int32_t use_graph);
+                        int32_t interval_launch);
 
 /* Tile shape (tile_variant 0..4 of lbm_set_launch, or the two-step variants
  * 9 and 10 when the sampling interval is a multiple of 4; LBM_EINVAL

@@ -39,13 +39,14 @@ int bdev_error(hipError_t e, const char* what) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int kPersistVariant = 2;  // 64x8: the tiles of the persistent interval launch
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   long long plane;     // floats per plane in every slot
   size_t slot_bytes;   // one slot's state
   size_t tmap_cap;     // tile-map entries
-  size_t off_ptab, off_otab, off_tmap, off_slots, off_steps, off_liq, off_shape, off_slots_ws, total;
+  size_t off_ptab, off_otab, off_tmap, off_slots, off_steps, off_liq, off_shape, off_bar, off_slots_ws, total;
 };
 
 int max_tiles(int nx, int ny) {
@@ -85,6 +86,8 @@ Layout layout(const lbm_params* p, int n, int slots) {
   o = align_up(o + sizeof(double) * 2 * slots);
   L.off_shape = o;
   o = align_up(o + sizeof(double) * 4 * slots);
+  L.off_bar = o;  // grid-barrier words of the persistent interval launch
+  o = align_up(o + sizeof(unsigned long long) * lbmk::NPERSIST_WORDS);
   L.off_slots_ws = o;
   L.total = o + L.slot_bytes * slots;
   return L;
@@ -126,10 +129,15 @@ struct lbm_batch {
   int store_mode;  // 0 and 1 cached, 2 streaming stores
   bool nt;         // the step kernels stream their stores
   bool use_graph;
+  int persist;                   // -1: launches per step; 0 / 1: one persistent launch per interval
+                                 // with the flat / per-XCD grid barrier
+  unsigned long long bar_limit;  // wall-clock ticks a barrier wait may take (2 s)
+  int persist_grid;              // workgroups of the last persistent launch
   hipGraphExec_t exec;
   bool graph_valid;
   double* h_liq;      // pinned: 2 doubles per slot
   unsigned* h_steps;  // pinned: step count of each slot's droplet at the start of an interval
+  unsigned long long* h_bar;  // pinned: the barrier words after the last persistent launch
   std::vector<double> shape;
   char* d(size_t off) const { return ws + off; }
   lbmk::KParams* d_ptab() const { return (lbmk::KParams*)d(L.off_ptab); }
@@ -139,6 +147,7 @@ struct lbm_batch {
   unsigned* d_steps() const { return (unsigned*)d(L.off_steps); }
   double* d_liq() const { return (double*)d(L.off_liq); }
   double* d_shape() const { return (double*)d(L.off_shape); }
+  unsigned long long* d_bar() const { return (unsigned long long*)d(L.off_bar); }
   char* slot_base(int s) const { return d(L.off_slots_ws) + (size_t)s * L.slot_bytes; }
 };
 
@@ -224,11 +233,22 @@ int upload_map(lbm_batch* b) {
 int enqueue_chunk(lbm_batch* b, hipStream_t st) {
   // step numbers at the start of the interval (read from pinned memory when the copy runs)
   LBMB_CK(hipMemcpyAsync(b->d_steps(), b->h_steps, sizeof(unsigned) * b->slots, hipMemcpyHostToDevice, st));
-  const int per = lbmk::is_two_step_any_storage(b->tile_variant) ? 2 : 1;  // steps per launch
-  for (int s = 0; s < b->sample_every; s += per)
-    if (lbmk::launch_batch(b->storage, b->tile_variant, false, b->nt, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(),
-                           b->d_steps(), b->nblocks, s, st))
-      return bdev_error(hipGetLastError(), "batch step launch");
+  if (b->persist >= 0) {
+    // the whole interval in one cooperative launch; its barrier words are
+    // read back with the liquid volumes and checked after the interval
+    hipError_t e = lbmk::launch_batch_persist(b->storage, b->nt, b->persist, b->ws, b->d_ptab(), b->d_otab(),
+                                              b->d_tmap(), b->d_steps(), b->nblocks, b->sample_every, b->d_bar(),
+                                              b->bar_limit, &b->persist_grid, st);
+    if (e != hipSuccess) return bdev_error(e, "persistent batch launch");
+    LBMB_CK(hipMemcpyAsync(b->h_bar, b->d_bar(), sizeof(unsigned long long) * lbmk::NPERSIST_WORDS,
+                           hipMemcpyDeviceToHost, st));
+  } else {
+    const int per = lbmk::is_two_step_any_storage(b->tile_variant) ? 2 : 1;  // steps per launch
+    for (int s = 0; s < b->sample_every; s += per)
+      if (lbmk::launch_batch(b->storage, b->tile_variant, false, b->nt, b->ws, b->d_ptab(), b->d_otab(),
+                             b->d_tmap(), b->d_steps(), b->nblocks, s, st))
+        return bdev_error(hipGetLastError(), "batch step launch");
+  }
   if (lbmk::launch_batch(b->storage, b->tile_variant, true, false, b->ws, b->d_ptab(), b->d_otab(), b->d_tmap(),
                          b->d_steps(), b->nblocks, 0, st))
     return bdev_error(hipGetLastError(), "batch fields launch");
@@ -239,9 +259,31 @@ int enqueue_chunk(lbm_batch* b, hipStream_t st) {
   return LBM_OK;
 }
 
+// After a persistent interval: no barrier wait timed out, and every
+// workgroup arrived once per barrier.
+int check_barrier(lbm_batch* b) {
+  const unsigned long long* w = b->h_bar;
+  if (w[1]) {
+    g_batch_error = "grid barrier of the persistent interval timed out; the states are invalid";
+    return LBM_EDEVICE;
+  }
+  const unsigned long long g = (unsigned long long)b->persist_grid, nb = (unsigned long long)(b->sample_every - 1);
+  unsigned long long arrivals = 0, placed = 0;
+  for (int x = 0; x < 8; ++x) {
+    arrivals += w[3 + x];
+    placed += w[11 + x];
+  }
+  const bool ok = b->persist ? (w[0] == g && arrivals == nb * g && placed == g) : (w[0] == nb * g && arrivals == 0);
+  if (!ok) {
+    g_batch_error = "grid barrier arrivals of the persistent interval do not add up; the states are invalid";
+    return LBM_EDEVICE;
+  }
+  return LBM_OK;
+}
+
 int run_chunk(lbm_batch* b) {
   for (int s : b->active) b->h_steps[s] = (unsigned)b->drops[b->slot_drop[s]].r.steps;
-  if (!b->use_graph) return enqueue_chunk(b, b->stream);
+  if (!b->use_graph || b->persist >= 0) return enqueue_chunk(b, b->stream);
   if (!b->graph_valid) {
     hipGraph_t g;
     LBMB_CK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -474,6 +516,10 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
   b->store_mode = 0;
   b->nt = false;
   b->use_graph = true;
+  b->persist = -1;
+  b->bar_limit = 0;
+  b->persist_grid = 0;
+  b->h_bar = nullptr;
   b->drops.resize(n);
   for (int i = 0; i < n; ++i) {
     Drop& D = b->drops[i];
@@ -498,6 +544,11 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_liq, sizeof(double) * 2 * b->slots, hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_steps, sizeof(unsigned) * b->slots, hipHostMallocDefault);
   if (e == hipSuccess) std::memset(b->h_steps, 0, sizeof(unsigned) * b->slots);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&b->h_bar, sizeof(unsigned long long) * lbmk::NPERSIST_WORDS, hipHostMallocDefault);
+  int rate_khz = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, b->device);
+  b->bar_limit = 2000ull * (unsigned long long)(rate_khz > 0 ? rate_khz : 100000);
   if (e != hipSuccess) {
     rc = bdev_error(e, "lbm_batch_init");
     lbm_batch_destroy(b);
@@ -527,24 +578,33 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
 }
 
 int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, double freeze_frac,
-                        int32_t use_graph) {
+                        int32_t interval_launch) {
   if (!b || sample_every < 2 || (sample_every & 1) || max_steps < 0 || !(freeze_frac > 0.0 && freeze_frac < 1.0))
     return LBM_EINVAL;
-  if (lbmk::is_two_step_any_storage(b->tile_variant) && sample_every % 4) {
+  if (interval_launch < LBM_INTERVAL_LAUNCHES || interval_launch > LBM_INTERVAL_PERSIST_PER_XCD) return LBM_EINVAL;
+  const bool persist = interval_launch >= LBM_INTERVAL_PERSIST_FLAT;
+  if (!persist && lbmk::is_two_step_any_storage(b->tile_variant) && sample_every % 4) {
     g_batch_error = "two steps per launch need a sampling interval that is a multiple of 4";
     return LBM_EINVAL;
   }
   b->sample_every = sample_every;
   b->max_steps = max_steps;
   b->freeze_frac = freeze_frac;
-  b->use_graph = use_graph != 0;
+  b->use_graph = interval_launch == LBM_INTERVAL_GRAPH;
+  b->persist = persist ? interval_launch - LBM_INTERVAL_PERSIST_FLAT : -1;
   drop_graph(b);
+  if (persist && b->tile_variant != kPersistVariant) {  // the persistent kernel runs 64x8 tiles
+    b->tile_variant = kPersistVariant;
+    return upload_map(b);
+  }
   return LBM_OK;
 }
 
 // Batch launch shapes: the single-step tiles 0-4 and, with a sampling
-// interval that is a multiple of 4, the two-step variants 9 and 10.
+// interval that is a multiple of 4, the two-step variants 9 and 10; with
+// persistent intervals, 64x8 only.
 static bool batch_variant_ok(const lbm_batch* b, int v) {
+  if (b->persist >= 0) return v == kPersistVariant;
   if (v >= 0 && v < lbmk::NBATCH_VARIANTS) return true;
   return lbmk::is_two_step_any_storage(v) && b->sample_every % 4 == 0;
 }
@@ -633,6 +693,7 @@ int lbm_batch_step(lbm_batch* b, int64_t nsteps, int32_t until_frozen) {
     int rc = run_chunk(b);
     if (rc) return rc;
     LBMB_CK(hipStreamSynchronize(b->stream));
+    if (b->persist >= 0 && (rc = check_barrier(b))) return rc;
     done_steps += b->sample_every;
     std::vector<int> fin = after_chunk(b, until_frozen != 0, status);
     if (fin.empty()) continue;
@@ -734,6 +795,7 @@ void lbm_batch_destroy(lbm_batch* b) {
   if (b->own_ws && b->ws) (void)hipFree(b->ws);
   if (b->h_liq) (void)hipHostFree(b->h_liq);
   if (b->h_steps) (void)hipHostFree(b->h_steps);
+  if (b->h_bar) (void)hipHostFree(b->h_bar);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   delete b;
 }

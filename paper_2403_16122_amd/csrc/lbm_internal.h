@@ -164,6 +164,14 @@ int launch_batch(int storage, int tile_variant, bool fields_only, bool stream_st
                  const KParams* d_ptab,
                  const StepOff* d_otab, const unsigned* d_tmap, const unsigned* d_steps, int nblocks, int s,
                  hipStream_t st);
+// Steps 0 .. nsteps-1 of a sampling interval (as nsteps launch_batch calls
+// of tile variant 2, 64x8) in one cooperative launch, with the grid barrier
+// of launch_persist between steps (per_xcd 0 flat, 1 per XCD) and the same
+// barrier words; d_tmap must be the map of 64x8 tiles.
+hipError_t launch_batch_persist(int storage, bool stream_stores, int per_xcd, char* d_base, const KParams* d_ptab,
+                                const StepOff* d_otab, const unsigned* d_tmap, const unsigned* d_steps, int nblocks,
+                                int nsteps, unsigned long long* bar, unsigned long long limit_ticks, int* grid_out,
+                                hipStream_t st);
 // Per listed slot (d_slots, nslots entries), from its field planes:
 // out[2 slot] = sum clamp(phi) f_l (liquid volume), out[2 slot + 1] = number
 // of non-finite phi, T, u values.

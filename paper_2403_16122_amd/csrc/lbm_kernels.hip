@@ -1656,6 +1656,40 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   step2w_tile<TX, TY, NT, PT, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
 }
 
+// nsteps single steps of many grids in one cooperative launch: the tiles of
+// the map tmap (as k_batch takes them, workgroup b the entries b,
+// b + gridDim.x, ...; gridDim.x a multiple of 8 keeps each on its XCD),
+// step s reading buffer set s & 1 of every slot, with the barrier of
+// k_persist between steps.
+template <class PT, bool STREAM>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_persist(
+    char* __restrict__ base, const KParams* __restrict__ ptab, const StepOff* __restrict__ otab,
+    const unsigned* __restrict__ tmap, const unsigned* __restrict__ steps, int nblocks, int nsteps, int per_xcd,
+    unsigned long long* bar, unsigned long long limit) {
+  constexpr int TX = 64, TY = 8;
+  XcdPlace pl{0u, 0ull, 0ull};
+  if (per_xcd && nsteps > 1 && !xcd_census(bar, limit, pl)) return;
+  for (int s = 0; s < nsteps; ++s) {
+    for (int v = blockIdx.x; v < nblocks; v += gridDim.x) {
+      const unsigned e = tmap[v];  // uniform over the workgroup
+      if (e != ~0u) {
+        const int slot = (int)(e >> 16), tile = (int)(e & 0xffffu);
+        KParams P = ptab[slot];
+        P.seed = steps[slot] + (unsigned)s;  // the grid's own step number
+        const StepIO io = io_of(base, otab[2 * slot + (s & 1)]);
+        const int ntx = (P.nx + TX - 1) / TX;
+        step_tile<TX, TY, false, PT, false, STREAM>(P, io, (tile % ntx) * TX, (tile / ntx) * TY);
+      }
+      __syncthreads();  // the next tile refills the LDS
+    }
+    if (s + 1 < nsteps) {
+      const bool go = per_xcd ? xcd_barrier(bar, (unsigned)(s + 1), pl, limit)
+                              : grid_barrier(bar, (unsigned long long)(s + 1) * gridDim.x, limit);
+      if (!go) return;
+    }
+  }
+}
+
 // Initial state (no time-stepping yet): u = 0, p = 0, liquid fraction 1,
 // each lattice at its equilibrium; computed in FP64 and rounded once.
 template <class PT>
@@ -2201,6 +2235,48 @@ int launch_batch(int storage, int tile_variant, bool fields_only, bool nt, char*
     return launch_batch_v<__bf16>(tile_variant, fields_only, nt, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s,
                                   st);
   return launch_batch_v<float>(tile_variant, fields_only, nt, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, s, st);
+}
+
+namespace {
+
+template <class PT>
+hipError_t launch_batch_persist_t(bool nt, int per_xcd, char* d_base, const KParams* d_ptab, const StepOff* d_otab,
+                                  const unsigned* d_tmap, const unsigned* d_steps, int nblocks, int nsteps,
+                                  unsigned long long* bar, unsigned long long limit, int* grid_out, hipStream_t st) {
+  const void* fn = nt ? (const void*)k_batch_persist<PT, true> : (const void*)k_batch_persist<PT, false>;
+  int dev = 0, ncu = 0, coop = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 512, 0);
+  if (e != hipSuccess) return e;
+  if (!coop) return hipErrorNotSupported;
+  const int cap = (per_cu * ncu) & ~7;  // co-resident workgroups, a multiple of 8
+  if (cap < 8) return hipErrorCooperativeLaunchTooLarge;
+  int grid = nblocks < cap ? nblocks : cap;
+  *grid_out = grid;
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, bar, (int)NPERSIST_WORDS);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  void* args[] = {&d_base, (void*)&d_ptab, (void*)&d_otab, (void*)&d_tmap, (void*)&d_steps, &nblocks, &nsteps,
+                  &per_xcd, &bar, &limit};
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(512), args, 0, st);
+}
+
+}  // namespace
+
+hipError_t launch_batch_persist(int storage, bool nt, int per_xcd, char* d_base, const KParams* d_ptab,
+                                const StepOff* d_otab, const unsigned* d_tmap, const unsigned* d_steps, int nblocks,
+                                int nsteps, unsigned long long* bar, unsigned long long limit_ticks, int* grid_out,
+                                hipStream_t st) {
+  if (nblocks <= 0 || nsteps <= 0) return hipErrorInvalidValue;
+  if (storage == STORE_FP16)
+    return launch_batch_persist_t<_Float16>(nt, per_xcd, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, nsteps, bar,
+                                            limit_ticks, grid_out, st);
+  if (storage == STORE_BF16)
+    return launch_batch_persist_t<__bf16>(nt, per_xcd, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, nsteps, bar,
+                                          limit_ticks, grid_out, st);
+  return launch_batch_persist_t<float>(nt, per_xcd, d_base, d_ptab, d_otab, d_tmap, d_steps, nblocks, nsteps, bar,
+                                       limit_ticks, grid_out, st);
 }
 
 int launch_batch_liquid(const char* d_base, const KParams* d_ptab, const StepOff* d_otab, const int* d_slots,

@@ -42,6 +42,7 @@ EXPORTED = [
 ]
 PERSIST_MAX_STEPS = 1000000  # LBM_PERSIST_MAX_STEPS
 PERSIST_BARRIERS = {"flat": 0, "per_xcd": 1}  # LBM_BARRIER_FLAT / LBM_BARRIER_PER_XCD
+INTERVAL_PERSIST = {"flat": 2, "per_xcd": 3}  # LBM_INTERVAL_PERSIST_FLAT / _PER_XCD
 DROP_STATUS = {0: "queued", 1: "running", 2: "frozen", 3: "limit", 4: "nonfinite"}
 
 
@@ -370,9 +371,13 @@ class Batch:
             self._h = None
 
     def configure(self, sample_every: int = 100, max_steps: int = 0, freeze_frac: float = 0.01,
-                  use_graph: bool = True):
-        self._check(self.L.lbm_batch_configure(self._h, int(sample_every), int(max_steps), float(freeze_frac),
-                                               int(bool(use_graph))), "lbm_batch_configure")
+                  use_graph: bool = True, persistent: Optional[str] = None):
+        """persistent None: one launch per step, replayed as a hipGraph unless
+        use_graph is False; "flat" or "per_xcd": each sampling interval in one
+        persistent cooperative launch with that grid barrier (64x8 tiles)."""
+        mode = INTERVAL_PERSIST[persistent] if persistent else int(bool(use_graph))
+        self._check(self.L.lbm_batch_configure(self._h, int(sample_every), int(max_steps), float(freeze_frac), mode),
+                    "lbm_batch_configure")
 
     def set_launch(self, tile: str = "64x4", xcd_group: int = 1):
         self._check(self.L.lbm_batch_set_launch(self._h, TILE_VARIANTS[tile], int(xcd_group)), "lbm_batch_set_launch")

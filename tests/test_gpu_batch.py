@@ -3,7 +3,7 @@
 * One launch over many grids computes exactly what the single-grid solver
   computes for each (same tile shape and storage: bitwise equal fields),
   whatever the tile layout, and the captured graph replays equal the same
-  steps launched one by one.
+  steps launched one by one, and a whole interval in one persistent launch.
 * Run until frozen, the queue (more droplets than slots, so slots are
   refilled) gives each droplet the freezing time, height, base radius and
   tip angle that the FP64 oracle and the shape checker give for it.
@@ -131,6 +131,42 @@ def oracle_freeze(oracle_mod, d, every, max_steps):
         if liq[-1] <= 0.01 * liq[0]:
             break
     return SH.freeze_time(steps, liq), steps[-1], o
+
+
+@pytest.mark.parametrize("barrier", ["flat", "per_xcd"])
+@pytest.mark.parametrize("storage", [0, 1])
+def test_persistent_intervals_equal_graph_replays(storage, barrier):
+    """Each sampling interval as one persistent cooperative launch (a grid
+    barrier between its steps) gives every droplet bitwise the state of the
+    replayed per-step launches, over a queue run until frozen with slots
+    refilled (so the tile map changes between intervals)."""
+    lbm = _lbm()
+    drops = small_sweep(5, seed=17, storage=storage, R_range=(6.0, 9.0), ste_range=(0.25, 0.3))
+    print(f"persistent intervals storage={storage} barrier={barrier}", flush=True)
+    g = make_batch(lbm, drops, slots=3)
+    p = make_batch(lbm, drops, slots=3)
+    g.configure(sample_every=40, max_steps=20000)
+    g.set_launch("64x8", 2)
+    p.configure(sample_every=40, max_steps=20000, persistent=barrier)
+    p.set_launch("64x8", 2)
+    with pytest.raises(lbm.LbmError):
+        p.set_launch("64x4", 2)  # persistent intervals run 64x8 tiles only
+    for rep in range(3):
+        print(f"interval {rep}", flush=True)
+        g.step(40)
+        p.step(40)
+        for i in range(3):
+            a, c = g.fields(i, ("phi", "T", "ux", "p")), p.fields(i, ("phi", "T", "ux", "p"))
+            for k in a:
+                assert np.array_equal(a[k], c[k]), (rep, i, k)
+    g.step(200000, until_frozen=True)
+    p.step(200000, until_frozen=True)
+    rg, rp = g.results(), p.results()
+    for a, c in zip(rg, rp):
+        print(f"graph {a}\npersistent {c}", flush=True)
+        assert a["status"] == c["status"] and a["steps"] == c["steps"]
+        for k in ("t_freeze", "liquid", "height", "base_radius", "tip_angle_deg"):
+            assert (a[k] == c[k]) or (math.isnan(a[k]) and math.isnan(c[k])), k
 
 
 def test_queue_until_frozen_against_oracle(oracle_mod):
