@@ -145,7 +145,8 @@ def run_sweep(lbm, W, n: int, storage: str, time_limit: float, chunk: int = 5000
     return drops, res, secs, node_steps, (tile, grp)
 
 
-def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float, reference: bool = True, chunk: int = 50000):
+def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float, reference: bool = True, chunk: int = 50000,
+                persistent: bool = True):
     """The batched sweep: n droplets (R ~ U(16,64), theta ~ U(60,150),
     Ste ~ U(0.05,0.3), gamma ~ U(0.85,1.1), 0-8 bubbles, grid 4R x 3R, FP16
     storage) all run until frozen as one queue; the same queue in FP32
@@ -164,20 +165,22 @@ def sweep_bench(lbm, W, n: int, n_plain: int, time_limit: float, reference: bool
         "node_steps": int(node_steps), "MLUPS": round(node_steps / secs / 1e6, 1), "tile": tile, "xcd_group": grp,
         "t_freeze_steps": [round(float(q), 1) for q in np.nanpercentile([r["t_freeze"] for r in res], [0, 50, 100])],
     }
-    # the same queue with every 200-step interval in one persistent launch
-    try:
-        _, resp, secsp, nsp, (tilep, grpp) = run_sweep(lbm, W, n, "fp16", time_limit, chunk, persistent="per_xcd")
-        same = all(a["steps"] == c["steps"] and (a["t_freeze"] == c["t_freeze"] or
-                                                 (np.isnan(a["t_freeze"]) and np.isnan(c["t_freeze"])))
-                   for a, c in zip(res, resp))
-        out["persistent_intervals"] = {
-            "barrier": "per_xcd", "seconds": round(secsp, 2),
-            "droplets_per_s": round(sum(r["status"] == "frozen" for r in resp) / secsp, 3),
-            "MLUPS": round(nsp / secsp / 1e6, 1), "tile": tilep, "xcd_group": grpp, "same_results": same,
-            "note": "each 200-step interval as one cooperative launch with a grid barrier between steps, "
-                    "against the replayed graph of per-step launches above"}
-    except lbm.LbmError as e:
-        out["persistent_intervals"] = {"error": str(e)}
+    if persistent:
+        # the same queue with every 200-step interval in one persistent launch
+        try:
+            _, resp, secsp, nsp, (tilep, grpp) = run_sweep(lbm, W, n, "fp16", time_limit, chunk,
+                                                           persistent="per_xcd")
+            same = all(a["steps"] == c["steps"] and (a["t_freeze"] == c["t_freeze"] or
+                                                     (np.isnan(a["t_freeze"]) and np.isnan(c["t_freeze"])))
+                       for a, c in zip(res, resp))
+            out["persistent_intervals"] = {
+                "barrier": "per_xcd", "seconds": round(secsp, 2),
+                "droplets_per_s": round(sum(r["status"] == "frozen" for r in resp) / secsp, 3),
+                "MLUPS": round(nsp / secsp / 1e6, 1), "tile": tilep, "xcd_group": grpp, "same_results": same,
+                "note": "each 200-step interval as one cooperative launch with a grid barrier between steps, "
+                        "against the replayed graph of per-step launches above"}
+        except lbm.LbmError as e:
+            out["persistent_intervals"] = {"error": str(e)}
     if not reference:
         return out
     _, res32, secs32, ns32, (tile32, grp32) = run_sweep(lbm, W, n, "fp32", time_limit)
@@ -493,6 +496,8 @@ def main():
                     help="headline workload only (no 128x64 and 512x256 rates)")
     ap.add_argument("--no-persistent", dest="persistent", action="store_false",
                     help="skip the persistent-launch comparison")
+    ap.add_argument("--no-sweep-persistent", dest="sweep_persistent", action="store_false",
+                    help="skip the sweep with one persistent launch per interval")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -639,7 +644,7 @@ def main():
         out["probe4096"] = probe
     if args.sweep_droplets > 0:
         out["sweep"] = sweep_bench(lbm, W, args.sweep_droplets, args.sweep_plain, args.sweep_time_limit,
-                                   args.sweep_reference, args.sweep_chunk)
+                                   args.sweep_reference, args.sweep_chunk, args.sweep_persistent)
         torch.cuda.empty_cache()
     if args.surrogate:
         out["surrogate"] = surrogate_bench(out.get("sweep"))
