@@ -193,7 +193,7 @@ def test_channel_flow_pressure_drift_and_profile(oracle_mod, storage):
     """Eq. (36) with tau = tau_f moves the pressure level uniformly by
     c_s^2 <F_0> / (2 tau_f (1 - w_0)) per step, F_0 = -w_0 u.F~ / c_s^2,
     while the velocity keeps the exact parabola (oracle: 2.4e-7 and 7.9e-6),
-    in each storage format."""
+    in each storage format (BF16's drift over a longer window)."""
     lbm = _lbm()
     nx, ny, g = 4, 32, 1e-5
     cs2, w0, tau = 1.0 / 3.0, 4.0 / 9.0, 0.5 + math.sqrt(3.0) / 4.0
@@ -220,14 +220,25 @@ def test_channel_flow_pressure_drift_and_profile(oracle_mod, storage):
     # 2.0e-3, 2.0e-3, 1.1e-2; BF16 0.40, 9.5e-3, 9.5e-3, 0.31.  The level sits
     # in the stored rest population f_0 ~ -5p/3 (f is stored as computed):
     # near p = 2.7e-4 a BF16 step there is 2^-19 = 1.9e-6, some 45 times the
-    # per-step drift of f_0, so the zero-mean stochastic rounding outweighs the drift over
-    # these 1000 steps and BF16 checks only the velocity
+    # per-step drift of f_0, and over these 1000 steps the BF16 level lags
+    # the closed form by a third.  The lag is a transient of the rounding,
+    # not a wrong rate: over longer windows from step 10000 it falls to 0.13,
+    # 0.11 and 0.060 (5000, 20000, 80000 steps; FP16 3.3e-2 to 8.4e-4), so
+    # BF16's drift is held over 80000 steps
     tol = {"fp32": (1e-2, 1e-4, 1e-3), "fp16": (0.15, 1e-2, 5e-2), "bf16": (None, 3e-2, None)}[storage]
     if tol[0] is not None:
         assert abs(drift - rate) < tol[0] * abs(rate)
     assert uerr < tol[1] and du < tol[1]
     if tol[2] is not None:
         assert dp < tol[2]
+    if storage == "bf16":
+        s.step(79000)
+        f = {k: v.astype(np.float64) for k, v in s.fields(["ux", "p", "rho"]).items()}
+        drift = (f["p"].mean() - p1.mean()) / 80000.0
+        rate = cs2 / (1.0 - w0) * (-w0 / cs2 * g * np.mean(f["rho"] * f["ux"])) / (2.0 * tau)
+        print(f"bf16 over 80000 steps: drift {drift:.6e} closed form {rate:.6e} rel {(drift - rate) / abs(rate):.2e}",
+              flush=True)
+        assert abs(drift - rate) < 0.1 * abs(rate)
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
