@@ -226,12 +226,6 @@ struct RefIO<true> {
   }
 };
 
-template <class PT, int LAT>
-__device__ __forceinline__ float pop_ld(const void* A, unsigned idx, const KParams& P) {
-  float v = PopIO<PT>::get(A, idx);
-  if constexpr (PopIO<PT>::kScaled) v *= P.sc_ld[LAT];
-  return v;
-}
 // rnd: the node's hash (sr_node) xor sr_pop(population); unused for FP32
 template <class PT, int LAT, bool NT = false>
 __device__ __forceinline__ void pop_st(void* B, unsigned idx, float v, const KParams& P, unsigned rnd) {
@@ -245,12 +239,6 @@ __device__ __forceinline__ void pop_lds_st(PT* dst, float v, const KParams& P, u
   if constexpr (PopIO<PT>::kScaled) v *= P.sc_st[LAT];
   *dst = cvt_store<PT>(v, rnd);
 }
-// Plane `j` of a population buffer.
-template <class PT>
-__device__ __forceinline__ void* pop_plane(void* B, unsigned j, unsigned pl) {
-  return (char*)B + (size_t)j * pl * sizeof(PT);
-}
-
 // Pull-stream the 9 populations of one lattice into node (x, y).  Sources
 // beyond a wall are replaced by the bounce-back of the node's own opposite
 // population (half-way rule); for h at the bottom wall by the
@@ -1173,8 +1161,9 @@ __global__ void k_zero_words(unsigned long long* w, int n) {
 // are bitwise those of two single steps.
 
 // Pull-stream one lattice into E cell (ex, ey) of grid row y from
-// first-step results in LDS (plane j at ep[j * ES], the storage type), with
-// pop_ld's conversion and pull9's wall rules.
+// first-step results in LDS (plane j at ep[j * ES], the storage type),
+// converted to FP32 with the lattice's load scale, and with pull9's wall
+// rules.
 template <int LAT, int EX, int ES, class PT>
 __device__ __forceinline__ void pull9_lds(const PT* __restrict__ ep, const KParams& P, int ex, int ey, int y,
                                           float q[9]) {

@@ -68,12 +68,13 @@ def test_persistent_steps_bitwise_equal_per_step_launches(storage, xcd, barrier)
 
 
 @pytest.mark.parametrize("barrier", BARRIERS)
-def test_persistent_grid_strides_over_more_tiles_than_resident_workgroups(barrier):
+@pytest.mark.parametrize("xcd", [0, 1, 2])
+def test_persistent_grid_strides_over_more_tiles_than_resident_workgroups(xcd, barrier):
     lbm = _lbm()
     p, phi0, T0 = droplet(1100, 530)
     ntiles = ((1100 + 63) // 64) * ((530 + 7) // 8)
-    print(f"persistent grid=1100x530 tiles={ntiles} barrier={barrier}", flush=True)
-    a, b = pair(lbm, p, phi0, T0, "fp32", 2)
+    print(f"persistent grid=1100x530 tiles={ntiles} xcd={xcd} barrier={barrier}", flush=True)
+    a, b = pair(lbm, p, phi0, T0, "fp32", xcd)
     a.step(12)
     wg = b.step_persistent(12, barrier)
     print(f"workgroups={wg}", flush=True)
