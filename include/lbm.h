@@ -123,15 +123,18 @@ int lbm_step(lbm_ctx* c, int32_t nsteps);
  * to arrive on each XCD (read from the XCC_ID hardware register) writes that
  * L2 back once for all of them.  Results are bitwise those of lbm_step in
  * both.  Kept to measure a persistent launch against one launch per step;
- * lbm_step is the faster path on MI355X.  nsteps in 0..LBM_PERSIST_MAX_STEPS
- * and barrier 0 or 1, else LBM_EINVAL.  *workgroups (optional) receives the
- * grid size.  Uses the context's reduction scratch for the barrier words.
- * Synchronises.  LBM_EDEVICE if the device has no cooperative launch, no
- * grid fits, or a barrier wait exceeded 2 s (then the state is invalid:
- * every wave still leaves the kernel). */
+ * lbm_step is the faster path on MI355X.  wait_limit_us bounds one barrier
+ * wait in microseconds of the device's wall clock (0: 2 s).  nsteps in
+ * 0..LBM_PERSIST_MAX_STEPS, barrier 0 or 1 and wait_limit_us >= 0, else
+ * LBM_EINVAL.  *workgroups (optional) receives the grid size.  Uses the
+ * context's reduction scratch for the barrier words.  Synchronises.
+ * LBM_EDEVICE if the device has no cooperative launch, no grid fits, or a
+ * barrier wait exceeded its bound: then no workgroup waits again, every wave
+ * leaves the kernel, and the context's state is invalid (load a checkpoint
+ * or destroy it). */
 #define LBM_PERSIST_MAX_STEPS 1000000
 enum { LBM_BARRIER_FLAT = 0, LBM_BARRIER_PER_XCD = 1 };
-int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t barrier, int32_t* workgroups);
+int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t barrier, int32_t wait_limit_us, int32_t* workgroups);
 
 /* Macroscopic fields at the current time level as the next step would
  * compute them: phi (Eq. (26)), T and f_l (Eq. (9)), u (Eq. (34)-(35), with

@@ -358,9 +358,10 @@ int lbm_step(lbm_ctx* c, int32_t nsteps) {
   return LBM_OK;
 }
 
-int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t barrier, int32_t* workgroups) {
+int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t barrier, int32_t wait_limit_us, int32_t* workgroups) {
   if (!c || nsteps < 0 || nsteps > LBM_PERSIST_MAX_STEPS) return LBM_EINVAL;
   if (barrier != LBM_BARRIER_FLAT && barrier != LBM_BARRIER_PER_XCD) return LBM_EINVAL;
+  if (wait_limit_us < 0) return LBM_EINVAL;
   if (nsteps == 0) return LBM_OK;
   int rate_khz = 0;
   LBM_CK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
@@ -368,8 +369,9 @@ int lbm_step_persistent(lbm_ctx* c, int32_t nsteps, int32_t barrier, int32_t* wo
     g_last_error = "device reports no wall-clock rate";
     return LBM_EDEVICE;
   }
-  // a barrier wait of 2 s is a failure: a step of the largest grid takes ~1 ms
-  const unsigned long long limit = 2000ull * (unsigned long long)rate_khz;
+  // by default a barrier wait of 2 s is a failure: a step of the largest grid takes ~1 ms
+  const unsigned long long us = wait_limit_us ? (unsigned long long)wait_limit_us : 2000000ull;
+  const unsigned long long limit = us * (unsigned long long)rate_khz / 1000ull;
   // the barrier words sit in the reduction scratch, which no step reads
   static_assert(lbmk::NPERSIST_WORDS <= (lbmk::RED_BLOCKS + 1) * lbmk::RED_NVAL, "barrier words");
   unsigned long long* bar = (unsigned long long*)c->S.part;

@@ -99,7 +99,7 @@ def load_library():
     L.lbm_workspace_bytes.argtypes = [C.POINTER(Params), C.POINTER(C.c_size_t)]
     L.lbm_init.argtypes = [C.POINTER(Params), dp, dp, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.lbm_step.argtypes = [vp, C.c_int32]
-    L.lbm_step_persistent.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    L.lbm_step_persistent.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     L.lbm_fields.argtypes = [vp, C.c_uint32, C.POINTER(dp)]
     L.lbm_fields_device.argtypes = [vp, C.c_uint32, C.POINTER(vp)]
     L.lbm_diag.argtypes = [vp, C.POINTER(Diag)]
@@ -232,13 +232,14 @@ class Solver:
     def step(self, n: int = 1):
         self._check(self.L.lbm_step(self._h, int(n)), "lbm_step")
 
-    def step_persistent(self, n: int = 1, barrier: str = "flat") -> int:
+    def step_persistent(self, n: int = 1, barrier: str = "flat", wait_limit_us: int = 0) -> int:
         """The same n steps in one persistent cooperative launch with a grid
         barrier between steps (lbm_step_persistent), barrier "flat" or
-        "per_xcd"; synchronises and returns the number of workgroups."""
+        "per_xcd", each barrier wait bounded by wait_limit_us (0: 2 s);
+        synchronises and returns the number of workgroups."""
         wg = C.c_int32(0)
-        self._check(self.L.lbm_step_persistent(self._h, int(n), PERSIST_BARRIERS[barrier], C.byref(wg)),
-                    "lbm_step_persistent")
+        self._check(self.L.lbm_step_persistent(self._h, int(n), PERSIST_BARRIERS[barrier], int(wait_limit_us),
+                                               C.byref(wg)), "lbm_step_persistent")
         return int(wg.value)
 
     def sync(self):

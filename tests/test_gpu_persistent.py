@@ -94,10 +94,34 @@ def test_persistent_mixes_with_per_step_launches_and_counts_steps():
     b.step_persistent(12)
     assert b.step_count == 30
     assert b.save() == a.save()
-    for bad in ((-1, 0), (lbm.PERSIST_MAX_STEPS + 1, 0), (5, 2), (5, -1)):
+    for bad in ((-1, 0, 0), (lbm.PERSIST_MAX_STEPS + 1, 0, 0), (5, 2, 0), (5, -1, 0), (5, 0, -1)):
         with pytest.raises(lbm.LbmError):
-            b._check(b.L.lbm_step_persistent(b._h, bad[0], bad[1], None), "lbm_step_persistent")
+            b._check(b.L.lbm_step_persistent(b._h, bad[0], bad[1], bad[2], None), "lbm_step_persistent")
     assert b.step_count == 30
+
+
+@pytest.mark.parametrize("barrier", BARRIERS)
+def test_a_barrier_wait_that_runs_out_is_reported_and_every_wave_leaves(barrier):
+    """The failure path, forced from the host: on 1100x530 (1206 tiles over
+    512 workgroups, so some step three tiles and the others two) the
+    two-tile workgroups wait several microseconds for the rest at the first
+    barrier, longer than a bound of 1 us.  The first wait to run out sets
+    the flag, every workgroup stops waiting and leaves, and the call
+    returns LBM_EDEVICE with the reason; the device then runs the same
+    steps normally."""
+    lbm = _lbm()
+    p, phi0, T0 = droplet(1100, 530)
+    print(f"forced barrier time-out barrier={barrier}", flush=True)
+    a, b = pair(lbm, p, phi0, T0, "fp32", 2)
+    with pytest.raises(lbm.LbmError) as err:
+        b.step_persistent(4, barrier, wait_limit_us=1)
+    assert err.value.code == lbm.LBM_EDEVICE and "timed out" in str(err.value)
+    assert b.step_count == 0  # the failed call does not count its steps
+    a.step(4)
+    c = lbm.Solver(dict(p, storage=lbm.STORAGE["fp32"]), phi0, T0)
+    c.set_launch("64x8", 2)
+    c.step_persistent(4, barrier)
+    assert c.save() == a.save()
 
 
 @pytest.mark.parametrize("barrier", BARRIERS)
