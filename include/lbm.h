@@ -274,8 +274,10 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
  * droplets' tiles, with the flat or per-XCD grid barrier of
  * lbm_step_persistent between steps (64x8 tiles only: the tile variant is
  * set to 2, and lbm_batch_set_launch and lbm_batch_autotune keep it there;
- * LBM_EDEVICE from lbm_batch_step if a barrier wait exceeds 2 s).  Results
- * are bitwise the same in every mode; anything else is LBM_EINVAL. */
+ * wait_limit_us bounds one barrier wait as in lbm_step_persistent, 0: 2 s;
+ * LBM_EDEVICE from lbm_batch_step if a wait runs out, and the resident
+ * droplets' states are then invalid).  Results are bitwise the same in
+ * every mode; anything else (or wait_limit_us < 0) is LBM_EINVAL. */
 enum {
   LBM_INTERVAL_LAUNCHES = 0,
   LBM_INTERVAL_GRAPH = 1,
@@ -283,7 +285,7 @@ enum {
   LBM_INTERVAL_PERSIST_PER_XCD = 3
 };
 int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, double freeze_frac,
-                        int32_t interval_launch);
+                        int32_t interval_launch, int32_t wait_limit_us);
 
 /* Tile shape (tile_variant 0..4 of lbm_set_launch, or the two-step variants
  * 9 and 10 when the sampling interval is a multiple of 4; LBM_EINVAL

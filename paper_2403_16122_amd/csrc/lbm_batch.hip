@@ -131,7 +131,8 @@ struct lbm_batch {
   bool use_graph;
   int persist;                   // -1: launches per step; 0 / 1: one persistent launch per interval
                                  // with the flat / per-XCD grid barrier
-  unsigned long long bar_limit;  // wall-clock ticks a barrier wait may take (2 s)
+  unsigned long long bar_limit;  // wall-clock ticks a barrier wait may take (default 2 s)
+  unsigned long long clock_khz;  // the device's wall-clock rate
   int persist_grid;              // workgroups of the last persistent launch
   hipGraphExec_t exec;
   bool graph_valid;
@@ -518,6 +519,7 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
   b->use_graph = true;
   b->persist = -1;
   b->bar_limit = 0;
+  b->clock_khz = 0;
   b->persist_grid = 0;
   b->h_bar = nullptr;
   b->drops.resize(n);
@@ -548,7 +550,8 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
     e = hipHostMalloc((void**)&b->h_bar, sizeof(unsigned long long) * lbmk::NPERSIST_WORDS, hipHostMallocDefault);
   int rate_khz = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, b->device);
-  b->bar_limit = 2000ull * (unsigned long long)(rate_khz > 0 ? rate_khz : 100000);
+  b->clock_khz = (unsigned long long)(rate_khz > 0 ? rate_khz : 100000);
+  b->bar_limit = 2000ull * b->clock_khz;
   if (e != hipSuccess) {
     rc = bdev_error(e, "lbm_batch_init");
     lbm_batch_destroy(b);
@@ -578,10 +581,11 @@ int lbm_batch_init(const lbm_params* p, int32_t n, const double* const* phi0, co
 }
 
 int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, double freeze_frac,
-                        int32_t interval_launch) {
+                        int32_t interval_launch, int32_t wait_limit_us) {
   if (!b || sample_every < 2 || (sample_every & 1) || max_steps < 0 || !(freeze_frac > 0.0 && freeze_frac < 1.0))
     return LBM_EINVAL;
   if (interval_launch < LBM_INTERVAL_LAUNCHES || interval_launch > LBM_INTERVAL_PERSIST_PER_XCD) return LBM_EINVAL;
+  if (wait_limit_us < 0) return LBM_EINVAL;
   const bool persist = interval_launch >= LBM_INTERVAL_PERSIST_FLAT;
   if (!persist && lbmk::is_two_step_any_storage(b->tile_variant) && sample_every % 4) {
     g_batch_error = "two steps per launch need a sampling interval that is a multiple of 4";
@@ -592,6 +596,7 @@ int lbm_batch_configure(lbm_batch* b, int32_t sample_every, int64_t max_steps, d
   b->freeze_frac = freeze_frac;
   b->use_graph = interval_launch == LBM_INTERVAL_GRAPH;
   b->persist = persist ? interval_launch - LBM_INTERVAL_PERSIST_FLAT : -1;
+  b->bar_limit = (wait_limit_us ? (unsigned long long)wait_limit_us : 2000000ull) * b->clock_khz / 1000ull;
   drop_graph(b);
   if (persist && b->tile_variant != kPersistVariant) {  // the persistent kernel runs 64x8 tiles
     b->tile_variant = kPersistVariant;

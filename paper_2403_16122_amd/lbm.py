@@ -123,7 +123,7 @@ def load_library():
     L.lbm_batch_workspace_bytes.argtypes = [C.POINTER(Params), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
     L.lbm_batch_init.argtypes = [C.POINTER(Params), C.c_int32, C.POINTER(dp), C.POINTER(dp), dp, C.c_int32, vp,
                                  C.c_size_t, vp, C.POINTER(vp)]
-    L.lbm_batch_configure.argtypes = [vp, C.c_int32, C.c_int64, C.c_double, C.c_int32]
+    L.lbm_batch_configure.argtypes = [vp, C.c_int32, C.c_int64, C.c_double, C.c_int32, C.c_int32]
     L.lbm_batch_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
     L.lbm_batch_set_store_mode.argtypes = [vp, C.c_int32]
     L.lbm_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
@@ -372,13 +372,14 @@ class Batch:
             self._h = None
 
     def configure(self, sample_every: int = 100, max_steps: int = 0, freeze_frac: float = 0.01,
-                  use_graph: bool = True, persistent: Optional[str] = None):
+                  use_graph: bool = True, persistent: Optional[str] = None, wait_limit_us: int = 0):
         """persistent None: one launch per step, replayed as a hipGraph unless
         use_graph is False; "flat" or "per_xcd": each sampling interval in one
-        persistent cooperative launch with that grid barrier (64x8 tiles)."""
+        persistent cooperative launch with that grid barrier (64x8 tiles),
+        each barrier wait bounded by wait_limit_us (0: 2 s)."""
         mode = INTERVAL_PERSIST[persistent] if persistent else int(bool(use_graph))
-        self._check(self.L.lbm_batch_configure(self._h, int(sample_every), int(max_steps), float(freeze_frac), mode),
-                    "lbm_batch_configure")
+        self._check(self.L.lbm_batch_configure(self._h, int(sample_every), int(max_steps), float(freeze_frac), mode,
+                                               int(wait_limit_us)), "lbm_batch_configure")
 
     def set_launch(self, tile: str = "64x4", xcd_group: int = 1):
         self._check(self.L.lbm_batch_set_launch(self._h, TILE_VARIANTS[tile], int(xcd_group)), "lbm_batch_set_launch")

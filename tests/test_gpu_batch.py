@@ -169,6 +169,36 @@ def test_persistent_intervals_equal_graph_replays(storage, barrier):
             assert (a[k] == c[k]) or (math.isnan(a[k]) and math.isnan(c[k])), k
 
 
+def test_a_persistent_interval_whose_barrier_wait_runs_out_is_reported():
+    """The failure path of the persistent interval, forced from the host:
+    40 droplets of R 40-64 give some 3000 tiles over 512 co-resident
+    workgroups, which step unequal numbers of tiles between barriers, so
+    the early ones wait longer than a bound of 1 us.  The wait runs out,
+    every workgroup leaves, and lbm_batch_step reports the time-out; a fresh
+    queue then runs persistent intervals bitwise equal to the graph."""
+    lbm = _lbm()
+    drops = small_sweep(40, seed=21, storage=1, R_range=(40.0, 64.0), ste_range=(0.05, 0.3))
+    print("forced batch barrier time-out", flush=True)
+    b = make_batch(lbm, drops)
+    b.configure(sample_every=20, persistent="per_xcd", wait_limit_us=1)
+    with pytest.raises(lbm.LbmError) as err:
+        b.step(20)
+    assert err.value.code == lbm.LBM_EDEVICE and "timed out" in str(err.value)
+    del b
+    g = make_batch(lbm, drops[:3])
+    p = make_batch(lbm, drops[:3])
+    g.configure(sample_every=20)
+    g.set_launch("64x8", 2)
+    p.configure(sample_every=20, persistent="flat")
+    p.set_launch("64x8", 2)
+    g.step(40)
+    p.step(40)
+    for i in range(3):
+        a, c = g.fields(i, ("phi", "T", "ux")), p.fields(i, ("phi", "T", "ux"))
+        for k in a:
+            assert np.array_equal(a[k], c[k]), (i, k)
+
+
 def test_queue_until_frozen_against_oracle(oracle_mod):
     lbm = _lbm()
     drops = small_sweep(3, seed=11, R_range=(6.0, 8.0), ste_range=(0.25, 0.3))
