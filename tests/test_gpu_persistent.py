@@ -69,6 +69,20 @@ def test_persistent_steps_bitwise_equal_per_step_launches(storage, xcd, barrier)
 
 @pytest.mark.parametrize("barrier", BARRIERS)
 @pytest.mark.parametrize("xcd", [0, 1, 2])
+def test_persistent_on_a_grid_narrower_than_a_tile(xcd, barrier):
+    """40 columns under 64-wide tiles: every tile is ragged, and tile order
+    2 deals padding workgroups that take no tile."""
+    lbm = _lbm()
+    p, phi0, T0 = droplet(40, 230)
+    print(f"persistent grid=40x230 xcd={xcd} barrier={barrier}", flush=True)
+    a, b = pair(lbm, p, phi0, T0, "fp16", xcd)
+    a.step(21)
+    b.step_persistent(21, barrier)
+    assert b.save() == a.save()
+
+
+@pytest.mark.parametrize("barrier", BARRIERS)
+@pytest.mark.parametrize("xcd", [0, 1, 2])
 def test_persistent_grid_strides_over_more_tiles_than_resident_workgroups(xcd, barrier):
     lbm = _lbm()
     p, phi0, T0 = droplet(1100, 530)
