@@ -426,7 +426,7 @@ def timed_run(lbm, W, name: str, storage: str, steps: int, warmup: int, args):
     return rec, secs, wall, (params, phi0, T0, meta)
 
 
-def persistent_vs_per_step(lbm, W, name: str, steps: int, warmup: int):
+def persistent_vs_per_step(lbm, W, name: str, steps: int, warmup: int, barriers=("flat", "per_xcd")):
     """`steps` FP32 steps of a workload as one launch per step and as one
     persistent cooperative launch (lbm_step_persistent) with each of its two
     grid barriers, all on 64x8 tiles in tile order 2 from the same state;
@@ -438,7 +438,7 @@ def persistent_vs_per_step(lbm, W, name: str, steps: int, warmup: int):
     params, phi0, T0, _ = W.workload(name, seed=0)
     N = params["nx"] * params["ny"]
     rec = {"workload": name, "steps": steps, "tile": "64x8", "xcd_remap": 2}
-    for mode in ("per_step", "persistent_flat", "persistent_per_xcd"):
+    for mode in ("per_step",) + tuple("persistent_" + b for b in barriers):
         s = lbm.Solver(params, phi0, T0)
         s.set_launch("64x8", 2)
         if mode == "per_step":
@@ -461,8 +461,7 @@ def persistent_vs_per_step(lbm, W, name: str, steps: int, warmup: int):
         del s
         torch.cuda.empty_cache()
     note(f"{name}: per-step launches {rec['per_step']['us_per_step']} us/step, persistent "
-         f"{rec['persistent_flat']['us_per_step']} (flat barrier) / "
-         f"{rec['persistent_per_xcd']['us_per_step']} (per-XCD barrier) us/step")
+         + ", ".join(f"{rec['persistent_' + b]['us_per_step']} ({b} barrier)" for b in barriers) + " us/step")
     return rec
 
 
@@ -498,6 +497,11 @@ def main():
                     help="skip the persistent-launch comparison")
     ap.add_argument("--no-sweep-persistent", dest="sweep_persistent", action="store_false",
                     help="skip the sweep with one persistent launch per interval")
+    ap.add_argument("--persistent-barrier", default="both", choices=("both", "flat", "per_xcd"),
+                    help="the grid barriers of the persistent-launch comparison")
+    ap.add_argument("--persistent-workloads", default="",
+                    help="comma-separated workloads of the persistent-launch comparison (default: the 128x64 and "
+                         "512x256 droplets, the headline workload and, with --probe-steps, the 4096x2048 grid)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -568,12 +572,17 @@ def main():
     if args.persistent:
         # one persistent launch over all steps against one launch per step
         per = {}
-        runs = [(n, max(args.steps, 200)) for n in ("sessile128", "sessile512", args.workload)]
-        if args.probe_steps > 0:
-            runs.append(("probe4096", args.probe_steps))
+        if args.persistent_workloads:
+            names = args.persistent_workloads.split(",")
+        else:
+            names = [n for n in ("sessile128", "sessile512") if n != args.workload] + [args.workload]
+            if args.probe_steps > 0 and args.workload != "probe4096":
+                names.append("probe4096")
+        runs = [(n, (args.probe_steps or 100) if n == "probe4096" else max(args.steps, 200)) for n in names]
+        barriers = ("flat", "per_xcd") if args.persistent_barrier == "both" else (args.persistent_barrier,)
         for name, n in runs:
             try:
-                per[name] = persistent_vs_per_step(lbm, W, name, n, 10)
+                per[name] = persistent_vs_per_step(lbm, W, name, n, 10, barriers)
             except lbm.LbmError as e:
                 per[name] = {"error": str(e)}
         out["persistent_launch"] = per
